@@ -1,0 +1,198 @@
+/*
+ * pcloth.h -- C ABI of the MI355X implicit cloth step (P-Cloth, Li et al.,
+ * arXiv 2008.00409).
+ *
+ * One backward-Euler step (paper Sec. 2.5, Eq. 1-3) assembles and solves
+ *     A dv = b,   A = M - h*df/dv - h^2*df/dx = M + h*(h+beta)*K,
+ *                 b = h*[ f(x + h*v) - beta*K*v ]          (rhs_mode 0, Eq. 3)
+ *                 b = h*[ f(x) - (h+beta)*K*v ]            (rhs_mode 1, linearised)
+ * then v += dv, x += h*v.  K = -df/dx is the positive semi-definite solver
+ * Jacobian of the per-triangle membrane (St. Venant-Kirchhoff, stress clamped
+ * to its PSD part in the geometric term) and per-hinge dihedral bending
+ * (Gauss-Newton) energies; f holds those forces plus gravity.  Pinned vertices
+ * are Dirichlet: A_ij = A_ji = 0 (j != i), A_ii = m_i I, b_i = 0.
+ *
+ * The matrix is rebuilt every step from the element list (Sec. 3.2.2: the
+ * block pattern is derived from the elements, duplicates removed, values
+ * summed per block), and solved by Jacobi-preconditioned CG (Sec. 3.1).
+ *
+ * Conventions (all entry points):
+ *  - Vectors (x, v, b, dv) are DEVICE arrays of nv*3 doubles, vertex-major
+ *    ((nv, 3) row-major), owned by the caller.  Mesh arrays in pc_mesh are HOST
+ *    arrays, copied by pc_create.
+ *  - All GPU work is enqueued on `stream` (a hipStream_t; NULL = default
+ *    stream).  Only calls that fill host outputs (pc_solve_info, status of
+ *    device-side checks) synchronise that stream.
+ *  - Errors are return codes; pc_last_error() gives a message.  No exception
+ *    crosses the ABI.  Calls on one context must not overlap; distinct
+ *    contexts are independent.
+ */
+#ifndef PCLOTH_H
+#define PCLOTH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pc_ctx pc_ctx;
+
+typedef enum {
+    PC_OK = 0,
+    PC_ERR_ARG = 1,            /* bad argument (null pointer, size, option) */
+    PC_ERR_MESH = 2,           /* bad index, degenerate rest triangle, edge in >2 triangles,
+                                  inconsistently oriented neighbours */
+    PC_ERR_HIP = 3,            /* a HIP runtime call failed */
+    PC_ERR_OOM = 4,            /* device allocation failed */
+    PC_ERR_NONFINITE = 5,      /* NaN/Inf in the right-hand side or the residual */
+    PC_ERR_NOT_CONVERGED = 6,  /* maxit reached; dv holds the last iterate */
+    PC_ERR_CAPACITY = 7        /* a vertex exceeds the per-row limits (64 incident
+                                  element corners, 64 distinct block columns) */
+} pc_status;
+
+/* Storage type of the matrix blocks.  Arithmetic is FP64 in every case. */
+typedef enum { PC_F64 = 0, PC_F32 = 1, PC_BF16 = 2 } pc_dtype;
+
+typedef struct {
+    double h;            /* time step (s) */
+    double mu, lambda;   /* membrane Lame constants (N/m) */
+    double k_bend;       /* bending stiffness (N m) */
+    double beta;         /* stiffness-proportional damping (s); 0 reproduces Eq. 3 */
+    double gravity[3];   /* m/s^2 */
+    int32_t rhs_mode;    /* 0: Eq. 3 as printed (lookahead force), 1: linearised */
+    int32_t reserved;
+} pc_params;
+
+typedef struct {
+    int32_t nv, nt;
+    const int32_t *tris;   /* host, nt*3, counter-clockwise w.r.t. the rest normal */
+    const double *rest;    /* host, nv*3 rest positions */
+    const double *mass;    /* host, nv, kg, > 0 */
+    const uint8_t *pinned; /* host, nv, 1 = Dirichlet vertex (may be NULL: none) */
+} pc_mesh;
+
+/* View of the assembled matrix, valid until the next cloth_assemble on the
+ * same context.  rowptr/colidx are the block-CSR pattern (columns ascending,
+ * diagonal included, pinned rows/columns kept as explicit zero blocks), device
+ * int32.  Values live in the context in a solver layout; cloth_export_blocks
+ * copies them out in block-CSR order. */
+typedef struct {
+    const int32_t *rowptr;   /* device, nrows+1 */
+    const int32_t *colidx;   /* device, nnzb */
+    pc_dtype dtype;
+    int32_t nrows, nnzb;
+} pc_bsr3;
+
+typedef struct {
+    double tol;            /* stop when ||b - A dv||_2 <= tol * ||b||_2, A with FP64 blocks */
+    double inner_rho;      /* each refinement sweep's CG stops once its residual has fallen by
+                              this factor (or reached tol); 0: default (BF16 blocks 1e-2,
+                              FP32/FP64 blocks: run each sweep to tol) */
+    int32_t maxit;         /* total CG iterations over all sweeps; default 20000 when <= 0 */
+    int32_t warm;          /* 0: zero start, 1: caller's dv as start */
+    int32_t check_every;   /* iterations between host convergence checks (0: auto) */
+    int32_t max_sweeps;    /* refinement sweeps; 0: default (BF16 40, otherwise 4) */
+} pc_solve_opts;
+
+typedef struct {
+    int32_t iters;             /* CG iterations performed */
+    int32_t sweeps;            /* outer refinement sweeps (1 without refinement) */
+    double rel_res_recursive;  /* ||r_k|| / ||b|| from the CG recurrence */
+    double rel_res_true;       /* ||b - A dv|| / ||b|| recomputed at exit with the FP64 blocks */
+    double bnorm;              /* ||b||_2 */
+    int32_t fallback;          /* 1 if the inner CG switched to the FP64 blocks after a
+                                  breakdown on the low-precision copy */
+    int32_t reserved;
+} pc_solve_info;
+
+/* Create a context: copies the mesh to the device, derives the rest shape
+ * data (per-triangle inverse rest frame and area, per-hinge coefficient and
+ * rest angle) and the hinge list (one per interior edge) on the GPU.
+ * Ownership: *out is owned by the caller and released by pc_destroy.
+ * Errors: PC_ERR_ARG (sizes, null), PC_ERR_MESH (index out of range,
+ * degenerate rest triangle, non-manifold or misoriented mesh), PC_ERR_OOM,
+ * PC_ERR_HIP.  Synchronises the default stream. */
+pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out);
+pc_status pc_destroy(pc_ctx *ctx);
+pc_status pc_set_params(pc_ctx *ctx, const pc_params *params);
+const char *pc_last_error(const pc_ctx *ctx);   /* NULL ctx: last pc_create error */
+
+/* Topology sizes: [nv, nt, nhinges, nnzb capacity]. */
+pc_status pc_sizes(const pc_ctx *ctx, int64_t out[4]);
+/* Copy the hinge list (nh*4 int32 a,b,c,d: edge a-b, wings c,d) and per-hinge
+ * (coefficient, rest angle) pairs to host memory (either pointer may be NULL). */
+pc_status pc_get_hinges(pc_ctx *ctx, int32_t *hinges_host, double *coef_host);
+
+/* Assemble A and b at state (x, v) (paper Sec. 3.2.2 and Eq. 3): rebuild the
+ * block pattern from the element list, sum the element blocks of each block
+ * (deterministic order: triangles then hinges, by index), eliminate pinned
+ * vertices, and form b and the Jacobi diagonal.  Block values are stored as
+ * `dtype`; diag_out (optional, device nv*3 doubles) receives diag(A).
+ * x, v: device nv*3 doubles.  b: device nv*3 doubles (output).
+ * A_out (optional, host struct) receives the pattern view.
+ * Asynchronous; capacity overflows detected on the device are reported by the
+ * next synchronising call (cloth_pcg_solve, cloth_step, pc_check). */
+pc_status cloth_assemble(pc_ctx *ctx, const double *x, const double *v, pc_dtype dtype,
+                         pc_bsr3 *A_out, double *b, double *diag_out, void *stream);
+
+/* Solve A dv = b by Jacobi-preconditioned CG on the most recently assembled
+ * matrix (Sec. 2.5: the linear system of Eq. 3, solved by PCG; Sec. 3.1).
+ * The off-diagonal blocks are applied in difference form,
+ *   (A y)_i = m_i y_i + D_i y_i + sum_{j != i} A_ij (y_j - y_i),
+ * with D_i = A_ii - m_i I + sum_{j != i} A_ij kept separately, so that rounding
+ * of the stored blocks does not disturb the mass term.  CG runs on the
+ * solver copy of the blocks (the assembled dtype); each sweep starts from the
+ * residual b - A dv computed with the FP64 copy, and sweeps repeat (iterative
+ * refinement) until that FP64 residual meets tol.  Dots, vectors and all
+ * accumulation are FP64 (the search direction is stored as FP32).
+ * dv: device nv*3 doubles, the start when opts->warm = 1, the solution on
+ * return (also when PC_ERR_NOT_CONVERGED).  info: host, optional.
+ * Synchronises the stream. */
+pc_status cloth_pcg_solve(pc_ctx *ctx, const double *b, double *dv, const pc_solve_opts *opts,
+                          pc_solve_info *info, void *stream);
+
+/* nsteps backward-Euler steps: assemble, solve, v += dv, x += h v (pinned
+ * vertices keep x, and v = 0).  x, v: device nv*3 doubles, updated in place.
+ * A step whose solve fails (not converged, non-finite) is not committed and
+ * the call returns that status.  infos: host array of nsteps, optional.
+ * The previous step's dv is used as the start when opts->warm = 1. */
+pc_status cloth_step(pc_ctx *ctx, double *x, double *v, int32_t nsteps, pc_dtype dtype,
+                     const pc_solve_opts *opts, pc_solve_info *infos, void *stream);
+
+/* y = A x with the assembled matrix (difference form, FP64 accumulation),
+ * using the FP64 blocks (solver_blocks = 0) or the solver copy in the
+ * assembled dtype (solver_blocks = 1).  x, y: device nv*3 doubles. */
+pc_status cloth_spmv(pc_ctx *ctx, const double *x, double *y, int32_t solver_blocks, void *stream);
+
+/* Copy the assembled blocks out in block-CSR order as FP64 (device nnzb*9,
+ * row-major 3x3), with the true diagonal blocks A_ii = m_i I + D_i -
+ * sum_{j != i} A_ij, and optionally the remainders D_i (device nv*9); from
+ * the FP64 copy (solver_blocks = 0) or the solver copy (solver_blocks = 1). */
+pc_status cloth_export_blocks(pc_ctx *ctx, double *vals_out, double *D_out, int32_t solver_blocks,
+                              void *stream);
+
+/* Block-CSR pattern of the last assembly.  Synchronises the stream, writes
+ * nnzb to *nnzb_out (host, optional) and copies rowptr (device nrows+1 int32)
+ * and colidx (device nnzb int32) into the caller's buffers when they are not
+ * NULL. */
+pc_status cloth_export_pattern(pc_ctx *ctx, int32_t *rowptr_out, int32_t *colidx_out, int64_t *nnzb_out,
+                               void *stream);
+
+/* Kernel timing with HIP events on the launch stream: with every > 0, one in
+ * `every` launches of each timed kernel is bracketed by an event pair (0 turns
+ * sampling off; any call resets the statistics).  pc_profile_read synchronises
+ * the device and writes, for each kind k in 0..7 (0 SpMV in CG, 1 CG vector
+ * update, 2 CG direction update, 3 row assembly, 4 row pattern, 5 whole
+ * assembly), out[4k..4k+3] = {samples, mean ms, min ms, max ms} (host, 32). */
+pc_status pc_profile(pc_ctx *ctx, int32_t every);
+pc_status pc_profile_read(pc_ctx *ctx, double *out);
+
+/* Synchronise the stream and report device-side errors of earlier calls. */
+pc_status pc_check(pc_ctx *ctx, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCLOTH_H */

@@ -1,0 +1,271 @@
+"""ctypes binding of libpcloth.so: argument marshalling only.
+
+Every computation runs in the HIP library.  If the library is missing the
+import fails; there is no fallback path.  Device buffers are torch tensors on
+``cuda:0`` (float64, shape (nv, 3), contiguous); the current torch stream is
+passed to every call.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcloth.so")
+
+PC_OK, PC_ERR_ARG, PC_ERR_MESH, PC_ERR_HIP, PC_ERR_OOM, PC_ERR_NONFINITE, PC_ERR_NOT_CONVERGED, \
+    PC_ERR_CAPACITY = range(8)
+STATUS_NAMES = {0: "PC_OK", 1: "PC_ERR_ARG", 2: "PC_ERR_MESH", 3: "PC_ERR_HIP", 4: "PC_ERR_OOM",
+                5: "PC_ERR_NONFINITE", 6: "PC_ERR_NOT_CONVERGED", 7: "PC_ERR_CAPACITY"}
+PC_F64, PC_F32, PC_BF16 = 0, 1, 2
+DTYPES = {"f64": PC_F64, "f32": PC_F32, "bf16": PC_BF16}
+
+# Names of every entry point declared in include/pcloth.h.
+ABI_SYMBOLS = ["pc_create", "pc_destroy", "pc_set_params", "pc_last_error", "pc_sizes", "pc_get_hinges",
+               "cloth_assemble", "cloth_pcg_solve", "cloth_step", "cloth_spmv", "cloth_export_blocks",
+               "cloth_export_pattern", "pc_check", "pc_profile", "pc_profile_read"]
+PROFILE_KINDS = ["spmv", "cg_update", "cg_dir", "row_assemble", "row_pattern", "assemble_all", "k6", "k7"]
+
+
+class PcParams(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("mu", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("k_bend", ctypes.c_double), ("beta", ctypes.c_double), ("gravity", ctypes.c_double * 3),
+                ("rhs_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PcMesh(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int32), ("nt", ctypes.c_int32), ("tris", ctypes.POINTER(ctypes.c_int32)),
+                ("rest", ctypes.POINTER(ctypes.c_double)), ("mass", ctypes.POINTER(ctypes.c_double)),
+                ("pinned", ctypes.POINTER(ctypes.c_uint8))]
+
+
+class PcBsr3(ctypes.Structure):
+    _fields_ = [("rowptr", ctypes.c_void_p), ("colidx", ctypes.c_void_p), ("dtype", ctypes.c_int),
+                ("nrows", ctypes.c_int32), ("nnzb", ctypes.c_int32)]
+
+
+class PcSolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("inner_rho", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("warm", ctypes.c_int32), ("check_every", ctypes.c_int32), ("max_sweeps", ctypes.c_int32)]
+
+
+def solve_opts(tol=1e-6, maxit=20000, warm=False, check_every=0, inner_rho=0.0, max_sweeps=0):
+    return PcSolveOpts(float(tol), float(inner_rho), int(maxit), int(bool(warm)), int(check_every),
+                       int(max_sweeps))
+
+
+class PcSolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("rel_res_recursive", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("bnorm", ctypes.c_double), ("fallback", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "sweeps": self.sweeps, "rel_res_recursive": self.rel_res_recursive,
+                "rel_res_true": self.rel_res_true, "bnorm": self.bnorm, "fallback": self.fallback}
+
+
+_lib = None
+
+
+def lib():
+    """Load libpcloth.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2008_00409_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.pc_create.argtypes = [ctypes.POINTER(PcMesh), ctypes.POINTER(PcParams), ctypes.POINTER(vp)]
+        L.pc_destroy.argtypes = [vp]
+        L.pc_set_params.argtypes = [vp, ctypes.POINTER(PcParams)]
+        L.pc_last_error.argtypes = [vp]
+        L.pc_last_error.restype = ctypes.c_char_p
+        L.pc_sizes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.pc_get_hinges.argtypes = [vp, vp, vp]
+        L.cloth_assemble.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(PcBsr3), vp, vp, vp]
+        L.cloth_pcg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(PcSolveOpts), ctypes.POINTER(PcSolveInfo), vp]
+        L.cloth_step.argtypes = [vp, vp, vp, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(PcSolveOpts),
+                                 ctypes.POINTER(PcSolveInfo), vp]
+        L.cloth_spmv.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+        L.cloth_export_blocks.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+        L.pc_check.argtypes = [vp, vp]
+        L.cloth_export_pattern.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
+        L.pc_profile.argtypes = [vp, ctypes.c_int32]
+        L.pc_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        for name in ABI_SYMBOLS:
+            if name not in ("pc_last_error",):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class PclothError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev3(t, nv, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+            and tuple(t.shape) == (nv, 3)):
+        raise ValueError(f"{name} must be a contiguous cuda float64 tensor of shape ({nv}, 3)")
+    return _ptr(t)
+
+
+def make_params(h, mu=1000.0, lam=500.0, k_bend=1e-5, beta=0.0, gravity=(0.0, 0.0, -9.81), rhs_mode=0):
+    p = PcParams()
+    p.h, p.mu, p.lambda_, p.k_bend, p.beta = float(h), float(mu), float(lam), float(k_bend), float(beta)
+    for a in range(3):
+        p.gravity[a] = float(gravity[a])
+    p.rhs_mode = int(rhs_mode)
+    return p
+
+
+class Context:
+    """One cloth on the GPU: wraps pc_create / pc_destroy and the step calls."""
+
+    def __init__(self, rest, tris, mass, pinned, params: PcParams):
+        L = lib()
+        self._keep = [np.ascontiguousarray(rest, dtype=np.float64),
+                      np.ascontiguousarray(tris, dtype=np.int32),
+                      np.ascontiguousarray(mass, dtype=np.float64),
+                      np.ascontiguousarray(pinned, dtype=np.uint8)]
+        rest_, tris_, mass_, pin_ = self._keep
+        m = PcMesh()
+        m.nv, m.nt = rest_.shape[0], tris_.shape[0]
+        m.tris = tris_.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        m.rest = rest_.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        m.mass = mass_.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        m.pinned = pin_.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        self.params = params
+        h = ctypes.c_void_p()
+        st = L.pc_create(ctypes.byref(m), ctypes.byref(params), ctypes.byref(h))
+        if st != PC_OK:
+            raise PclothError(st, L.pc_last_error(None).decode())
+        self.h = h
+        self.nv, self.nt = int(m.nv), int(m.nt)
+        sz = (ctypes.c_int64 * 4)()
+        L.pc_sizes(self.h, sz)
+        self.nh, self.cap = int(sz[2]), int(sz[3])
+
+    @classmethod
+    def from_cloth(cls, c, **kw):
+        return cls(c.rest, c.tris, c.mass, c.pinned, make_params(c.h, **kw))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != PC_OK:
+            raise PclothError(st, lib().pc_last_error(self.h).decode())
+
+    # -- entry points -------------------------------------------------------
+    def set_params(self, params: PcParams):
+        self._check(lib().pc_set_params(self.h, ctypes.byref(params)))
+        self.params = params
+
+    def hinges(self):
+        H = np.zeros((self.nh, 4), dtype=np.int32)
+        C = np.zeros((self.nh, 2), dtype=np.float64)
+        self._check(lib().pc_get_hinges(self.h, H.ctypes.data_as(ctypes.c_void_p),
+                                        C.ctypes.data_as(ctypes.c_void_p)))
+        return H, C
+
+    def cloth_assemble(self, x, v, dtype="f32", b=None, diag=None):
+        import torch
+        dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        if b is None:
+            b = torch.empty((self.nv, 3), dtype=torch.float64, device=x.device)
+        A = PcBsr3()
+        self._check(lib().cloth_assemble(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"), dt,
+                                         ctypes.byref(A), _dev3(b, self.nv, "b"),
+                                         _dev3(diag, self.nv, "diag") if diag is not None else None, _stream()))
+        self._A = A
+        return b
+
+    def pattern(self):
+        """Block-CSR pattern of the last assembly as torch int32 tensors (rowptr, colidx)."""
+        import torch
+        n = ctypes.c_int64()
+        self._check(lib().cloth_export_pattern(self.h, None, None, ctypes.byref(n), _stream()))
+        rowptr = torch.empty(self.nv + 1, dtype=torch.int32, device="cuda")
+        colidx = torch.empty(max(1, n.value), dtype=torch.int32, device="cuda")
+        self._check(lib().cloth_export_pattern(self.h, _ptr(rowptr), _ptr(colidx), None, _stream()))
+        return rowptr, colidx[:n.value]
+
+    def cloth_pcg_solve(self, b, dv=None, tol=1e-6, maxit=20000, warm=False, check_every=0, raise_on_error=True,
+                        inner_rho=0.0, max_sweeps=0):
+        import torch
+        if dv is None:
+            dv = torch.zeros((self.nv, 3), dtype=torch.float64, device=b.device)
+        o = solve_opts(tol, maxit, warm, check_every, inner_rho, max_sweeps)
+        info = PcSolveInfo()
+        st = lib().cloth_pcg_solve(self.h, _dev3(b, self.nv, "b"), _dev3(dv, self.nv, "dv"), ctypes.byref(o),
+                                   ctypes.byref(info), _stream())
+        if raise_on_error:
+            self._check(st)
+        d = info.as_dict()
+        d["status"] = st
+        return dv, d
+
+    def cloth_spmv(self, x, y=None, solver_blocks=False):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        self._check(lib().cloth_spmv(self.h, _dev3(x, self.nv, "x"), _dev3(y, self.nv, "y"), int(solver_blocks),
+                                     _stream()))
+        return y
+
+    def cloth_export_blocks(self, with_D=True, solver_blocks=False):
+        import torch
+        rowptr, colidx = self.pattern()
+        vals = torch.empty((colidx.numel(), 3, 3), dtype=torch.float64, device="cuda")
+        D = torch.empty((self.nv, 3, 3), dtype=torch.float64, device="cuda") if with_D else None
+        self._check(lib().cloth_export_blocks(self.h, _ptr(vals), _ptr(D) if D is not None else None,
+                                              int(solver_blocks), _stream()))
+        return rowptr, colidx, vals, D
+
+    def cloth_step(self, x, v, nsteps=1, dtype="f32", tol=1e-6, maxit=20000, warm=False, check_every=0,
+                   inner_rho=0.0, max_sweeps=0):
+        dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        o = solve_opts(tol, maxit, warm, check_every, inner_rho, max_sweeps)
+        infos = (PcSolveInfo * max(1, nsteps))()
+        st = lib().cloth_step(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"), int(nsteps), dt,
+                              ctypes.byref(o), infos, _stream())
+        self._check(st)
+        return [infos[k].as_dict() for k in range(nsteps)]
+
+    def profile(self, every):
+        self._check(lib().pc_profile(self.h, int(every)))
+
+    def profile_read(self):
+        out = (ctypes.c_double * 32)()
+        self._check(lib().pc_profile_read(self.h, out))
+        return {PROFILE_KINDS[k]: {"samples": int(out[4 * k]), "mean_ms": out[4 * k + 1], "min_ms": out[4 * k + 2],
+                                   "max_ms": out[4 * k + 3]} for k in range(8) if out[4 * k] > 0}
+
+    def check(self):
+        self._check(lib().pc_check(self.h, _stream()))

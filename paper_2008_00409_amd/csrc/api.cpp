@@ -1,0 +1,380 @@
+// C ABI entry points: argument checks, context lifetime, orchestration of
+// the assembly / solve / update launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pc_ctx.h"
+
+using namespace pc;
+
+struct pc_ctx {
+    Ctx c;
+};
+
+static thread_local std::string g_create_err;
+
+namespace pc {
+
+pc_status dev_alloc(Ctx *ctx, void **p, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        ctx->err = "hipMalloc(" + std::to_string(bytes) + " bytes): " + hipGetErrorString(e);
+        return e == hipErrorOutOfMemory ? PC_ERR_OOM : PC_ERR_HIP;
+    }
+    return PC_OK;
+}
+
+}  // namespace pc
+
+static DevParams make_params(const pc_params &u) {
+    DevParams d;
+    d.h = u.h;
+    d.mu = u.mu;
+    d.lam = u.lambda;
+    d.kb = u.k_bend;
+    d.beta = u.beta;
+    d.g[0] = u.gravity[0];
+    d.g[1] = u.gravity[1];
+    d.g[2] = u.gravity[2];
+    d.c = u.h * (u.h + u.beta);
+    d.s_look = u.rhs_mode == 0 ? 1.0 : 0.0;
+    d.kv_coef = u.rhs_mode == 0 ? u.beta : u.h + u.beta;
+    return d;
+}
+
+static bool params_ok(const pc_params *p, std::string &err) {
+    if (!p) { err = "params is NULL"; return false; }
+    if (!(p->h > 0.0) || !std::isfinite(p->h)) { err = "h must be > 0"; return false; }
+    if (!(p->mu >= 0.0) || !(p->lambda >= 0.0) || !(p->k_bend >= 0.0) || !(p->beta >= 0.0)) {
+        err = "material constants must be >= 0";
+        return false;
+    }
+    if (p->rhs_mode != 0 && p->rhs_mode != 1) { err = "rhs_mode must be 0 or 1"; return false; }
+    return true;
+}
+
+static void free_all(Ctx *c) {
+    void *ptrs[] = {c->tri, c->Bm, c->A0, c->hinge, c->hcoef, c->htbar, c->mass, c->pinned, c->status,
+                    c->inc_cnt, c->inc_ptr, c->inc, c->rowlen, c->rowptr, c->colidx, c->jcol, c->lane_row,
+                    c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->x, c->r, c->q, c->tmp, c->bbuf,
+                    c->p, c->partials, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->status_host) (void)hipHostFree(c->status_host);
+}
+
+extern "C" {
+
+const char *pc_last_error(const pc_ctx *ctx) { return ctx ? ctx->c.err.c_str() : g_create_err.c_str(); }
+
+pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) {
+    g_create_err.clear();
+    if (!out) { g_create_err = "out is NULL"; return PC_ERR_ARG; }
+    *out = nullptr;
+    if (!mesh || !mesh->tris || !mesh->rest || !mesh->mass) { g_create_err = "mesh arrays are NULL"; return PC_ERR_ARG; }
+    if (mesh->nv <= 0 || mesh->nt <= 0) { g_create_err = "nv and nt must be > 0"; return PC_ERR_ARG; }
+    if (mesh->nt >= (1 << 29) - 1 || mesh->nv >= (1 << 30)) { g_create_err = "mesh too large"; return PC_ERR_ARG; }
+    if (!params_ok(params, g_create_err)) return PC_ERR_ARG;
+    const int nv = mesh->nv, nt = mesh->nt;
+    for (int i = 0; i < nv; ++i)
+        if (!(mesh->mass[i] > 0.0) || !std::isfinite(mesh->mass[i])) {
+            g_create_err = "mass must be finite and > 0 (vertex " + std::to_string(i) + ")";
+            return PC_ERR_ARG;
+        }
+    for (int64_t k = 0; k < 3 * (int64_t)nt; ++k)
+        if (mesh->tris[k] < 0 || mesh->tris[k] >= nv) {
+            g_create_err = "triangle index out of range";
+            return PC_ERR_MESH;
+        }
+    pc_ctx *h = new (std::nothrow) pc_ctx();
+    if (!h) { g_create_err = "host allocation failed"; return PC_ERR_OOM; }
+    Ctx *ctx = &h->c;
+    ctx->nv = nv;
+    ctx->nt = nt;
+    ctx->nslices = (nv + WAVE - 1) / WAVE;
+    ctx->user_prm = *params;
+    ctx->prm = make_params(*params);
+    hipStream_t s = nullptr;
+    pc_status st = PC_OK;
+    auto fail = [&](pc_status code) {
+        g_create_err = ctx->err;
+        free_all(ctx);
+        delete h;
+        return code;
+    };
+#define ALLOC(ptr, bytes) \
+    if ((st = dev_alloc(ctx, (void **)&(ptr), (bytes)))) return fail(st)
+    // static data
+    ALLOC(ctx->tri, sizeof(int) * 3 * (size_t)nt);
+    ALLOC(ctx->Bm, sizeof(double) * 4 * (size_t)nt);
+    ALLOC(ctx->A0, sizeof(double) * (size_t)nt);
+    ALLOC(ctx->mass, sizeof(double) * (size_t)nv);
+    ALLOC(ctx->pinned, (size_t)nv);
+    ALLOC(ctx->status, sizeof(int));
+    ALLOC(ctx->inc_cnt, sizeof(int) * (size_t)nv);
+    ALLOC(ctx->inc_ptr, sizeof(int) * (size_t)(nv + 1));
+    ALLOC(ctx->tmp, sizeof(double) * 3 * (size_t)nv);
+    {
+        std::vector<int> soa(3 * (size_t)nt);
+        for (int t = 0; t < nt; ++t)
+            for (int k = 0; k < 3; ++k) soa[(size_t)k * nt + t] = mesh->tris[3 * (size_t)t + k];
+        if (hipMemcpy(ctx->tri, soa.data(), sizeof(int) * soa.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(ctx->tmp, mesh->rest, sizeof(double) * 3 * (size_t)nv, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(ctx->mass, mesh->mass, sizeof(double) * (size_t)nv, hipMemcpyHostToDevice) != hipSuccess) {
+            ctx->err = "upload failed";
+            return fail(PC_ERR_HIP);
+        }
+        std::vector<uint8_t> pin((size_t)nv, 0);
+        if (mesh->pinned)
+            for (int i = 0; i < nv; ++i) pin[i] = mesh->pinned[i] ? 1 : 0;
+        if (hipMemcpy(ctx->pinned, pin.data(), (size_t)nv, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(ctx->status, 0, sizeof(int)) != hipSuccess ||
+            hipMemset(ctx->inc_cnt, 0, sizeof(int) * (size_t)nv) != hipSuccess) {
+            ctx->err = "upload failed";
+            return fail(PC_ERR_HIP);
+        }
+    }
+    if ((st = topo_build(ctx, mesh, s))) return fail(st);
+    const int nh = ctx->nh;
+    ctx->ninc = 3 * (int64_t)nt + 4 * (int64_t)nh;
+    // block capacity: diagonal + both directions of every triangle edge (6
+    // per triangle, duplicates included) + both wing pairs of every hinge
+    ctx->cap = (int64_t)nv + 6 * (int64_t)nt + 2 * (int64_t)nh;
+    if (ctx->cap >= (int64_t)1 << 31) {
+        ctx->err = "block capacity exceeds int32 indexing";
+        return fail(PC_ERR_ARG);
+    }
+    const size_t nsl = (size_t)ctx->nslices;
+    ALLOC(ctx->inc, sizeof(int) * (size_t)ctx->ninc);
+    ALLOC(ctx->rowlen, sizeof(int) * (size_t)nv);
+    ALLOC(ctx->rowptr, sizeof(int) * (size_t)(nv + 1));
+    ALLOC(ctx->colidx, sizeof(int) * (size_t)ctx->cap);
+    ALLOC(ctx->jcol, sizeof(int) * (size_t)ctx->cap);
+    ALLOC(ctx->lane_row, sizeof(int) * nsl * WAVE);
+    ALLOC(ctx->row_lane, sizeof(int) * (size_t)nv);
+    ALLOC(ctx->slot_cnt, nsl * WAVE);
+    ALLOC(ctx->diag, sizeof(double) * 3 * (size_t)nv);
+    ALLOC(ctx->dinv, sizeof(float) * 3 * (size_t)nv);
+    ALLOC(ctx->x, sizeof(double) * 3 * (size_t)nv);
+    ALLOC(ctx->r, sizeof(double) * 3 * (size_t)nv);
+    ALLOC(ctx->q, sizeof(double) * 3 * (size_t)nv);
+    ALLOC(ctx->bbuf, sizeof(double) * 3 * (size_t)nv);
+    ALLOC(ctx->p, sizeof(float4) * (size_t)nv);
+    {
+        const size_t nblk = (size_t)(nv / 256 + 16) + nsl / 4 + 16;
+        ALLOC(ctx->partials, sizeof(double) * 4 * nblk);
+    }
+    ALLOC(ctx->res2, sizeof(double) * 2);
+    ALLOC(ctx->counter, sizeof(unsigned) * 4);
+    ALLOC(ctx->st, sizeof(PcgState));
+#undef ALLOC
+    if (hipHostMalloc((void **)&ctx->st_host, sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->status_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        ctx->err = "pinned host allocation failed";
+        return fail(PC_ERR_OOM);
+    }
+    if (hipMemset(ctx->counter, 0, sizeof(unsigned) * 4) != hipSuccess ||
+        hipMemset(ctx->tmp, 0, sizeof(double) * 3 * (size_t)nv) != hipSuccess ||
+        hipMemset(ctx->p, 0, sizeof(float4) * (size_t)nv) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        ctx->err = "initialisation failed";
+        return fail(PC_ERR_HIP);
+    }
+    *out = h;
+    return PC_OK;
+}
+
+pc_status pc_profile(pc_ctx *h, int32_t every) {
+    if (!h || every < 0) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    (void)hipDeviceSynchronize();
+    ctx->prof.harvest();
+    ctx->prof.init(512);
+    ctx->prof.reset();
+    ctx->prof.every = every;
+    return PC_OK;
+}
+
+pc_status pc_profile_read(pc_ctx *h, double *out) {
+    if (!h || !out) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    PC_HIP(hipDeviceSynchronize());
+    ctx->prof.harvest();
+    for (int k = 0; k < PK_NKINDS; ++k) {
+        const long long n = ctx->prof.count[k];
+        out[4 * k] = (double)n;
+        out[4 * k + 1] = n ? ctx->prof.sum_ms[k] / n : 0.0;
+        out[4 * k + 2] = ctx->prof.min_ms[k];
+        out[4 * k + 3] = ctx->prof.max_ms[k];
+    }
+    return PC_OK;
+}
+
+pc_status pc_destroy(pc_ctx *h) {
+    if (!h) return PC_ERR_ARG;
+    (void)hipDeviceSynchronize();
+    h->c.prof.destroy();
+    free_all(&h->c);
+    delete h;
+    return PC_OK;
+}
+
+pc_status pc_set_params(pc_ctx *h, const pc_params *params) {
+    if (!h) return PC_ERR_ARG;
+    if (!params_ok(params, h->c.err)) return PC_ERR_ARG;
+    h->c.user_prm = *params;
+    h->c.prm = make_params(*params);
+    return PC_OK;
+}
+
+pc_status pc_sizes(const pc_ctx *h, int64_t out[4]) {
+    if (!h || !out) return PC_ERR_ARG;
+    out[0] = h->c.nv;
+    out[1] = h->c.nt;
+    out[2] = h->c.nh;
+    out[3] = h->c.cap;
+    return PC_OK;
+}
+
+pc_status pc_get_hinges(pc_ctx *h, int32_t *hinges_host, double *coef_host) {
+    if (!h) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    const int nh = ctx->nh;
+    if (nh == 0) return PC_OK;
+    if (hinges_host) {
+        std::vector<int> soa(4 * (size_t)nh);
+        PC_HIP(hipMemcpy(soa.data(), ctx->hinge, sizeof(int) * soa.size(), hipMemcpyDeviceToHost));
+        for (int e = 0; e < nh; ++e)
+            for (int k = 0; k < 4; ++k) hinges_host[4 * (size_t)e + k] = soa[(size_t)k * nh + e];
+    }
+    if (coef_host) {
+        std::vector<double> c(nh), t(nh);
+        PC_HIP(hipMemcpy(c.data(), ctx->hcoef, sizeof(double) * nh, hipMemcpyDeviceToHost));
+        PC_HIP(hipMemcpy(t.data(), ctx->htbar, sizeof(double) * nh, hipMemcpyDeviceToHost));
+        for (int e = 0; e < nh; ++e) {
+            coef_host[2 * (size_t)e] = c[e];
+            coef_host[2 * (size_t)e + 1] = t[e];
+        }
+    }
+    return PC_OK;
+}
+
+pc_status cloth_assemble(pc_ctx *h, const double *x, const double *v, pc_dtype dtype, pc_bsr3 *A_out, double *b,
+                         double *diag_out, void *stream) {
+    if (!h) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (!x || !v || !b) { ctx->err = "cloth_assemble: x, v and b must be device pointers"; return PC_ERR_ARG; }
+    if (dtype != PC_F64 && dtype != PC_F32 && dtype != PC_BF16) { ctx->err = "bad dtype"; return PC_ERR_ARG; }
+    pc_status st = assemble_run(ctx, x, v, dtype, b, diag_out, (hipStream_t)stream);
+    if (st) return st;
+    if (A_out) {
+        A_out->rowptr = ctx->rowptr;
+        A_out->colidx = ctx->colidx;
+        A_out->dtype = dtype;
+        A_out->nrows = ctx->nv;
+        A_out->nnzb = -1;  // known after synchronisation: rowptr[nrows]
+    }
+    return PC_OK;
+}
+
+pc_status pc_check(pc_ctx *h, void *stream) {
+    if (!h) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    int bits = 0;
+    pc_status st = read_status(ctx, (hipStream_t)stream, &bits);
+    if (st) return st;
+    if (bits & (ST_INC_OVERFLOW | ST_COL_OVERFLOW | ST_BUCKET_OVERFLOW)) {
+        ctx->err = "a vertex exceeds the per-row limits (64 incident corners / 64 block columns)";
+        return PC_ERR_CAPACITY;
+    }
+    if (bits & ST_NONFINITE) {
+        ctx->err = "non-finite right-hand side";
+        PC_HIP(hipMemsetAsync(ctx->status, 0, sizeof(int), (hipStream_t)stream));
+        return PC_ERR_NONFINITE;
+    }
+    if (bits) {
+        ctx->err = "device check bits " + std::to_string(bits);
+        return PC_ERR_MESH;
+    }
+    return PC_OK;
+}
+
+pc_status cloth_pcg_solve(pc_ctx *h, const double *b, double *dv, const pc_solve_opts *opts, pc_solve_info *info,
+                          void *stream) {
+    if (!h) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (!b || !dv) { ctx->err = "cloth_pcg_solve: b and dv must be device pointers"; return PC_ERR_ARG; }
+    if (opts && (!(opts->tol >= 0.0) || opts->warm < 0 || opts->warm > 1 || !(opts->inner_rho >= 0.0) ||
+                 opts->inner_rho >= 1.0)) {
+        ctx->err = "bad solve options";
+        return PC_ERR_ARG;
+    }
+    pc_status st = pc_check(h, stream);
+    if (st) return st;
+    return pcg_run(ctx, b, dv, opts, info, (hipStream_t)stream);
+}
+
+pc_status cloth_spmv(pc_ctx *h, const double *x, double *y, int32_t solver_blocks, void *stream) {
+    if (!h || !x || !y) return PC_ERR_ARG;
+    return spmv_run(&h->c, x, y, solver_blocks != 0, (hipStream_t)stream);
+}
+
+pc_status cloth_export_pattern(pc_ctx *h, int32_t *rowptr_out, int32_t *colidx_out, int64_t *nnzb_out,
+                               void *stream) {
+    if (!h) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (!ctx->assembled) { ctx->err = "cloth_export_pattern: nothing assembled"; return PC_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    pc_status st = pc_check(h, stream);
+    if (st) return st;
+    int nnzb = 0;
+    PC_HIP(hipMemcpyAsync(ctx->status_host, ctx->rowptr + ctx->nv, sizeof(int), hipMemcpyDeviceToHost, s));
+    PC_HIP(hipStreamSynchronize(s));
+    nnzb = *ctx->status_host;
+    if (nnzb_out) *nnzb_out = nnzb;
+    if (rowptr_out)
+        PC_HIP(hipMemcpyAsync(rowptr_out, ctx->rowptr, sizeof(int) * (size_t)(ctx->nv + 1), hipMemcpyDeviceToDevice, s));
+    if (colidx_out && nnzb > 0)
+        PC_HIP(hipMemcpyAsync(colidx_out, ctx->colidx, sizeof(int) * (size_t)nnzb, hipMemcpyDeviceToDevice, s));
+    return PC_OK;
+}
+
+pc_status cloth_export_blocks(pc_ctx *h, double *vals_out, double *D_out, int32_t solver_blocks, void *stream) {
+    if (!h || !vals_out) return PC_ERR_ARG;
+    return export_blocks(&h->c, vals_out, D_out, solver_blocks != 0, (hipStream_t)stream);
+}
+
+pc_status cloth_step(pc_ctx *h, double *x, double *v, int32_t nsteps, pc_dtype dtype, const pc_solve_opts *opts,
+                     pc_solve_info *infos, void *stream) {
+    if (!h) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (!x || !v || nsteps < 0) { ctx->err = "cloth_step: bad arguments"; return PC_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    pc_solve_opts o = opts ? *opts : pc_solve_opts{1e-6, 0.0, 20000, 0, 0, 0};
+    // dv lives in ctx->tmp between steps (previous-step start when warm = 1)
+    for (int k = 0; k < nsteps; ++k) {
+        pc_status st = assemble_run(ctx, x, v, dtype, ctx->bbuf, nullptr, s);
+        if (st) return st;
+        pc_solve_info info{};
+        if ((st = pc_check(h, stream))) return st;
+        pc_solve_opts ok = o;
+        if (!ctx->have_prev_dv) ok.warm = 0;
+        st = pcg_run(ctx, ctx->bbuf, ctx->tmp, &ok, &info, s);
+        if (infos) infos[k] = info;
+        if (st) return st;
+        if ((st = update_run(ctx, ctx->tmp, x, v, s))) return st;
+        ctx->have_prev_dv = true;
+    }
+    PC_HIP(hipStreamSynchronize(s));
+    return PC_OK;
+}
+
+}  // extern "C"

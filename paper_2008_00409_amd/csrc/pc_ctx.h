@@ -1,0 +1,167 @@
+// Host-side context of the library: device buffers and launch helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "pc_common.h"
+#include "pcloth.h"
+
+namespace pc {
+
+struct PcgState {
+    double rz, pq, alpha, beta, rr, bb, tol2, rz0;
+    double rho2;     // inner reduction factor squared (refinement sweeps)
+    double thresh;   // stop when ||r||^2 <= thresh = max(tol^2 ||b||^2, rho^2 ||r_0||^2)
+    double rr0;      // ||r_0||^2 of this sweep
+    int iters, maxit, done, flags;   // flags: 1 breakdown (p.Ap <= 0), 2 non-finite
+};
+
+// Sampled kernel timing with HIP events on the launch stream: every
+// `every`-th launch of a timed kind is bracketed by an event pair; pairs are
+// read back at the next synchronisation point.
+enum ProfKind { PK_SPMV = 0, PK_UPDATE = 1, PK_DIR = 2, PK_ROW_ASM = 3, PK_ROW_PAT = 4, PK_ASM_ALL = 5,
+                PK_NKINDS = 8 };
+
+struct Prof {
+    int every = 0;
+    long long tick[PK_NKINDS] = {};
+    std::vector<hipEvent_t> pool;      // 2 events per slot
+    std::vector<int> free_slots;
+    std::vector<std::pair<int, int>> pending;  // (kind, slot)
+    double sum_ms[PK_NKINDS] = {}, min_ms[PK_NKINDS] = {}, max_ms[PK_NKINDS] = {};
+    long long count[PK_NKINDS] = {};
+
+    void init(int nslots) {
+        if (!pool.empty()) return;
+        pool.resize(2 * (size_t)nslots);
+        for (auto &e : pool) (void)hipEventCreate(&e);
+        for (int k = nslots - 1; k >= 0; --k) free_slots.push_back(k);
+    }
+    void destroy() {
+        for (auto &e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+        free_slots.clear();
+        pending.clear();
+    }
+    void reset() {
+        for (int k = 0; k < PK_NKINDS; ++k) {
+            sum_ms[k] = min_ms[k] = max_ms[k] = 0.0;
+            count[k] = 0;
+            tick[k] = 0;
+        }
+    }
+    // returns a slot (>= 0) when this launch is sampled; records the start event
+    int begin(int kind, hipStream_t s) {
+        if (every <= 0) return -1;
+        if ((tick[kind]++ % every) != 0 || free_slots.empty()) return -1;
+        const int slot = free_slots.back();
+        free_slots.pop_back();
+        (void)hipEventRecord(pool[2 * (size_t)slot], s);
+        pending.emplace_back(kind, slot);
+        return slot;
+    }
+    void end(int slot, hipStream_t s) {
+        if (slot >= 0) (void)hipEventRecord(pool[2 * (size_t)slot + 1], s);
+    }
+    // call after the stream has been synchronised
+    void harvest() {
+        for (auto &kp : pending) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, pool[2 * (size_t)kp.second], pool[2 * (size_t)kp.second + 1]) ==
+                hipSuccess) {
+                const int k = kp.first;
+                if (count[k] == 0 || ms < min_ms[k]) min_ms[k] = ms;
+                if (count[k] == 0 || ms > max_ms[k]) max_ms[k] = ms;
+                sum_ms[k] += ms;
+                count[k] += 1;
+            }
+            free_slots.push_back(kp.second);
+        }
+        pending.clear();
+    }
+};
+
+struct Ctx {
+    std::string err;
+    Prof prof;
+    int nv = 0, nt = 0, nh = 0;
+    int nslices = 0;          // ceil(nv / 64)
+    int64_t cap = 0;          // block capacity (upper bound of nnzb)
+    int64_t ninc = 0;         // 3 nt + 4 nh incidences
+    DevParams prm{};
+    pc_params user_prm{};
+
+    // static topology / rest data (device)
+    int *tri = nullptr;       // 3 planes of nt
+    double *Bm = nullptr;     // 4 planes of nt (inverse rest frame, row major)
+    double *A0 = nullptr;     // nt
+    int *hinge = nullptr;     // 4 planes of nh
+    double *hcoef = nullptr;  // nh, 3|e|^2 / (A1 + A2)
+    double *htbar = nullptr;  // nh, rest angle
+    double *mass = nullptr;   // nv
+    uint8_t *pinned = nullptr;
+    int *status = nullptr;    // device error bits
+
+    // per-step pattern
+    int *inc_cnt = nullptr;   // nv (kept at zero between uses)
+    int *inc_ptr = nullptr;   // nv + 1
+    int *inc = nullptr;       // ninc
+    int *rowlen = nullptr;    // nv
+    int *rowptr = nullptr;    // nv + 1
+    int *colidx = nullptr;    // cap (block-CSR order)
+    int *jcol = nullptr;      // cap (solver layout)
+    int *lane_row = nullptr;  // nslices * 64 (row of each lane, -1 padding)
+    int *row_lane = nullptr;  // nv
+    uint8_t *slot_cnt = nullptr;  // nslices * 64
+    void *jval = nullptr;     // cap * 9 values of dtype (solver copy)
+    size_t jval_bytes = 0;
+    double *jval_hi = nullptr;  // cap * 9 FP64 values (refinement residual), when dtype != PC_F64
+    bool hi_valid = false;
+    pc_dtype dtype = PC_F32;
+    bool assembled = false;
+    bool have_prev_dv = false;  // ctx->tmp holds the previous step's dv
+    double *diag = nullptr;   // nv * 3
+    float *dinv = nullptr;    // nv * 3
+
+    // solver vectors
+    double *x = nullptr, *r = nullptr, *q = nullptr, *tmp = nullptr, *bbuf = nullptr;
+    float4 *p = nullptr;
+    double *partials = nullptr;   // per-block partial sums (4 doubles per block)
+    double *res2 = nullptr;       // 2 doubles: true-residual check
+    unsigned *counter = nullptr;
+    PcgState *st = nullptr;       // device
+    PcgState *st_host = nullptr;  // pinned host
+    int *status_host = nullptr;   // pinned host
+
+    // scan scratch
+    int *scan_tmp = nullptr;
+    size_t scan_tmp_elems = 0;
+};
+
+// Error helpers (host)
+#define PC_HIP(call)                                                                 \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+            return PC_ERR_HIP;                                                       \
+        }                                                                            \
+    } while (0)
+
+// launch-side entry points implemented in the .hip files
+pc_status topo_build(Ctx *ctx, const pc_mesh *mesh, hipStream_t s);
+pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtype, double *b,
+                       double *diag_out, hipStream_t s);
+pc_status export_blocks(Ctx *ctx, double *vals, double *D, bool solver, hipStream_t s);
+pc_status spmv_run(Ctx *ctx, const double *xin, double *y, bool solver, hipStream_t s);
+pc_status pcg_run(Ctx *ctx, const double *b, double *dv, const pc_solve_opts *o, pc_solve_info *info,
+                  hipStream_t s);
+pc_status update_run(Ctx *ctx, const double *dv, double *x, double *v, hipStream_t s);
+pc_status scan_excl(Ctx *ctx, const int *in, int *out, int n, hipStream_t s);
+pc_status dev_alloc(Ctx *ctx, void **p, size_t bytes);
+pc_status read_status(Ctx *ctx, hipStream_t s, int *bits);
+
+}  // namespace pc

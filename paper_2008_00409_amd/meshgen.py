@@ -128,15 +128,18 @@ def interior_edges(tris: np.ndarray):
 
 
 def flip_edges(rest: np.ndarray, tris: np.ndarray, fraction: float,
-               rng: np.random.Generator) -> np.ndarray:
+               rng: np.random.Generator, delaunay: bool = True, strict: bool = False) -> np.ndarray:
     """Flip a random `fraction` of interior edges.
 
     A flip of edge a-b between t1=(a,b,c) and t2=(b,a,d) replaces them with
-    (c,a,d) and (d,b,c).  It is accepted only when both new triangles have
-    positive area in the rest plane (strictly convex quad), the new diagonal
-    c-d is not already an edge, and neither triangle has been flipped before in
-    this pass.  Edges are visited in a seeded random order until the target
-    count is reached.
+    (c,a,d) and (d,b,c).  With `delaunay` (the default) only illegal edges are
+    flipped -- d strictly inside the circumcircle of (a,b,c) in the rest plane --
+    so every flip makes its edge Delaunay-legal (and the quad is then convex).
+    A flip is accepted only when both new triangles have positive area, the new
+    diagonal c-d is not already an edge, and neither triangle has been flipped
+    before in this pass.  Edges are visited in a seeded random order until the
+    target count is reached (or every edge has been visited; `strict` then
+    raises).
     """
     tris = tris.copy()
     a, b, t1, t2 = interior_edges(tris)
@@ -160,6 +163,15 @@ def flip_edges(rest: np.ndarray, tris: np.ndarray, fraction: float,
         return ((xy[q, 0] - xy[p, 0]) * (xy[r, 1] - xy[p, 1])
                 - (xy[q, 1] - xy[p, 1]) * (xy[r, 0] - xy[p, 0]))
 
+    def in_circle(p, q, r, t):
+        # > 0 when t lies inside the circumcircle of the counter-clockwise p, q, r
+        rows = []
+        for u in (p, q, r):
+            dx, dy = xy[u, 0] - xy[t, 0], xy[u, 1] - xy[t, 1]
+            rows.append((dx, dy, dx * dx + dy * dy))
+        (a1, a2, a3), (b1, b2, b3), (c1, c2, c3) = rows
+        return a1 * (b2 * c3 - b3 * c2) - a2 * (b1 * c3 - b3 * c1) + a3 * (b1 * c2 - b2 * c1)
+
     done = 0
     for e in perm:
         if done >= target:
@@ -177,13 +189,15 @@ def flip_edges(rest: np.ndarray, tris: np.ndarray, fraction: float,
             continue
         if ccw(c, va, d) <= 0.0 or ccw(d, vb, c) <= 0.0:
             continue
+        if delaunay and in_circle(va, vb, c, d) <= 0.0:
+            continue
         tris[ta] = (c, va, d)
         tris[tb] = (d, vb, c)
         used[ta] = used[tb] = True
         edges.discard(min(va, vb) * nv + max(va, vb))
         edges.add(key)
         done += 1
-    if done < target:
+    if done < target and strict:
         raise RuntimeError(f"edge flips: reached {done} of {target}")
     return tris
 
@@ -241,7 +255,8 @@ def config_medium(seed: int = 2000) -> Cloth:
 
 
 def irregular_sheet(nx: int, ny: int, ell: float, z0: float, seed: int,
-                    flip_fraction: float, bumps: bool = True):
+                    flip_fraction: float, bumps: bool = True, strict: bool = False,
+                    delaunay: bool = True):
     """Jittered (0.3 ell, in-plane, interior vertices) and edge-flipped grid sheet
     with its top row pinned; returns rest, tris, pinned, initial positions."""
     rng = _rng(seed)
@@ -249,7 +264,7 @@ def irregular_sheet(nx: int, ny: int, ell: float, z0: float, seed: int,
     rest, tris = grid(nx, ny, width, height, z0)
     rest = jitter_rest(rest, nx, ny, ell, 0.3, rng)
     if flip_fraction > 0.0:
-        tris = flip_edges(rest, tris, flip_fraction, rng)
+        tris = flip_edges(rest, tris, flip_fraction, rng, delaunay=delaunay, strict=strict)
     pinned = np.zeros(rest.shape[0], dtype=np.uint8)
     pinned[(ny - 1) * nx:] = 1
     x0 = rest.copy()
@@ -285,7 +300,7 @@ def config_large(seed_base: int = 3000, sheets: int = 3, nx: int = 501, ny: int 
     """Three stacked irregular sheets, 501 x 551 vertices each (550,000 triangles
     each, 1.65M in total), edge length 2 mm, at z = 0, 0.02, 0.04 m; 10% of
     interior edges flipped; top rows pinned; h = 0.01 s, tolerance 1e-6."""
-    parts = [irregular_sheet(nx, ny, 0.002, 0.02 * s, seed_base + s, flip_fraction)
+    parts = [irregular_sheet(nx, ny, 0.002, 0.02 * s, seed_base + s, flip_fraction, strict=True)
              for s in range(sheets)]
     return stack_sheets(parts, f"stacked-{sheets}x{nx}x{ny}", 0.01, 1e-6, 100)
 

@@ -1,0 +1,175 @@
+"""GPU parity of the SpMV, the Jacobi-PCG solve and the step (paper Sec. 2.5,
+Eq. 3 solved by PCG; Sec. 3.1) against the FP64 oracle, through the C ABI.
+
+A CG solution is not unique, so the solve is judged by its residual through
+the oracle's FP64 matrix: ||b - A_oracle dv|| / ||b|| <= tol for every block
+storage type (the refinement residual is taken with FP64 blocks)."""
+import numpy as np
+import pytest
+
+from gpu_helpers import random_velocity, require_gpu, sheet, to_dev
+from paper_2008_00409_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2008_00409_amd import binding
+    return binding
+
+
+@pytest.mark.parametrize("dtype,rtol", [("f64", 1e-13), ("f32", 1e-6), ("bf16", 5e-2)])
+def test_spmv_matches_oracle(torch, B, oracle_mod, dtype, rtol):
+    c = sheet(33, 31, seed=11, flips=0.1)
+    P = oracle_mod.Problem.from_cloth(c)
+    v = random_velocity(c)
+    A = P.assemble(c.x0, v)
+    ctx = B.Context.from_cloth(c)
+    try:
+        ctx.cloth_assemble(to_dev(torch, c.x0), to_dev(torch, v), dtype)
+        rng = np.random.default_rng(5)
+        # smooth and rough inputs
+        xs = [np.sin(3 * c.rest[:, :1] + np.array([[0.0, 1.0, 2.0]])) * 0.01, rng.normal(size=c.rest.shape)]
+        for xin in xs:
+            want = P.spmv(A, xin)
+            y = ctx.cloth_spmv(to_dev(torch, xin), solver_blocks=True).cpu().numpy()
+            err = np.linalg.norm(y - want) / np.linalg.norm(want)
+            assert err <= rtol, f"{dtype}: {err:.3e}"
+            y = ctx.cloth_spmv(to_dev(torch, xin), solver_blocks=False).cpu().numpy()
+            err = np.linalg.norm(y - want) / np.linalg.norm(want)
+            assert err <= 1e-13, f"FP64 copy: {err:.3e}"
+    finally:
+        ctx.close()
+
+
+def solve_case(torch, B, oracle_mod, c, dtype, tol, v_scale=0.05):
+    P = oracle_mod.Problem.from_cloth(c)
+    v = random_velocity(c, v_scale)
+    A = P.assemble(c.x0, v)
+    ctx = B.Context.from_cloth(c)
+    try:
+        b = ctx.cloth_assemble(to_dev(torch, c.x0), to_dev(torch, v), dtype)
+        dv, info = ctx.cloth_pcg_solve(b, tol=tol)
+        return P, A, dv.cpu().numpy(), info
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_solve_tiny_residual_through_oracle(torch, B, oracle_mod, dtype):
+    """The refinement residual uses FP64 blocks, so for every storage type the
+    solution meets the tolerance through the oracle's FP64 matrix."""
+    c = mg.config_tiny()
+    P, A, dv, info = solve_case(torch, B, oracle_mod, c, dtype, 1e-8, v_scale=0.0)
+    res = P.residual(A, dv)
+    assert res <= (1.0 + 1e-6) * 1e-8, res
+    assert info["rel_res_true"] <= 1e-8 * (1 + 1e-9)
+    if dtype == "f64":
+        # iteration count close to the oracle's (same method, same tolerance)
+        _, oinfo = P.pcg(A, tol=1e-8)
+        assert abs(info["iters"] - oinfo["iters"]) <= max(3, 0.02 * oinfo["iters"])
+    # against the dense direct solve
+    ref = np.linalg.solve(A.dense(), A.b.ravel())
+    assert np.linalg.norm(dv.ravel() - ref) / np.linalg.norm(ref) < 1e-5
+    assert np.all(dv[c.pinned == 1] == 0)
+
+
+@pytest.mark.parametrize("name,c", [("ragged-7x9", sheet(7, 9, seed=1)),
+                                    ("flipped-40x37", sheet(40, 37, seed=3, flips=0.1)),
+                                    ("grid-96", mg.config_grid(96, seed=21))])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_solve_residual_through_oracle(torch, B, oracle_mod, name, c, dtype):
+    P, A, dv, info = solve_case(torch, B, oracle_mod, c, dtype, 1e-6)
+    res = P.residual(A, dv)
+    assert res <= 1e-6 * (1 + 1e-6), res
+    assert info["rel_res_true"] <= 1e-6
+
+
+def test_bf16_breakdown_falls_back_to_fp64_blocks(torch, B, oracle_mod):
+    """Arbitrary convex flips make sliver triangles (condition number ~1e8);
+    the BF16-rounded operator is then indefinite and its CG breaks down.  The
+    solve must switch to the FP64 blocks and still meet the tolerance."""
+    c = sheet(40, 37, seed=3, flips=0.1, delaunay=False)
+    P, A, dv, info = solve_case(torch, B, oracle_mod, c, "bf16", 1e-6)
+    assert info["fallback"] == 1
+    assert P.residual(A, dv) <= 1e-6 * (1 + 1e-6)
+
+
+def test_solve_edge_cases(torch, B, oracle_mod):
+    c = sheet(10, 10, seed=6)
+    ctx = B.Context.from_cloth(c)
+    try:
+        x = to_dev(torch, c.x0)
+        b = ctx.cloth_assemble(x, torch.zeros_like(x), "f32")
+        # b = 0: zero iterations and dv = 0 whatever the start
+        z = torch.zeros_like(b)
+        dv, info = ctx.cloth_pcg_solve(z, dv=torch.ones_like(b), warm=True)
+        assert info["iters"] == 0 and float(dv.abs().max()) == 0.0
+        # maxit too small: not converged, last iterate returned
+        dv, info = ctx.cloth_pcg_solve(b, tol=1e-12, maxit=2, raise_on_error=False)
+        assert info["status"] == B.PC_ERR_NOT_CONVERGED and info["iters"] == 2
+        # warm start from the solution: converges at once
+        dv, info = ctx.cloth_pcg_solve(b, tol=1e-6)
+        dv2, info2 = ctx.cloth_pcg_solve(b, dv=dv.clone(), tol=1e-6, warm=True)
+        assert info2["iters"] <= 1
+        # non-finite state is reported
+        xn = x.clone()
+        xn[5, 0] = float("nan")
+        b = ctx.cloth_assemble(xn, torch.zeros_like(x), "f32")
+        with pytest.raises(B.PclothError, match="PC_ERR_NONFINITE"):
+            ctx.cloth_pcg_solve(b)
+    finally:
+        ctx.close()
+
+
+def test_solve_deterministic(torch, B):
+    c = sheet(40, 40, seed=13, flips=0.1)
+    ctx = B.Context.from_cloth(c)
+    try:
+        x, v = to_dev(torch, c.x0), to_dev(torch, random_velocity(c))
+        outs = []
+        for _ in range(2):
+            b = ctx.cloth_assemble(x, v, "f32")
+            dv, info = ctx.cloth_pcg_solve(b, tol=1e-7)
+            outs.append((dv.cpu().numpy().copy(), info["iters"]))
+        assert outs[0][1] == outs[1][1]
+        assert np.array_equal(outs[0][0].view(np.uint64), outs[1][0].view(np.uint64))
+    finally:
+        ctx.close()
+
+
+def test_steps_match_oracle_trajectory(torch, B, oracle_mod):
+    c = sheet(16, 16, seed=17, flips=0.1)
+    P = oracle_mod.Problem.from_cloth(c)
+    ctx = B.Context.from_cloth(c)
+    try:
+        x, v = to_dev(torch, c.x0), to_dev(torch, c.v0)
+        xo, vo = c.x0.copy(), c.v0.copy()
+        tol = 1e-10
+        infos = ctx.cloth_step(x, v, nsteps=3, dtype="f64", tol=tol)
+        for k in range(3):
+            xo, vo, dvo, oinfo = P.step(xo, vo, tol=tol)
+        xg, vg = x.cpu().numpy(), v.cpu().numpy()
+        # both solve to 1e-10: velocities agree to a small multiple of that
+        assert np.linalg.norm(vg - vo) / np.linalg.norm(vo) < 1e-6
+        assert np.abs(xg - xo).max() < 1e-8
+        np.testing.assert_array_equal(xg[c.pinned == 1], c.x0[c.pinned == 1])
+        assert all(i["rel_res_true"] <= tol * (1 + 1e-6) for i in infos)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.slow
+def test_medium_full_size_solve(torch, B, oracle_mod):
+    """512 x 512 workload: one step's solve at tolerance 1e-6 with FP32
+    blocks, judged through the oracle's FP64 matrix."""
+    c = mg.config_medium()
+    P, A, dv, info = solve_case(torch, B, oracle_mod, c, "f32", 1e-6, v_scale=0.0)
+    res = P.residual(A, dv)
+    assert res <= 1e-6 * (1 + 1e-6), res
