@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "medium"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prof-every", type=int, default=8)
+    ap.add_argument("--graph", type=int, default=0, help="CG iterations per captured HIP graph (0: off)")
+    ap.add_argument("--warm", action="store_true", help="previous-step dv as the CG start")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the whole 1.65M-triangle workload fits in one MI355X "
@@ -100,15 +102,18 @@ def main():
     print(f"# workload {cloth.name}: nv={cloth.nv} nt={cloth.nt} ({time.perf_counter() - t0:.1f} s)",
           file=sys.stderr, flush=True)
     ctx = binding.Context.from_cloth(cloth)
+    if args.graph:
+        ctx.set_option(binding.PC_OPT_GRAPH_CHUNK, args.graph)
     x = torch.from_numpy(cloth.x0.copy()).cuda()
     v = torch.from_numpy(cloth.v0.copy()).cuda()
     tol = cloth.tol
-    warm_infos = ctx.cloth_step(x, v, nsteps=args.warmup, dtype=args.blocks, tol=tol) if args.warmup else []
+    warm_infos = (ctx.cloth_step(x, v, nsteps=args.warmup, dtype=args.blocks, tol=tol, warm=args.warm)
+                  if args.warmup else [])
     print(f"# warmup done: iters {[i['iters'] for i in warm_infos]}", file=sys.stderr, flush=True)
     ctx.profile(args.prof_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = ctx.cloth_step(x, v, nsteps=args.steps, dtype=args.blocks, tol=tol)
+    infos = ctx.cloth_step(x, v, nsteps=args.steps, dtype=args.blocks, tol=tol, warm=args.warm)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = ctx.profile_read()
@@ -138,7 +143,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{cloth.name}: {nt} triangles, {nv} vertices, {nh} hinges, nnzb {nnzb}",
-            "h": cloth.h, "tol": tol, "block_storage": args.blocks, "warm_start": "zero",
+            "h": cloth.h, "tol": tol, "block_storage": args.blocks,
+            "warm_start": "previous-step" if args.warm else "zero", "graph_chunk": args.graph,
+            "refinement_sweeps": [i["sweeps"] for i in infos],
             "preconditioner": "jacobi", "cg_iters_per_step": {"mean": float(np.mean(iters)),
                                                                "min": int(min(iters)), "max": int(max(iters))},
             "rel_res_true_max": max(i["rel_res_true"] for i in infos),

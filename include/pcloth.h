@@ -61,7 +61,13 @@ typedef struct {
     double k_bend;       /* bending stiffness (N m) */
     double beta;         /* stiffness-proportional damping (s); 0 reproduces Eq. 3 */
     double gravity[3];   /* m/s^2 */
-    int32_t rhs_mode;    /* 0: Eq. 3 as printed (lookahead force), 1: linearised */
+    int32_t rhs_mode;    /* 0: Eq. 3 as printed, lookahead force f(x + h v);
+                            1: the same force linearised with the matrix's own Jacobian
+                            (Eq. 2 applied to the right-hand side): h [f(x) - (h+beta) K v].
+                            With the PSD solver Jacobian only mode 1 is stable on cloth with
+                            compressed regions (mode 0 integrates the negative stiffness
+                            explicitly and grows exponentially); mode 1 is the recommended
+                            setting. */
     int32_t reserved;
 } pc_params;
 
@@ -188,6 +194,14 @@ pc_status cloth_export_pattern(pc_ctx *ctx, int32_t *rowptr_out, int32_t *colidx
  * assembly), out[4k..4k+3] = {samples, mean ms, min ms, max ms} (host, 32). */
 pc_status pc_profile(pc_ctx *ctx, int32_t every);
 pc_status pc_profile_read(pc_ctx *ctx, double *out);
+
+/* Context options.
+ * PC_OPT_GRAPH_CHUNK: when > 0, CG iterations are captured once into a HIP
+ *   graph of that many iterations and replayed (the convergence flag makes
+ *   iterations after convergence exit at once); event nodes around the first
+ *   iteration of each replay feed pc_profile.  0 (default): plain launches. */
+typedef enum { PC_OPT_GRAPH_CHUNK = 0 } pc_option;
+pc_status pc_set_option(pc_ctx *ctx, int32_t option, int64_t value);
 
 /* Synchronise the stream and report device-side errors of earlier calls. */
 pc_status pc_check(pc_ctx *ctx, void *stream);

@@ -189,7 +189,7 @@ class Material:
     kb: float = 1e-5
     beta: float = 0.0
     gravity: tuple = (0.0, 0.0, -9.81)
-    rhs_mode: int = 0
+    rhs_mode: int = 1
     hess_mode: int = 0
 
 

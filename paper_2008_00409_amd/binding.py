@@ -25,7 +25,8 @@ DTYPES = {"f64": PC_F64, "f32": PC_F32, "bf16": PC_BF16}
 # Names of every entry point declared in include/pcloth.h.
 ABI_SYMBOLS = ["pc_create", "pc_destroy", "pc_set_params", "pc_last_error", "pc_sizes", "pc_get_hinges",
                "cloth_assemble", "cloth_pcg_solve", "cloth_step", "cloth_spmv", "cloth_export_blocks",
-               "cloth_export_pattern", "pc_check", "pc_profile", "pc_profile_read"]
+               "cloth_export_pattern", "pc_check", "pc_profile", "pc_profile_read", "pc_set_option"]
+PC_OPT_GRAPH_CHUNK = 0
 PROFILE_KINDS = ["spmv", "cg_update", "cg_dir", "row_assemble", "row_pattern", "assemble_all", "k6", "k7"]
 
 
@@ -93,6 +94,7 @@ def lib():
         L.pc_check.argtypes = [vp, vp]
         L.cloth_export_pattern.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
         L.pc_profile.argtypes = [vp, ctypes.c_int32]
+        L.pc_set_option.argtypes = [vp, ctypes.c_int32, ctypes.c_int64]
         L.pc_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         for name in ABI_SYMBOLS:
             if name not in ("pc_last_error",):
@@ -127,7 +129,7 @@ def _dev3(t, nv, name):
     return _ptr(t)
 
 
-def make_params(h, mu=1000.0, lam=500.0, k_bend=1e-5, beta=0.0, gravity=(0.0, 0.0, -9.81), rhs_mode=0):
+def make_params(h, mu=1000.0, lam=500.0, k_bend=1e-5, beta=0.0, gravity=(0.0, 0.0, -9.81), rhs_mode=1):
     p = PcParams()
     p.h, p.mu, p.lambda_, p.k_bend, p.beta = float(h), float(mu), float(lam), float(k_bend), float(beta)
     for a in range(3):
@@ -257,6 +259,9 @@ class Context:
                               ctypes.byref(o), infos, _stream())
         self._check(st)
         return [infos[k].as_dict() for k in range(nsteps)]
+
+    def set_option(self, option, value):
+        self._check(lib().pc_set_option(self.h, int(option), int(value)))
 
     def profile(self, every):
         self._check(lib().pc_profile(self.h, int(every)))

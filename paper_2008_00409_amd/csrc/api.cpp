@@ -218,10 +218,33 @@ pc_status pc_profile_read(pc_ctx *h, double *out) {
     return PC_OK;
 }
 
+pc_status pc_set_option(pc_ctx *h, int32_t option, int64_t value) {
+    if (!h) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    switch (option) {
+        case PC_OPT_GRAPH_CHUNK:
+            if (value < 0 || value > 4096) {
+                ctx->err = "graph chunk must be in [0, 4096]";
+                return PC_ERR_ARG;
+            }
+            ctx->graph_chunk = (int)value;
+            return PC_OK;
+        default:
+            ctx->err = "unknown option";
+            return PC_ERR_ARG;
+    }
+}
+
 pc_status pc_destroy(pc_ctx *h) {
     if (!h) return PC_ERR_ARG;
     (void)hipDeviceSynchronize();
     h->c.prof.destroy();
+    for (int v = 0; v < 2; ++v) {
+        if (h->c.gexec[v]) (void)hipGraphExecDestroy(h->c.gexec[v]);
+        for (int k = 0; k < 6; ++k)
+            if (h->c.gev[v][k]) (void)hipEventDestroy(h->c.gev[v][k]);
+    }
+    if (h->c.cap_stream) (void)hipStreamDestroy(h->c.cap_stream);
     free_all(&h->c);
     delete h;
     return PC_OK;

@@ -139,6 +139,17 @@ struct Ctx {
     // scan scratch
     int *scan_tmp = nullptr;
     size_t scan_tmp_elems = 0;
+
+    // CG iterations captured as HIP graphs: one per inner operator (0: the
+    // solver copy, 1: the FP64 blocks), each `graph_chunk` iterations long,
+    // with event nodes around the first iteration's kernels for timing.
+    int graph_chunk = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    const void *gkey[2] = {nullptr, nullptr};
+    int gkey_dtype[2] = {-1, -1};
+    int gkey_chunk[2] = {0, 0};
+    hipEvent_t gev[2][6] = {};
 };
 
 // Error helpers (host)

@@ -32,6 +32,14 @@ struct SpmvArgs {
     const double *mass;
 };
 
+// Streamed (read-once per product) loads bypass cache retention so that the
+// gathered vector stays resident.
+__device__ __forceinline__ double ld_stream(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_stream(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ bf16_t ld_stream(const bf16_t *p) {
+    return bf16_t{__builtin_nontemporal_load(&p->bits)};
+}
+
 struct VecF4 {
     const float4 *p;
     __device__ __forceinline__ void load(int i, double &a, double &b, double &c) const {
@@ -74,10 +82,10 @@ __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, 
             act[u] = (k + u < nslots) && lane < c;
             jc[u] = row;
             if (act[u]) {
-                jc[u] = M.jcol[off + lane];
+                jc[u] = __builtin_nontemporal_load(M.jcol + off + lane);
                 const TB *vp = (const TB *)M.jval + 9 * (int64_t)off + lane;
 #pragma unroll
-                for (int e = 0; e < 9; ++e) v[u][e] = vp[(int64_t)e * c];
+                for (int e = 0; e < 9; ++e) v[u][e] = ld_stream(vp + (int64_t)e * c);
             }
         }
 #pragma unroll
@@ -222,23 +230,29 @@ __global__ void __launch_bounds__(1024) k_fin_alpha(const double *partials, int 
 }
 
 // x += alpha p, r -= alpha q; partials of r.z (z = D^-1 r) and r.r.
-__global__ void __launch_bounds__(256) k_pcg_update(int nv, double *x, double *r, const float4 *p,
+// Flat indexing over the 3 nv components: each thread handles UPD_PER
+// components spaced by the block size, so every load instruction of a
+// wavefront covers consecutive 8-byte elements.
+constexpr int UPD_PER = 4;
+__global__ void __launch_bounds__(256) k_pcg_update(int n3, double *x, double *r, const float *pf,
                                                     const double *q, const float *dinv, const PcgState *st,
                                                     double *partials) {
     if (st->done) return;
     const double alpha = st->alpha;
-    const int i = row_of_thread();
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int base = b * (256 * UPD_PER) + threadIdx.x;
     double rz = 0.0, rr = 0.0;
-    if (i < nv) {
-        const float4 pv = p[i];
-        const double pp[3] = {pv.x, pv.y, pv.z};
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            x[3 * i + a] += alpha * pp[a];
-            const double ra = r[3 * i + a] - alpha * q[3 * i + a];
-            r[3 * i + a] = ra;
-            rz += ra * ra * (double)dinv[3 * i + a];
-            rr += ra * ra;
+    for (int u = 0; u < UPD_PER; ++u) {
+        const int k = base + u * 256;
+        if (k < n3) {
+            const int i = k / 3;
+            const double pk = pf[4 * i + (k - 3 * i)];
+            x[k] += alpha * pk;
+            const double rk = r[k] - alpha * q[k];
+            r[k] = rk;
+            rz += rk * rk * (double)dinv[k];
+            rr += rk * rk;
         }
     }
     double v[2] = {rz, rr};
@@ -428,27 +442,48 @@ static inline int pad8(int n) { return ((n + 7) / 8) * 8; }
 struct Grids {
     int slice_blocks;  // 4 slices per 256-thread block
     int row_blocks;    // 256 rows per block
+    int upd_blocks;    // 256 * UPD_PER components per block
 };
 
 static Grids grids(Ctx *ctx) {
     Grids g;
     g.slice_blocks = pad8((ctx->nslices + 3) / 4);
     g.row_blocks = pad8((ctx->nv + 255) / 256);
+    g.upd_blocks = pad8((3 * ctx->nv + 256 * UPD_PER - 1) / (256 * UPD_PER));
     return g;
 }
 
+// One CG iteration.  With `ev` (graph capture) the three main kernels are
+// bracketed by the given event pairs instead of the sampled profiler.
 template <typename TB>
-static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Grids &g, hipStream_t s) {
+static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Grids &g, hipStream_t s, hipEvent_t *ev = nullptr) {
+    if (ev) {
+        (void)hipEventRecord(ev[0], s);
+        hipLaunchKernelGGL(k_pcg_spmv<TB>, dim3(g.slice_blocks), dim3(256), 0, s, M, ctx->p, ctx->q, ctx->st,
+                           ctx->partials);
+        (void)hipEventRecord(ev[1], s);
+        hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(1024), 0, s, ctx->partials, g.slice_blocks, ctx->st);
+        (void)hipEventRecord(ev[2], s);
+        hipLaunchKernelGGL(k_pcg_update, dim3(g.upd_blocks), dim3(256), 0, s, 3 * ctx->nv, ctx->x, ctx->r,
+                           (const float *)ctx->p, ctx->q, ctx->dinv, ctx->st, ctx->partials);
+        (void)hipEventRecord(ev[3], s);
+        hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(1024), 0, s, ctx->partials, g.upd_blocks, ctx->st);
+        (void)hipEventRecord(ev[4], s);
+        hipLaunchKernelGGL(k_pcg_dir, dim3(g.row_blocks), dim3(256), 0, s, ctx->nv, ctx->r, ctx->p, ctx->dinv,
+                           ctx->st);
+        (void)hipEventRecord(ev[5], s);
+        return;
+    }
     int slot = ctx->prof.begin(PK_SPMV, s);
     hipLaunchKernelGGL(k_pcg_spmv<TB>, dim3(g.slice_blocks), dim3(256), 0, s, M, ctx->p, ctx->q, ctx->st,
                        ctx->partials);
     ctx->prof.end(slot, s);
     hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(1024), 0, s, ctx->partials, g.slice_blocks, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
-    hipLaunchKernelGGL(k_pcg_update, dim3(g.row_blocks), dim3(256), 0, s, ctx->nv, ctx->x, ctx->r, ctx->p,
-                       ctx->q, ctx->dinv, ctx->st, ctx->partials);
+    hipLaunchKernelGGL(k_pcg_update, dim3(g.upd_blocks), dim3(256), 0, s, 3 * ctx->nv, ctx->x, ctx->r,
+                       (const float *)ctx->p, ctx->q, ctx->dinv, ctx->st, ctx->partials);
     ctx->prof.end(slot, s);
-    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(1024), 0, s, ctx->partials, g.row_blocks, ctx->st);
+    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(1024), 0, s, ctx->partials, g.upd_blocks, ctx->st);
     slot = ctx->prof.begin(PK_DIR, s);
     hipLaunchKernelGGL(k_pcg_dir, dim3(g.row_blocks), dim3(256), 0, s, ctx->nv, ctx->r, ctx->p, ctx->dinv,
                        ctx->st);
@@ -468,6 +503,54 @@ static void launch_residual(Ctx *ctx, const SpmvArgs &M, const Grids &g, const d
         hipLaunchKernelGGL((k_residual<TB, 1>), dim3(g.slice_blocks), dim3(256), 0, s, M, b, x, ctx->r, ctx->p,
                            ctx->dinv, ctx->partials);
         hipLaunchKernelGGL(k_fin_check, dim3(1), dim3(1024), 0, s, ctx->partials, g.slice_blocks, out2);
+    }
+}
+
+// Capture `chunk` iterations on the context's capture stream.
+template <typename TB>
+static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Grids &g, int chunk, int variant) {
+    if (!ctx->cap_stream) PC_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    if (!ctx->gev[variant][0])
+        for (int k = 0; k < 6; ++k) PC_HIP(hipEventCreate(&ctx->gev[variant][k]));
+    if (ctx->gexec[variant]) {
+        (void)hipGraphExecDestroy(ctx->gexec[variant]);
+        ctx->gexec[variant] = nullptr;
+    }
+    hipStream_t cs = ctx->cap_stream;
+    PC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int c = 0; c < chunk; ++c) launch_iter<TB>(ctx, M, g, cs, c == 0 ? ctx->gev[variant] : nullptr);
+    hipGraph_t graph = nullptr;
+    PC_HIP(hipStreamEndCapture(cs, &graph));
+    hipError_t e = hipGraphInstantiate(&ctx->gexec[variant], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        ctx->err = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
+        ctx->gexec[variant] = nullptr;
+        return PC_ERR_HIP;
+    }
+    ctx->gkey[variant] = M.jval;
+    ctx->gkey_dtype[variant] = (int)sizeof(TB);
+    ctx->gkey_chunk[variant] = chunk;
+    return PC_OK;
+}
+
+// Add the graph's event-pair timings (first iteration of the chunk) to the
+// profiler statistics; call after the stream has been synchronised.
+static void harvest_graph_events(Ctx *ctx, int variant) {
+    if (ctx->prof.every <= 0) return;
+    const int kinds[3] = {PK_SPMV, PK_UPDATE, PK_DIR};
+    for (int q = 0; q < 3; ++q) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ctx->gev[variant][2 * q], ctx->gev[variant][2 * q + 1]) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        Prof &P = ctx->prof;
+        const int k = kinds[q];
+        if (P.count[k] == 0 || ms < P.min_ms[k]) P.min_ms[k] = ms;
+        if (P.count[k] == 0 || ms > P.max_ms[k]) P.max_ms[k] = ms;
+        P.sum_ms[k] += ms;
+        P.count[k] += 1;
     }
 }
 
@@ -536,19 +619,38 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
         PC_HIP(hipStreamSynchronize(s));
         h = *ctx->st_host;
         ++sweeps;
+        const int variant = inner_hi ? 1 : 0;
+        const bool graph = ctx->graph_chunk > 0;
+        if (graph) {
+            const SpmvArgs &Mv = inner_hi ? Mhi : M;
+            const int want_size = inner_hi ? (int)sizeof(double) : (int)sizeof(TB);
+            if (!ctx->gexec[variant] || ctx->gkey[variant] != Mv.jval || ctx->gkey_dtype[variant] != want_size ||
+                ctx->gkey_chunk[variant] != ctx->graph_chunk) {
+                pc_status cst = inner_hi ? capture_chunk<double>(ctx, Mhi, g, ctx->graph_chunk, variant)
+                                         : capture_chunk<TB>(ctx, M, g, ctx->graph_chunk, variant);
+                if (cst) return cst;
+            }
+        }
         while (!h.done && h.iters < h.maxit) {
-            int chunk = check > 0 ? check : std::min(256, std::max(16, (total_iters + h.iters) / 4));
-            chunk = std::min(chunk, h.maxit - h.iters);
-            for (int c = 0; c < chunk; ++c) {
-                if (inner_hi)
-                    launch_iter<double>(ctx, Mhi, g, s);
-                else
-                    launch_iter<TB>(ctx, M, g, s);
+            if (graph) {
+                PC_HIP(hipGraphLaunch(ctx->gexec[variant], s));
+            } else {
+                int chunk = check > 0 ? check : std::min(256, std::max(16, (total_iters + h.iters) / 4));
+                chunk = std::min(chunk, h.maxit - h.iters);
+                for (int c = 0; c < chunk; ++c) {
+                    if (inner_hi)
+                        launch_iter<double>(ctx, Mhi, g, s);
+                    else
+                        launch_iter<TB>(ctx, M, g, s);
+                }
             }
             PC_HIP(hipGetLastError());
             PC_HIP(hipMemcpyAsync(ctx->st_host, ctx->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
             PC_HIP(hipStreamSynchronize(s));
-            ctx->prof.harvest();
+            if (graph)
+                harvest_graph_events(ctx, variant);
+            else
+                ctx->prof.harvest();
             h = *ctx->st_host;
         }
         total_iters += h.iters;

@@ -144,6 +144,30 @@ def test_solve_deterministic(torch, B):
         ctx.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_graph_replay_matches_plain_launches(torch, B, dtype):
+    """Iterations replayed from a captured HIP graph give the same iterate,
+    bit for bit, as plain launches (same kernels, same order), on several
+    solves in a row with eager work between the replays."""
+    c = sheet(40, 40, seed=13, flips=0.1)
+    ctx = B.Context.from_cloth(c)
+    try:
+        x, v = to_dev(torch, c.x0), to_dev(torch, random_velocity(c))
+        b = ctx.cloth_assemble(x, v, dtype)
+        ref, rinfo = ctx.cloth_pcg_solve(b, tol=1e-7)
+        ref = ref.cpu().numpy().copy()
+        ctx.set_option(B.PC_OPT_GRAPH_CHUNK, 24)
+        for rep in range(3):
+            b2 = ctx.cloth_assemble(x, v, dtype)
+            dv, info = ctx.cloth_pcg_solve(b2, tol=1e-7)
+            _ = (b2 * 2.0).sum().item()   # eager torch work between replays
+            assert info["iters"] == rinfo["iters"]
+            assert np.array_equal(dv.cpu().numpy().view(np.uint64), ref.view(np.uint64))
+        ctx.set_option(B.PC_OPT_GRAPH_CHUNK, 0)
+    finally:
+        ctx.close()
+
+
 def test_steps_match_oracle_trajectory(torch, B, oracle_mod):
     c = sheet(16, 16, seed=17, flips=0.1)
     P = oracle_mod.Problem.from_cloth(c)

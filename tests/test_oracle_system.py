@@ -300,3 +300,23 @@ def test_update_and_pins(oracle_mod):
     np.testing.assert_allclose(x1, c.x0 + c.h * v1, rtol=0, atol=1e-15)
     # the cloth falls: mean z velocity is negative after one step under gravity
     assert v1[c.pinned == 0, 2].mean() < 0
+
+
+def test_linearised_rhs_is_stable_and_lookahead_is_not(oracle_mod):
+    """Reading of Eq. 3's right-hand side.  With the PSD solver Jacobian, the
+    literal lookahead force f(x + h v) feeds the negative stiffness of
+    compressed cloth explicitly and the velocity grows exponentially; the same
+    force linearised with the matrix's own Jacobian (Eq. 2 applied to the
+    right-hand side) stays bounded.  This is why rhs_mode 1 is the default."""
+    c = mg.config_grid(32, seed=2000, h=1.0 / 200)
+    growth = {}
+    for mode in (0, 1):
+        P = oracle_mod.Problem.from_cloth(c, oracle_mod.Material(rhs_mode=mode))
+        x, v = c.x0.copy(), c.v0.copy()
+        norms = []
+        for _ in range(24):
+            x, v, dv, info = P.step(x, v, tol=1e-9, maxit=100000)
+            norms.append(np.linalg.norm(v))
+        growth[mode] = norms[-1] / norms[3]
+    assert growth[1] < 5.0, growth
+    assert growth[0] > 100.0, growth
