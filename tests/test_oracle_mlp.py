@@ -1,0 +1,139 @@
+"""Pins of the learned-warm-start oracle (oracle/mlp.py): gradients against
+central finite differences, the energy loss against its closed-form minimum,
+Adam's first step against its closed form, bf16 rounding against hand-picked
+values, and the features against invariances and direct definitions."""
+import numpy as np
+import pytest
+
+from paper_2008_00409_amd import meshgen as mg
+
+
+@pytest.fixture(scope="module")
+def M():
+    from oracle import mlp
+    return mlp
+
+
+def test_bf16_rounding_closed_form(M):
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -2.5, 3.0e-3, 65504.0])
+    # 3e-3 = 1.536 * 2^-9; 1.536 * 128 = 196.6 rounds to 197; 65504 rounds up to 2^16
+    want = np.array([1.0, 1.0, 1 + 2 * 2 ** -7, -2.5, 197 / 128 * 2 ** -9, 65536.0])
+    np.testing.assert_array_equal(M.bf16_round(vals), want)
+
+
+def test_backward_matches_finite_differences(M):
+    rng = np.random.default_rng(0)
+    params = M.init_params(1)
+    params[3][0] *= 100.0            # undo the small last-layer init for a well-scaled check
+    for k in range(4):
+        params[k][1] = 0.1 * rng.normal(size=params[k][1].shape)
+    X = rng.normal(size=(7, M.IN))
+    gy = rng.normal(size=(7, M.OUT))
+    y, hs = M.forward(params, X)
+    grads = M.backward(params, X, hs, gy)
+    f = lambda p: float((M.forward(p, X)[0] * gy).sum())
+    step = 1e-6
+    for k in range(4):
+        for q in range(2):
+            arr = params[k][q]
+            for idx in [tuple(rng.integers(0, s) for s in arr.shape) for _ in range(6)]:
+                old = arr[idx]
+                arr[idx] = old + step
+                fp = f(params)
+                arr[idx] = old - step
+                fm = f(params)
+                arr[idx] = old
+                fd = (fp - fm) / (2 * step)
+                assert grads[k][q][idx] == pytest.approx(fd, rel=1e-5, abs=1e-8)
+
+
+def small_system(oracle_mod, n=6):
+    c = mg.config_grid(n, seed=31, h=0.01)
+    P = oracle_mod.Problem.from_cloth(c)
+    x = c.x0
+    v = 0.05 * np.random.default_rng(2).normal(size=x.shape)
+    v[c.pinned == 1] = 0
+    A = P.assemble(x, v)
+    return c, P, A, x, v
+
+
+def test_energy_loss_gradient_and_minimum(M, oracle_mod):
+    c, P, A, x, v = small_system(oracle_mod)
+    apply_A = lambda z: P.spmv(A, z)
+    sv = (1.0 / (6 - 1)) / c.h
+    rng = np.random.default_rng(3)
+    dv_prev = 0.01 * rng.normal(size=x.shape)
+    y = 0.001 * rng.normal(size=x.shape)
+    dv0 = M.start_from_output(y, dv_prev, c.pinned, sv)
+    L, gy = M.energy_loss_grad(apply_A, A.b, A.diag, dv0, c.pinned, sv)
+    step = 1e-7
+    for idx in [(3, 0), (10, 2), (20, 1)]:
+        yp, ym = y.copy(), y.copy()
+        yp[idx] += step
+        ym[idx] -= step
+        Lp = M.energy_loss_grad(apply_A, A.b, A.diag, M.start_from_output(yp, dv_prev, c.pinned, sv),
+                                c.pinned, sv)[0]
+        Lm = M.energy_loss_grad(apply_A, A.b, A.diag, M.start_from_output(ym, dv_prev, c.pinned, sv),
+                                c.pinned, sv)[0]
+        assert gy[idx] == pytest.approx((Lp - Lm) / (2 * step), rel=1e-5)
+    # at the exact solution the gradient vanishes and L = -0.5 b.A^-1 b / E0
+    sol = np.linalg.solve(A.dense(), A.b.ravel()).reshape(-1, 3)
+    Ls, gs = M.energy_loss_grad(apply_A, A.b, A.diag, sol, c.pinned, sv)
+    E0 = float((A.b * A.b / A.diag).sum())
+    assert Ls == pytest.approx(-0.5 * float((A.b * sol).sum()) / E0, rel=1e-10)
+    assert np.abs(gs).max() < 1e-8 * sv / E0 * np.abs(A.b).max()
+
+
+def test_adam_first_step_closed_form(M):
+    params = M.init_params(2)
+    grads = [[np.full_like(W, 0.5), np.full_like(c, -2.0)] for W, c in params]
+    before = M.flatten(params)
+    M.adam_step(params, grads, {}, lr=1e-3)
+    delta = M.flatten(params) - before
+    # first step: m_hat = g, v_hat = g^2  ->  update = -lr * g / (|g| + eps)
+    gflat = M.flatten(grads)
+    np.testing.assert_allclose(delta, -1e-3 * gflat / (np.abs(gflat) + 1e-8), rtol=1e-12)
+
+
+def test_features_definitions_and_invariance(M, oracle_mod):
+    c, P, A, x, v = small_system(oracle_mod)
+    rng = np.random.default_rng(4)
+    dvp = rng.normal(size=x.shape)
+    ell, h = 0.2, c.h
+    F = M.features(P.rowptr, P.colidx, x, v, A.b, A.diag, c.mass, c.pinned, dvp, ell, h)
+    assert F.shape == (P.nv, 27)
+    sv = ell / h
+    np.testing.assert_allclose(F[:, 0:3], v / sv)
+    np.testing.assert_allclose(F[:, 12:15], A.b / A.diag / sv)
+    np.testing.assert_array_equal(F[:, 24], c.pinned)
+    np.testing.assert_allclose(F[:, 26], (np.diff(P.rowptr) - 1) / 12.0)
+    # vertex 7's neighbour mean of dv_prev, written out from its row
+    i = 7
+    nb = [j for j in P.colidx[P.rowptr[i]:P.rowptr[i + 1]] if j != i]
+    np.testing.assert_allclose(F[i, 9:12], dvp[nb].mean(axis=0) / sv)
+    # curvature feature is translation invariant; velocity features are linear
+    F2 = M.features(P.rowptr, P.colidx, x + 3.0, v, A.b, A.diag, c.mass, c.pinned, dvp, ell, h)
+    np.testing.assert_allclose(F2[:, 21:24], F[:, 21:24], atol=1e-12)
+    F3 = M.features(P.rowptr, P.colidx, x, 2 * v, A.b, A.diag, c.mass, c.pinned, 2 * dvp, ell, h)
+    np.testing.assert_allclose(F3[:, 0:3], 2 * F[:, 0:3])
+    np.testing.assert_allclose(F3[:, 18:21], 2 * F[:, 18:21])
+
+
+def test_energy_training_reduces_the_loss(M, oracle_mod):
+    """Full-batch training on one small system lowers the energy loss of the
+    start (the network can only improve on the previous-step start)."""
+    c, P, A, x, v = small_system(oracle_mod, n=8)
+    apply_A = lambda z: P.spmv(A, z)
+    sv = (1.0 / 7) / c.h
+    dvp = np.zeros_like(x)
+    X = M.features(P.rowptr, P.colidx, x, v, A.b, A.diag, c.mass, c.pinned, dvp, 1.0 / 7, c.h)
+    params = M.init_params(5)
+    state = {}
+    losses = []
+    for it in range(200):
+        y, hs = M.forward(params, X)
+        dv0 = M.start_from_output(y, dvp, c.pinned, sv)
+        L, gy = M.energy_loss_grad(apply_A, A.b, A.diag, dv0, c.pinned, sv)
+        losses.append(L)
+        M.adam_step(params, M.backward(params, X, hs, gy), state, lr=3e-3)
+    assert losses[-1] < losses[0] - 0.1 * abs(losses[0])
