@@ -75,17 +75,75 @@ def cpu_baseline(cloth, gpu_iters_per_step, seconds_budget=25.0):
                        f"same tolerance")}
 
 
+def time_steps(ctx, x, v, steps, warmup, blocks, tol, warm, prof_every):
+    """Run warmup then timed steps; returns (elapsed s, infos, profile)."""
+    import torch
+    if warmup:
+        ctx.cloth_step(x, v, nsteps=warmup, dtype=blocks, tol=tol, warm=warm)
+    ctx.profile(prof_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = ctx.cloth_step(x, v, nsteps=steps, dtype=blocks, tol=tol, warm=warm)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = ctx.profile_read()
+    ctx.profile(0)
+    return elapsed, infos, prof
+
+
+def train_warm_start(binding, meshgen, steps, adam_per_step, lr, log):
+    """Online training of the warm-start network on the 512 x 512 workload's
+    own trajectory: at every step the current system is assembled, the
+    network takes `adam_per_step` Adam steps on its energy loss, and the
+    solver advances with the learned start."""
+    import torch
+
+    from oracle import mlp as oracle_mlp  # only its seeded initial weights (init_params)
+    c = meshgen.config_medium()
+    ctx = binding.Context.from_cloth(c)
+    ctx.ws_set_params(oracle_mlp.flatten(oracle_mlp.init_params(0)))
+    x = torch.from_numpy(c.x0.copy()).cuda()
+    v = torch.zeros_like(x)
+    dvp = torch.zeros_like(x)
+    pin = torch.from_numpy(c.pinned.astype(bool)).cuda()
+    x_pin = x[pin].clone()
+    losses = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        b = ctx.cloth_assemble(x, v, "f32")
+        for it in range(adam_per_step):
+            L = ctx.ws_train_step(x, v, b, dvp, lr=lr, want_loss=(it == adam_per_step - 1))
+        losses.append(L)
+        dv, info = ctx.cloth_pcg_solve(b, dv=dvp.clone(), tol=c.tol, warm="learned")
+        v += dv
+        v[pin] = 0
+        x += c.h * v
+        x[pin] = x_pin
+        dvp = dv
+        if k % 10 == 0:
+            log(f"# train step {k}: loss {L:.4f}, iters {info['iters']}, start {info['warm_used']}")
+    params = ctx.ws_get_params()
+    ctx.close()
+    return params, {"steps": steps, "adam_per_step": adam_per_step, "lr": lr,
+                    "loss_first": losses[0], "loss_last": losses[-1], "seconds": time.perf_counter() - t0,
+                    "workload": c.name}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--blocks", default="f32", choices=["f32", "bf16", "f64"])
+    ap.add_argument("--blocks", default="bf16", choices=["f32", "bf16", "f64"],
+                    help="block storage of the project configuration")
+    ap.add_argument("--warm", default="learned", choices=["zero", "prev", "learned"],
+                    help="CG start of the project configuration")
     ap.add_argument("--workload", default="large", choices=["large", "medium"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 / zero-start reference run")
     ap.add_argument("--prof-every", type=int, default=8)
-    ap.add_argument("--graph", type=int, default=0, help="CG iterations per captured HIP graph (0: off)")
-    ap.add_argument("--warm", action="store_true", help="previous-step dv as the CG start")
+    ap.add_argument("--train-steps", type=int, default=30)
+    ap.add_argument("--autotune", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the whole 1.65M-triangle workload fits in one MI355X "
@@ -96,33 +154,65 @@ def main():
 
     from paper_2008_00409_amd import binding, meshgen
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t0 = time.perf_counter()
     cloth = meshgen.config_large() if args.workload == "large" else meshgen.config_medium()
-    print(f"# workload {cloth.name}: nv={cloth.nv} nt={cloth.nt} ({time.perf_counter() - t0:.1f} s)",
-          file=sys.stderr, flush=True)
+    log(f"# workload {cloth.name}: nv={cloth.nv} nt={cloth.nt} ({time.perf_counter() - t0:.1f} s)")
+    tol = cloth.tol
+    rec_plain = None
+    if not args.no_plain:
+        ctx = binding.Context.from_cloth(cloth)
+        x = torch.from_numpy(cloth.x0.copy()).cuda()
+        v = torch.from_numpy(cloth.v0.copy()).cuda()
+        el, infos, prof = time_steps(ctx, x, v, args.steps, args.warmup, "f32", tol, "zero", args.prof_every)
+        rowptr, colidx = ctx.pattern()
+        nnzb = int(colidx.numel())
+        sp = prof.get("spmv", {}).get("mean_ms", float("nan"))
+        rec_plain = {"steps_per_s": args.steps / el, "block_storage": "f32", "warm_start": "zero",
+                     "cg_iters_per_step": [i["iters"] for i in infos],
+                     "rel_res_true_max": max(i["rel_res_true"] for i in infos),
+                     "spmv_mean_ms": sp, "spmv_GBs": spmv_bytes(ctx.nv, nnzb, "f32") / (sp * 1e-3) / 1e9}
+        log(f"# plain: {rec_plain['steps_per_s']:.3f} steps/s, iters {rec_plain['cg_iters_per_step']}")
+        ctx.close()
+        del x, v
+    train_info = None
+    params = None
+    if args.warm == "learned":
+        params, train_info = train_warm_start(binding, meshgen, args.train_steps, 3, 1e-3, log)
     ctx = binding.Context.from_cloth(cloth)
-    if args.graph:
-        ctx.set_option(binding.PC_OPT_GRAPH_CHUNK, args.graph)
+    if params is not None:
+        ctx.ws_set_params(params)
     x = torch.from_numpy(cloth.x0.copy()).cuda()
     v = torch.from_numpy(cloth.v0.copy()).cuda()
-    tol = cloth.tol
-    warm_infos = (ctx.cloth_step(x, v, nsteps=args.warmup, dtype=args.blocks, tol=tol, warm=args.warm)
-                  if args.warmup else [])
-    print(f"# warmup done: iters {[i['iters'] for i in warm_infos]}", file=sys.stderr, flush=True)
-    ctx.profile(args.prof_every)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = ctx.cloth_step(x, v, nsteps=args.steps, dtype=args.blocks, tol=tol, warm=args.warm)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = ctx.profile_read()
+    tune = None
+    if args.autotune:
+        b = ctx.cloth_assemble(x, v, args.blocks)
+        tune = ctx.autotune(b, iters=64)
+        log(f"# autotune: {tune}")
+    el, infos, prof = time_steps(ctx, x, v, args.steps, args.warmup, args.blocks, tol, args.warm, args.prof_every)
     rowptr, colidx = ctx.pattern()
     nnzb = int(colidx.numel())
     nv, nt, nh = ctx.nv, ctx.nt, ctx.nh
     iters = [i["iters"] for i in infos]
-    print(f"# timed: {args.steps} steps in {elapsed:.3f} s, iters {iters}, "
-          f"true residuals {[float('%.2e' % i['rel_res_true']) for i in infos]}", file=sys.stderr, flush=True)
+    log(f"# timed: {args.steps} steps in {el:.3f} s, iters {iters}, sweeps {[i['sweeps'] for i in infos]}, "
+        f"starts {[i['warm_used'] for i in infos]}, true residuals {[float('%.2e' % i['rel_res_true']) for i in infos]}")
+    # paired comparison of the starts on one further system of the same
+    # trajectory: one more step gives the previous increment, then the next
+    # system is solved from each start to the same tolerance
+    v_before = v.clone()
+    ctx.cloth_step(x, v, nsteps=1, dtype=args.blocks, tol=tol, warm=args.warm)
+    dv_prev = v - v_before
+    b = ctx.cloth_assemble(x, v, args.blocks)
+    paired = {}
+    for mode in (["zero", "prev"] + (["learned"] if params is not None else [])):
+        dv0 = torch.zeros_like(x) if mode == "zero" else dv_prev.clone()
+        _, pinfo = ctx.cloth_pcg_solve(b, dv=dv0, tol=tol, warm=mode)
+        paired[mode] = {"iters": pinfo["iters"], "start_used": pinfo["warm_used"],
+                        "rel_res_true": pinfo["rel_res_true"]}
+    log(f"# paired starts on one system: {paired}")
     spmv = prof.get("spmv", {})
     spmv_ms = spmv.get("mean_ms", float("nan"))
     ach = spmv_bytes(nv, nnzb, args.blocks) / (spmv_ms * 1e-3) / 1e9 if spmv_ms == spmv_ms else None
@@ -130,12 +220,12 @@ def main():
     asm_ms = asm.get("mean_ms", float("nan"))
     rec = {
         "metric": "implicit steps/s + CG iters to 1e-6 residual @1.65M tris, learned vs plain",
-        "value": args.steps / elapsed,
+        "value": args.steps / el,
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * el / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -143,13 +233,17 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{cloth.name}: {nt} triangles, {nv} vertices, {nh} hinges, nnzb {nnzb}",
-            "h": cloth.h, "tol": tol, "block_storage": args.blocks,
-            "warm_start": "previous-step" if args.warm else "zero", "graph_chunk": args.graph,
-            "refinement_sweeps": [i["sweeps"] for i in infos],
+            "h": cloth.h, "tol": tol, "block_storage": args.blocks, "warm_start": args.warm,
+            "refinement_sweeps": [i["sweeps"] for i in infos], "starts_used": [i["warm_used"] for i in infos],
             "preconditioner": "jacobi", "cg_iters_per_step": {"mean": float(np.mean(iters)),
                                                                "min": int(min(iters)), "max": int(max(iters))},
             "rel_res_true_max": max(i["rel_res_true"] for i in infos),
+            "schedule": tune,
         },
+        "plain": rec_plain,
+        "paired_starts": paired,
+        "speedup_vs_plain": (args.steps / el) / rec_plain["steps_per_s"] if rec_plain else None,
+        "training": train_info,
         "roofline": {
             "bound": "hbm", "kernel": f"k_pcg_spmv<{args.blocks}>",
             "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -170,7 +264,7 @@ def main():
         rec["cg_vector_GBs"] = cg_vector_bytes(nv) / (cg * 1e-3) / 1e9
     ctx.close()
     if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle)...", file=sys.stderr, flush=True)
+        log("# cpu baseline (oracle)...")
         rec["cpu_baseline"] = cpu_baseline(cloth, float(np.mean(iters)))
     print(json.dumps(rec), flush=True)
 

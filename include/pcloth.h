@@ -97,7 +97,10 @@ typedef struct {
                               this factor (or reached tol); 0: default (BF16 blocks 1e-2,
                               FP32/FP64 blocks: run each sweep to tol) */
     int32_t maxit;         /* total CG iterations over all sweeps; default 20000 when <= 0 */
-    int32_t warm;          /* 0: zero start, 1: caller's dv as start */
+    int32_t warm;          /* 0: zero start, 1: caller's dv as start, 2: learned start predicted
+                              from the caller's dv taken as the previous step's increment
+                              (needs pc_ws_set_params); a start whose residual exceeds ||b||
+                              is replaced by the zero start */
     int32_t check_every;   /* iterations between host convergence checks (0: auto) */
     int32_t max_sweeps;    /* refinement sweeps; 0: default (BF16 40, otherwise 4) */
 } pc_solve_opts;
@@ -110,7 +113,7 @@ typedef struct {
     double bnorm;              /* ||b||_2 */
     int32_t fallback;          /* 1 if the inner CG switched to the FP64 blocks after a
                                   breakdown on the low-precision copy */
-    int32_t reserved;
+    int32_t warm_used;         /* start actually used: 0 zero, 1 given / previous, 2 learned */
 } pc_solve_info;
 
 /* Create a context: copies the mesh to the device, derives the rest shape
@@ -195,13 +198,77 @@ pc_status cloth_export_pattern(pc_ctx *ctx, int32_t *rowptr_out, int32_t *colidx
 pc_status pc_profile(pc_ctx *ctx, int32_t every);
 pc_status pc_profile_read(pc_ctx *ctx, double *out);
 
-/* Context options.
+/* ---- Learned warm start (project addition to the paper's method) ----
+ * A per-vertex MLP (27 features -> 64 -> 64 -> 64 -> 3, ReLU) predicts a
+ * correction to the previous step's increment: dv0 = dv_prev + s_v y on free
+ * vertices (s_v = mean rest edge length / h), used as the CG start of Eq. 3
+ * after scaling by c = dv0.b / dv0.A dv0.  Features of vertex i (N(i): block
+ * columns of row i other than i): v/s_v, (b/m)/s_v, dv_prev/s_v, mean_N dv_prev/s_v,
+ * (b/diag A)/s_v, (mean_N b/m - b_i/m_i)/s_v, (mean_N v - v_i)/s_v,
+ * (mean_N x - x_i)/l, pinned, log10(mean diag A_i / m_i), |N(i)|/12.
+ * It runs on BF16 matrix cores with FP32 accumulation and is trained with
+ * the energy loss L = (dv0.A dv0 / 2 - b.dv0) / (b.D^-1 b), whose gradient is
+ * the residual of the start.  Parameters cross the ABI as PC_WS_PARAMS host
+ * floats: per layer the weights [in][out] row-major, then the biases.
+ * All calls use the most recent cloth_assemble of the context. */
+#define PC_WS_PARAMS 10307
+pc_status pc_ws_set_params(pc_ctx *ctx, const float *params_host, int32_t n);
+pc_status pc_ws_get_params(pc_ctx *ctx, float *params_host, int32_t n);
+/* Features as BF16 bits (device nv*32 uint16, features 27..31 zero). */
+pc_status pc_ws_features(pc_ctx *ctx, const double *x, const double *v, const double *b, const double *dv_prev,
+                         uint16_t *feat_out, void *stream);
+/* Unscaled prediction dv0 = dv_prev + s_v y (device nv*3 doubles). */
+pc_status pc_ws_predict(pc_ctx *ctx, const double *x, const double *v, const double *b, const double *dv_prev,
+                        double *dv0_out, void *stream);
+/* Loss and its gradient with respect to the parameters (host floats, same
+ * layout as the parameters); no update.  Synchronises the stream. */
+pc_status pc_ws_gradient(pc_ctx *ctx, const double *x, const double *v, const double *b, const double *dv_prev,
+                         float *grad_host, double *loss_host, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, FP32 master weights) on
+ * the loss of the assembled system.  loss_host (optional) synchronises. */
+pc_status pc_ws_train_step(pc_ctx *ctx, const double *x, const double *v, const double *b, const double *dv_prev,
+                           double lr, double *loss_host, void *stream);
+/* Matrix-core lane-layout self test: D = A*B for two known 16x16 BF16 pairs
+ * (A[i][k] = 16i+k, B = I; then A = I, B[k][j] = 16k+j); out_host receives
+ * the two 16x16 FP32 results, row-major (512 floats). */
+pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
+
+/* Context options (launch schedule; results do not depend on them).
  * PC_OPT_GRAPH_CHUNK: when > 0, CG iterations are captured once into a HIP
- *   graph of that many iterations and replayed (the convergence flag makes
- *   iterations after convergence exit at once); event nodes around the first
- *   iteration of each replay feed pc_profile.  0 (default): plain launches. */
-typedef enum { PC_OPT_GRAPH_CHUNK = 0 } pc_option;
+ *   graph of that many iterations and replayed on the caller's stream; the
+ *   per-instance convergence flags make iterations after convergence exit at
+ *   once.  0 (default): plain launches.  pc_profile timings come from plain
+ *   launches only.
+ * PC_OPT_SPMV_SLICES_PER_BLOCK: 64-row slices per SpMV work item / block
+ *   (1, 2, 4 (default) or 8).
+ * PC_OPT_VECTOR_ROWS_PER_BLOCK: rows per work item of the CG vector kernels
+ *   (multiple of 64, default 256). */
+typedef enum { PC_OPT_GRAPH_CHUNK = 0, PC_OPT_SPMV_SLICES_PER_BLOCK = 1, PC_OPT_VECTOR_ROWS_PER_BLOCK = 2 } pc_option;
 pc_status pc_set_option(pc_ctx *ctx, int32_t option, int64_t value);
+pc_status pc_get_option(pc_ctx *ctx, int32_t option, int64_t *value);
+
+/* Autotuner: on the assembled system and right-hand side b (device nv*3),
+ * time `iters` CG iterations for every candidate schedule (slices per SpMV
+ * block 1/2/4/8 x rows per vector block 256/512/1024 x graph chunk 0/32)
+ * with HIP events on the stream, and keep the fastest.  chosen (host,
+ * optional) receives {slices per block, rows per block, graph chunk};
+ * ms_per_iter (host, optional) the best time per iteration.  Overwrites the
+ * solver's work vectors (not dv, not b).  Synchronises the stream. */
+pc_status pc_autotune(pc_ctx *ctx, const double *b, int32_t iters, int64_t *chosen, double *ms_per_iter,
+                      void *stream);
+
+/* ---- Many independent cloths in one context (project addition) ----
+ * The mesh given to pc_create is the concatenation of ninst cloths occupying
+ * the vertex ranges [vertex_begin[i], vertex_begin[i+1]) (host, ninst+1
+ * entries, vertex_begin[0] = 0, vertex_begin[ninst] = nv); no triangle may
+ * join two ranges (PC_ERR_MESH).  Each instance then gets its own CG scalars,
+ * convergence test and refinement sweeps, while every kernel launch covers all
+ * instances (instances that have converged skip their work).  Call before
+ * cloth_assemble.  After a solve, pc_get_instance_info copies the per-instance
+ * results (host array of ninst); the pc_solve_info of cloth_pcg_solve /
+ * cloth_step then holds the largest iteration count and residuals. */
+pc_status pc_set_instances(pc_ctx *ctx, const int32_t *vertex_begin, int32_t ninst);
+pc_status pc_get_instance_info(pc_ctx *ctx, pc_solve_info *infos, int32_t n);
 
 /* Synchronise the stream and report device-side errors of earlier calls. */
 pc_status pc_check(pc_ctx *ctx, void *stream);

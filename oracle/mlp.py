@@ -122,7 +122,7 @@ def backward(params, X, hs, gy, bf16=False):
     r = bf16_round if bf16 else (lambda a: a)
     inputs = [r(X)] + hs
     grads = [None] * 4
-    g = gy
+    g = r(gy)
     for k in range(3, -1, -1):
         W, c = params[k]
         grads[k] = [inputs[k].T @ g, g.sum(axis=0)]

@@ -25,8 +25,13 @@ DTYPES = {"f64": PC_F64, "f32": PC_F32, "bf16": PC_BF16}
 # Names of every entry point declared in include/pcloth.h.
 ABI_SYMBOLS = ["pc_create", "pc_destroy", "pc_set_params", "pc_last_error", "pc_sizes", "pc_get_hinges",
                "cloth_assemble", "cloth_pcg_solve", "cloth_step", "cloth_spmv", "cloth_export_blocks",
-               "cloth_export_pattern", "pc_check", "pc_profile", "pc_profile_read", "pc_set_option"]
-PC_OPT_GRAPH_CHUNK = 0
+               "cloth_export_pattern", "pc_check", "pc_profile", "pc_profile_read", "pc_set_option",
+               "pc_ws_set_params", "pc_ws_get_params", "pc_ws_features", "pc_ws_predict", "pc_ws_gradient",
+               "pc_ws_train_step", "pc_mfma_probe", "pc_get_option", "pc_set_instances", "pc_get_instance_info",
+               "pc_autotune"]
+WS_PARAMS = 10307
+WARM = {"zero": 0, "prev": 1, "given": 1, "learned": 2}
+PC_OPT_GRAPH_CHUNK, PC_OPT_SPMV_SLICES_PER_BLOCK, PC_OPT_VECTOR_ROWS_PER_BLOCK = 0, 1, 2
 PROFILE_KINDS = ["spmv", "cg_update", "cg_dir", "row_assemble", "row_pattern", "assemble_all", "k6", "k7"]
 
 
@@ -53,18 +58,19 @@ class PcSolveOpts(ctypes.Structure):
 
 
 def solve_opts(tol=1e-6, maxit=20000, warm=False, check_every=0, inner_rho=0.0, max_sweeps=0):
-    return PcSolveOpts(float(tol), float(inner_rho), int(maxit), int(bool(warm)), int(check_every),
-                       int(max_sweeps))
+    w = WARM[warm] if isinstance(warm, str) else int(warm)
+    return PcSolveOpts(float(tol), float(inner_rho), int(maxit), w, int(check_every), int(max_sweeps))
 
 
 class PcSolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("rel_res_recursive", ctypes.c_double),
                 ("rel_res_true", ctypes.c_double), ("bnorm", ctypes.c_double), ("fallback", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("warm_used", ctypes.c_int32)]
 
     def as_dict(self):
         return {"iters": self.iters, "sweeps": self.sweeps, "rel_res_recursive": self.rel_res_recursive,
-                "rel_res_true": self.rel_res_true, "bnorm": self.bnorm, "fallback": self.fallback}
+                "rel_res_true": self.rel_res_true, "bnorm": self.bnorm, "fallback": self.fallback,
+                "warm_used": self.warm_used}
 
 
 _lib = None
@@ -95,6 +101,18 @@ def lib():
         L.cloth_export_pattern.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
         L.pc_profile.argtypes = [vp, ctypes.c_int32]
         L.pc_set_option.argtypes = [vp, ctypes.c_int32, ctypes.c_int64]
+        L.pc_ws_set_params.argtypes = [vp, vp, ctypes.c_int32]
+        L.pc_ws_get_params.argtypes = [vp, vp, ctypes.c_int32]
+        L.pc_ws_features.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.pc_ws_predict.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.pc_ws_gradient.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+        L.pc_ws_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
+        L.pc_mfma_probe.argtypes = [vp, vp]
+        L.pc_get_option.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+        L.pc_set_instances.argtypes = [vp, vp, ctypes.c_int32]
+        L.pc_get_instance_info.argtypes = [vp, ctypes.POINTER(PcSolveInfo), ctypes.c_int32]
+        L.pc_autotune.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_double), vp]
         L.pc_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         for name in ABI_SYMBOLS:
             if name not in ("pc_last_error",):
@@ -260,8 +278,101 @@ class Context:
         self._check(st)
         return [infos[k].as_dict() for k in range(nsteps)]
 
+    # -- learned warm start --------------------------------------------------
+    def ws_set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        assert a.size == WS_PARAMS
+        self._check(lib().pc_ws_set_params(self.h, a.ctypes.data_as(ctypes.c_void_p), WS_PARAMS))
+
+    def ws_get_params(self):
+        a = np.zeros(WS_PARAMS, dtype=np.float32)
+        self._check(lib().pc_ws_get_params(self.h, a.ctypes.data_as(ctypes.c_void_p), WS_PARAMS))
+        return a
+
+    def ws_features(self, x, v, b, dv_prev):
+        import torch
+        out = torch.empty((self.nv, 32), dtype=torch.int16, device="cuda")
+        self._check(lib().pc_ws_features(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"),
+                                         _dev3(b, self.nv, "b"), _dev3(dv_prev, self.nv, "dv_prev"), _ptr(out),
+                                         _stream()))
+        return out
+
+    def ws_predict(self, x, v, b, dv_prev):
+        import torch
+        out = torch.empty((self.nv, 3), dtype=torch.float64, device="cuda")
+        self._check(lib().pc_ws_predict(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"),
+                                        _dev3(b, self.nv, "b"), _dev3(dv_prev, self.nv, "dv_prev"), _ptr(out),
+                                        _stream()))
+        return out
+
+    def ws_gradient(self, x, v, b, dv_prev):
+        g = np.zeros(WS_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(lib().pc_ws_gradient(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"),
+                                         _dev3(b, self.nv, "b"), _dev3(dv_prev, self.nv, "dv_prev"),
+                                         g.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss), _stream()))
+        return g, loss.value
+
+    def ws_train_step(self, x, v, b, dv_prev, lr=1e-3, want_loss=True):
+        loss = ctypes.c_double()
+        self._check(lib().pc_ws_train_step(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"),
+                                           _dev3(b, self.nv, "b"), _dev3(dv_prev, self.nv, "dv_prev"),
+                                           float(lr), ctypes.byref(loss) if want_loss else None, _stream()))
+        return loss.value if want_loss else None
+
+    def mfma_probe(self):
+        out = np.zeros(512, dtype=np.float32)
+        self._check(lib().pc_mfma_probe(self.h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out.reshape(2, 16, 16)
+
     def set_option(self, option, value):
         self._check(lib().pc_set_option(self.h, int(option), int(value)))
+
+    def get_option(self, option):
+        v = ctypes.c_int64()
+        self._check(lib().pc_get_option(self.h, int(option), ctypes.byref(v)))
+        return v.value
+
+    def set_instances(self, vertex_begin):
+        a = np.ascontiguousarray(vertex_begin, dtype=np.int32)
+        self._check(lib().pc_set_instances(self.h, a.ctypes.data_as(ctypes.c_void_p), a.size - 1))
+        self.ninst = a.size - 1
+
+    def autotune(self, b, iters=64, cache=None, key=None):
+        """Pick the fastest launch schedule for the assembled system (see
+        pc_autotune).  With a cache path and key, a previous choice is reused
+        and new choices are stored (JSON)."""
+        import json
+        if cache and key and os.path.exists(cache):
+            with open(cache) as fh:
+                known = json.load(fh)
+            if key in known:
+                spb, rpb, chunk = known[key]["choice"]
+                self.set_option(PC_OPT_SPMV_SLICES_PER_BLOCK, spb)
+                self.set_option(PC_OPT_VECTOR_ROWS_PER_BLOCK, rpb)
+                self.set_option(PC_OPT_GRAPH_CHUNK, chunk)
+                return {"choice": [spb, rpb, chunk], "ms_per_iter": known[key]["ms_per_iter"], "cached": True}
+        chosen = (ctypes.c_int64 * 3)()
+        ms = ctypes.c_double()
+        self._check(lib().pc_autotune(self.h, _dev3(b, self.nv, "b"), int(iters), chosen, ctypes.byref(ms),
+                                      _stream()))
+        res = {"choice": [chosen[0], chosen[1], chosen[2]], "ms_per_iter": ms.value, "cached": False}
+        if cache and key:
+            known = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    known = json.load(fh)
+            known[key] = {"choice": res["choice"], "ms_per_iter": res["ms_per_iter"]}
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as fh:
+                json.dump(known, fh, indent=1)
+        return res
+
+    def instance_info(self):
+        n = getattr(self, "ninst", 1)
+        arr = (PcSolveInfo * n)()
+        self._check(lib().pc_get_instance_info(self.h, arr, n))
+        return [arr[i].as_dict() for i in range(n)]
 
     def profile(self, every):
         self._check(lib().pc_profile(self.h, int(every)))

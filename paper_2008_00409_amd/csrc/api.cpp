@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "pc_ctx.h"
+#include "pc_mlp.h"
 
 using namespace pc;
 
@@ -65,10 +65,12 @@ static void free_all(Ctx *c) {
     void *ptrs[] = {c->tri, c->Bm, c->A0, c->hinge, c->hcoef, c->htbar, c->mass, c->pinned, c->status,
                     c->inc_cnt, c->inc_ptr, c->inc, c->rowlen, c->rowptr, c->colidx, c->jcol, c->lane_row,
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->x, c->r, c->q, c->tmp, c->bbuf,
-                    c->p, c->partials, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi};
+                    c->p, c->partials, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0,
+                    c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (c->st_host) (void)hipHostFree(c->st_host);
+    if (c->restart_h) (void)hipHostFree(c->restart_h);
     if (c->status_host) (void)hipHostFree(c->status_host);
 }
 
@@ -143,6 +145,17 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
             return fail(PC_ERR_HIP);
         }
     }
+    {
+        double sum = 0.0;
+        for (int t = 0; t < nt; ++t)
+            for (int k = 0; k < 3; ++k) {
+                const double *a = mesh->rest + 3 * (size_t)mesh->tris[3 * (size_t)t + k];
+                const double *b = mesh->rest + 3 * (size_t)mesh->tris[3 * (size_t)t + (k + 1) % 3];
+                sum += std::sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) +
+                                 (a[2] - b[2]) * (a[2] - b[2]));
+            }
+        ctx->ell = sum / (3.0 * nt);
+    }
     if ((st = topo_build(ctx, mesh, s))) return fail(st);
     const int nh = ctx->nh;
     ctx->ninc = 3 * (int64_t)nt + 4 * (int64_t)nh;
@@ -159,9 +172,7 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
     ALLOC(ctx->rowptr, sizeof(int) * (size_t)(nv + 1));
     ALLOC(ctx->colidx, sizeof(int) * (size_t)ctx->cap);
     ALLOC(ctx->jcol, sizeof(int) * (size_t)ctx->cap);
-    ALLOC(ctx->lane_row, sizeof(int) * nsl * WAVE);
     ALLOC(ctx->row_lane, sizeof(int) * (size_t)nv);
-    ALLOC(ctx->slot_cnt, nsl * WAVE);
     ALLOC(ctx->diag, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->dinv, sizeof(float) * 3 * (size_t)nv);
     ALLOC(ctx->x, sizeof(double) * 3 * (size_t)nv);
@@ -169,19 +180,16 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
     ALLOC(ctx->q, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->bbuf, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->p, sizeof(float4) * (size_t)nv);
-    {
-        const size_t nblk = (size_t)(nv / 256 + 16) + nsl / 4 + 16;
-        ALLOC(ctx->partials, sizeof(double) * 4 * nblk);
-    }
-    ALLOC(ctx->res2, sizeof(double) * 2);
     ALLOC(ctx->counter, sizeof(unsigned) * 4);
-    ALLOC(ctx->st, sizeof(PcgState));
 #undef ALLOC
-    if (hipHostMalloc((void **)&ctx->st_host, sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->status_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    (void)nsl;
+    if (hipHostMalloc((void **)&ctx->status_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
         ctx->err = "pinned host allocation failed";
         return fail(PC_ERR_OOM);
     }
+    ctx->inst_row0_h = {0, nv};
+    ctx->ninst = 0;  // forces the per-instance buffers to be allocated
+    if ((st = build_schedule(ctx))) return fail(st);
     if (hipMemset(ctx->counter, 0, sizeof(unsigned) * 4) != hipSuccess ||
         hipMemset(ctx->tmp, 0, sizeof(double) * 3 * (size_t)nv) != hipSuccess ||
         hipMemset(ctx->p, 0, sizeof(float4) * (size_t)nv) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
@@ -229,21 +237,178 @@ pc_status pc_set_option(pc_ctx *h, int32_t option, int64_t value) {
             }
             ctx->graph_chunk = (int)value;
             return PC_OK;
+        case PC_OPT_SPMV_SLICES_PER_BLOCK: {
+            if (value != 1 && value != 2 && value != 4 && value != 8) {
+                ctx->err = "slices per block must be 1, 2, 4 or 8";
+                return PC_ERR_ARG;
+            }
+            const bool was = ctx->assembled;
+            ctx->spb = (int)value;
+            pc_status st = build_schedule(ctx);
+            ctx->assembled = was;  // the slices themselves are unchanged
+            return st;
+        }
+        case PC_OPT_VECTOR_ROWS_PER_BLOCK: {
+            if (value < 64 || value > 4096 || (value % 64)) {
+                ctx->err = "rows per block must be a multiple of 64 in [64, 4096]";
+                return PC_ERR_ARG;
+            }
+            const bool was = ctx->assembled;
+            ctx->rpb = (int)value;
+            pc_status st = build_schedule(ctx);
+            ctx->assembled = was;
+            return st;
+        }
         default:
             ctx->err = "unknown option";
             return PC_ERR_ARG;
     }
 }
 
+pc_status pc_get_option(pc_ctx *h, int32_t option, int64_t *value) {
+    if (!h || !value) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    switch (option) {
+        case PC_OPT_GRAPH_CHUNK: *value = ctx->graph_chunk; return PC_OK;
+        case PC_OPT_SPMV_SLICES_PER_BLOCK: *value = ctx->spb; return PC_OK;
+        case PC_OPT_VECTOR_ROWS_PER_BLOCK: *value = ctx->rpb; return PC_OK;
+        default: ctx->err = "unknown option"; return PC_ERR_ARG;
+    }
+}
+
+pc_status pc_autotune(pc_ctx *h, const double *b, int32_t iters, int64_t *chosen, double *ms_per_iter, void *stream) {
+    if (!h || !b || iters < 1) return PC_ERR_ARG;
+    float ms = 0.0f;
+    pc_status st = autotune_run(&h->c, b, iters, chosen, &ms, (hipStream_t)stream);
+    if (ms_per_iter) *ms_per_iter = ms;
+    return st;
+}
+
+pc_status pc_set_instances(pc_ctx *h, const int32_t *vertex_begin, int32_t ninst) {
+    if (!h || !vertex_begin || ninst < 1) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (vertex_begin[0] != 0 || vertex_begin[ninst] != ctx->nv) {
+        ctx->err = "instance ranges must start at 0 and end at nv";
+        return PC_ERR_ARG;
+    }
+    for (int i = 0; i < ninst; ++i)
+        if (vertex_begin[i + 1] <= vertex_begin[i]) {
+            ctx->err = "instance ranges must be non-empty and increasing";
+            return PC_ERR_ARG;
+        }
+    // no triangle may join two instances
+    std::vector<int> tri((size_t)3 * ctx->nt);
+    PC_HIP(hipMemcpy(tri.data(), ctx->tri, sizeof(int) * tri.size(), hipMemcpyDeviceToHost));
+    std::vector<int> inst_of(ctx->nv);
+    for (int i = 0; i < ninst; ++i)
+        for (int v = vertex_begin[i]; v < vertex_begin[i + 1]; ++v) inst_of[v] = i;
+    for (int t = 0; t < ctx->nt; ++t) {
+        const int a = inst_of[tri[t]], b = inst_of[tri[(size_t)ctx->nt + t]], c = inst_of[tri[2 * (size_t)ctx->nt + t]];
+        if (a != b || b != c) {
+            ctx->err = "triangle " + std::to_string(t) + " joins two instances";
+            return PC_ERR_MESH;
+        }
+    }
+    ctx->inst_row0_h.assign(vertex_begin, vertex_begin + ninst + 1);
+    return build_schedule(ctx);
+}
+
+pc_status pc_get_instance_info(pc_ctx *h, pc_solve_info *infos, int32_t n) {
+    if (!h || !infos || n != h->c.ninst) return PC_ERR_ARG;
+    for (int i = 0; i < n; ++i) infos[i] = h->c.inst_info[i];
+    return PC_OK;
+}
+
+static MlpState *mlp_of(Ctx *ctx) {
+    if (!ctx->mlp) ctx->mlp = new (std::nothrow) MlpState();
+    return ctx->mlp;
+}
+
+pc_status pc_ws_set_params(pc_ctx *h, const float *params_host, int32_t n) {
+    if (!h || !params_host || n != PC_WS_PARAMS) return PC_ERR_ARG;
+    MlpState *M = mlp_of(&h->c);
+    if (!M) return PC_ERR_OOM;
+    return mlp_set_params(&h->c, M, params_host);
+}
+
+pc_status pc_ws_get_params(pc_ctx *h, float *params_host, int32_t n) {
+    if (!h || !params_host || n != PC_WS_PARAMS) return PC_ERR_ARG;
+    if (!h->c.mlp) { h->c.err = "no warm-start parameters set"; return PC_ERR_ARG; }
+    return mlp_get_params(&h->c, h->c.mlp, params_host);
+}
+
+static bool ws_args(Ctx *ctx, const void *x, const void *v, const void *b, const void *dvp) {
+    if (!x || !v || !b || !dvp) { ctx->err = "warm start: x, v, b, dv_prev must be device pointers"; return false; }
+    if (!ctx->assembled) { ctx->err = "warm start: nothing assembled"; return false; }
+    return true;
+}
+
+pc_status pc_ws_features(pc_ctx *h, const double *x, const double *v, const double *b, const double *dv_prev,
+                         uint16_t *feat_out, void *stream) {
+    if (!h || !feat_out || !ws_args(&h->c, x, v, b, dv_prev)) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    MlpState *M = mlp_of(ctx);
+    if (!M) return PC_ERR_OOM;
+    hipStream_t s = (hipStream_t)stream;
+    pc_status st = mlp_features(ctx, M, x, v, b, dv_prev, s);
+    if (st) return st;
+    PC_HIP(hipMemcpyAsync(feat_out, M->X, sizeof(short) * 32 * (size_t)ctx->nv, hipMemcpyDeviceToDevice, s));
+    return PC_OK;
+}
+
+pc_status pc_ws_predict(pc_ctx *h, const double *x, const double *v, const double *b, const double *dv_prev,
+                        double *dv0_out, void *stream) {
+    if (!h || !dv0_out || !ws_args(&h->c, x, v, b, dv_prev)) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (!ctx->mlp || !ctx->mlp->has_params) { ctx->err = "no warm-start parameters set"; return PC_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    pc_status st = mlp_features(ctx, ctx->mlp, x, v, b, dv_prev, s);
+    if (st) return st;
+    return mlp_forward(ctx, ctx->mlp, dv_prev, dv0_out, false, s);
+}
+
+pc_status pc_ws_gradient(pc_ctx *h, const double *x, const double *v, const double *b, const double *dv_prev,
+                         float *grad_host, double *loss_host, void *stream) {
+    if (!h || !ws_args(&h->c, x, v, b, dv_prev)) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (!ctx->mlp || !ctx->mlp->has_params) { ctx->err = "no warm-start parameters set"; return PC_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    double loss = 0.0;
+    pc_status st = mlp_gradient(ctx, ctx->mlp, x, v, b, dv_prev, &loss, s);
+    if (st) return st;
+    PC_HIP(hipStreamSynchronize(s));
+    if (loss_host) *loss_host = loss;
+    if (grad_host) return mlp_get_grads(ctx, ctx->mlp, grad_host);
+    return PC_OK;
+}
+
+pc_status pc_ws_train_step(pc_ctx *h, const double *x, const double *v, const double *b, const double *dv_prev,
+                           double lr, double *loss_host, void *stream) {
+    if (!h || !ws_args(&h->c, x, v, b, dv_prev) || !(lr >= 0.0)) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (!ctx->mlp || !ctx->mlp->has_params) { ctx->err = "no warm-start parameters set"; return PC_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    pc_status st = mlp_gradient(ctx, ctx->mlp, x, v, b, dv_prev, loss_host, s);
+    if (st) return st;
+    return mlp_adam(ctx, ctx->mlp, lr, s);
+}
+
+pc_status pc_mfma_probe(pc_ctx *h, float *out_host) {
+    if (!h || !out_host) return PC_ERR_ARG;
+    return mlp_probe(&h->c, out_host);
+}
+
 pc_status pc_destroy(pc_ctx *h) {
     if (!h) return PC_ERR_ARG;
     (void)hipDeviceSynchronize();
-    h->c.prof.destroy();
-    for (int v = 0; v < 2; ++v) {
-        if (h->c.gexec[v]) (void)hipGraphExecDestroy(h->c.gexec[v]);
-        for (int k = 0; k < 6; ++k)
-            if (h->c.gev[v][k]) (void)hipEventDestroy(h->c.gev[v][k]);
+    if (h->c.mlp) {
+        mlp_free(h->c.mlp);
+        delete h->c.mlp;
+        h->c.mlp = nullptr;
     }
+    h->c.prof.destroy();
+    for (int v = 0; v < 2; ++v)
+        if (h->c.gexec[v]) (void)hipGraphExecDestroy(h->c.gexec[v]);
     if (h->c.cap_stream) (void)hipStreamDestroy(h->c.cap_stream);
     free_all(&h->c);
     delete h;
@@ -335,7 +500,7 @@ pc_status cloth_pcg_solve(pc_ctx *h, const double *b, double *dv, const pc_solve
     if (!h) return PC_ERR_ARG;
     Ctx *ctx = &h->c;
     if (!b || !dv) { ctx->err = "cloth_pcg_solve: b and dv must be device pointers"; return PC_ERR_ARG; }
-    if (opts && (!(opts->tol >= 0.0) || opts->warm < 0 || opts->warm > 1 || !(opts->inner_rho >= 0.0) ||
+    if (opts && (!(opts->tol >= 0.0) || opts->warm < 0 || opts->warm > 2 || !(opts->inner_rho >= 0.0) ||
                  opts->inner_rho >= 1.0)) {
         ctx->err = "bad solve options";
         return PC_ERR_ARG;
@@ -389,7 +554,7 @@ pc_status cloth_step(pc_ctx *h, double *x, double *v, int32_t nsteps, pc_dtype d
         pc_solve_info info{};
         if ((st = pc_check(h, stream))) return st;
         pc_solve_opts ok = o;
-        if (!ctx->have_prev_dv) ok.warm = 0;
+        if (!ctx->have_prev_dv && ok.warm == 1) ok.warm = 0;  // the learned start accepts dv_prev = 0
         st = pcg_run(ctx, ctx->bbuf, ctx->tmp, &ok, &info, s);
         if (infos) infos[k] = info;
         if (st) return st;

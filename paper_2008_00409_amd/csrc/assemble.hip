@@ -444,7 +444,7 @@ struct AsmArgs {
     const double *x, *v;
     DevParams prm;
     int *rowlen, *rowptr, *colidx, *jcol;
-    const int *row_lane;
+    const int *row_lane, *row_slice, *slice_row0;
     const uint8_t *slot_cnt;
     void *jval;
     double *jval_hi;   // FP64 copy (nullptr when the solver copy is FP64)
@@ -538,22 +538,25 @@ __global__ void __launch_bounds__(64) k_row_pattern(AsmArgs A) {
     }
 }
 
-// Solver layout of one 64-row slice: rows ordered by decreasing length (ties
-// by row), lane_row / row_lane give the order, slot_cnt[k] = rows with more
-// than k blocks.  Block k of the row in lane l of slice s then sits at
-// rowptr[64 s] + sum_{k' < k} slot_cnt[k'] + l.
-__global__ void __launch_bounds__(64) k_slice_layout(int nv, int nslices, const int *rowlen, int *lane_row,
-                                                     int *row_lane, uint8_t *slot_cnt) {
+// Solver layout of one slice (up to 64 consecutive rows of one instance):
+// rows ordered by decreasing length (ties by row), lane_row / row_lane give
+// the order, slot_cnt[k] = rows with more than k blocks.  Block k of the row
+// in lane l of slice s then sits at rowptr[slice_row0[s]] +
+// sum_{k' < k} slot_cnt[k'] + l.
+__global__ void __launch_bounds__(64) k_slice_layout(int nslices, const int *slice_row0, const int *rowlen,
+                                                     int *lane_row, int *row_lane, uint8_t *slot_cnt) {
     const int s = blockIdx.x;
     if (s >= nslices) return;
     const int t = threadIdx.x;
-    const int row = s * WAVE + t;
-    const int len = row < nv ? rowlen[row] : 0;
+    const int r0 = slice_row0[s], r1 = slice_row0[s + 1];
+    const int row = r0 + t;
+    const bool in = row < r1;
+    const int len = in ? rowlen[row] : 0;
     const int key = ((WAVE - len) << 8) | t;   // len <= 64
     int rank = 0;
     for (int m = 0; m < WAVE; ++m) rank += (__shfl(key, m, WAVE) < key) ? 1 : 0;
-    lane_row[s * WAVE + rank] = row < nv ? row : -1;
-    if (row < nv) row_lane[row] = rank;
+    lane_row[s * WAVE + rank] = in ? row : -1;
+    if (in) row_lane[row] = rank;
     int c = 0;
     for (int k = 0; k < MAX_COLS; ++k) {
         unsigned long long bal = __ballot(len > k);
@@ -567,8 +570,8 @@ __global__ void __launch_bounds__(64) k_slice_layout(int nv, int nslices, const 
 // status word makes every solve refuse the matrix.
 template <typename TB>
 __device__ void write_overflow_row(const AsmArgs &A, int i) {
-    const int s = i / WAVE;
-    const int64_t seg = A.rowptr[s * WAVE];
+    const int s = A.row_slice[i];
+    const int64_t seg = A.rowptr[A.slice_row0[s]];
     const int cnt = (int)A.slot_cnt[s * WAVE];
     const int lane = A.row_lane[i];
     A.colidx[A.rowptr[i]] = i;
@@ -774,12 +777,12 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
     }
 
     // block-CSR pattern and solver layout
-    const int s = i / WAVE;
+    const int s = A.row_slice[i];
     const int cnt = (int)A.slot_cnt[s * WAVE + t];
     const int off = wave_excl_scan(cnt);
     if (active) {
         A.colidx[A.rowptr[i] + t] = col;
-        const int64_t seg = (int64_t)A.rowptr[s * WAVE] + off;
+        const int64_t seg = (int64_t)A.rowptr[A.slice_row0[s]] + off;
         const int lane = A.row_lane[i];
         A.jcol[seg + lane] = col;
         TB *val = (TB *)A.jval + 9 * seg + lane;
@@ -796,13 +799,13 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
 // Export: solver layout -> block-CSR FP64 with the true diagonal block
 // A_ii = m_i I + D_i - sum_{j != i} A_ij; optionally D_i.
 template <typename TB>
-__global__ void __launch_bounds__(64) k_export(int nv, const int *rowptr, const int *row_lane,
-                                               const uint8_t *slot_cnt, const int *jcol, const void *jval,
-                                               const double *mass, double *out, double *Dout) {
+__global__ void __launch_bounds__(64) k_export(int nv, const int *rowptr, const int *row_lane, const int *row_slice,
+                                               const int *slice_row0, const uint8_t *slot_cnt, const int *jcol,
+                                               const void *jval, const double *mass, double *out, double *Dout) {
     const int i = blockIdx.x;
     if (i >= nv) return;
     const int t = threadIdx.x;
-    const int s = i / WAVE;
+    const int s = row_slice[i];
     const int cnt = (int)slot_cnt[s * WAVE + t];
     const int off = wave_excl_scan(cnt);
     const int len = rowptr[i + 1] - rowptr[i];
@@ -810,7 +813,7 @@ __global__ void __launch_bounds__(64) k_export(int nv, const int *rowptr, const 
     double blk[9];
     int col = -1;
     if (active) {
-        const int64_t seg = (int64_t)rowptr[s * WAVE] + off;
+        const int64_t seg = (int64_t)rowptr[slice_row0[s]] + off;
         const int lane = row_lane[i];
         col = jcol[seg + lane];
         const TB *val = (const TB *)jval + 9 * seg + lane;
@@ -857,6 +860,8 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
         ctx->jval_bytes = need;
     }
     ctx->dtype = dtype;
+    ctx->last_x = x;
+    ctx->last_v = v;
     if (dtype != PC_F64 && !ctx->jval_hi) {
         if ((st = dev_alloc(ctx, (void **)&ctx->jval_hi, (size_t)ctx->cap * 9 * sizeof(double)))) return st;
     }
@@ -877,6 +882,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     a.pinned = ctx->pinned; a.x = x; a.v = v; a.prm = ctx->prm;
     a.rowlen = ctx->rowlen; a.rowptr = ctx->rowptr; a.colidx = ctx->colidx; a.jcol = ctx->jcol;
     a.row_lane = ctx->row_lane; a.slot_cnt = ctx->slot_cnt; a.jval = ctx->jval;
+    a.row_slice = ctx->row_slice; a.slice_row0 = ctx->slice_row0;
     a.jval_hi = dtype != PC_F64 ? ctx->jval_hi : nullptr;
     a.b = b; a.diag = diag_out ? diag_out : ctx->diag; a.dinv = ctx->dinv; a.status = ctx->status;
     const int nb = ((nv + 7) / 8) * 8;
@@ -885,8 +891,8 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     ctx->prof.end(slot, s);
     if ((st = scan_excl(ctx, ctx->rowlen, ctx->rowptr, nv, s))) return st;
     // 3. solver layout
-    hipLaunchKernelGGL(k_slice_layout, dim3(ctx->nslices), dim3(64), 0, s, nv, ctx->nslices, ctx->rowlen,
-                       ctx->lane_row, ctx->row_lane, ctx->slot_cnt);
+    hipLaunchKernelGGL(k_slice_layout, dim3(ctx->nslices), dim3(64), 0, s, ctx->nslices, ctx->slice_row0,
+                       ctx->rowlen, ctx->lane_row, ctx->row_lane, ctx->slot_cnt);
     // 4. values
     slot = ctx->prof.begin(PK_ROW_ASM, s);
     switch (dtype) {
@@ -913,15 +919,15 @@ pc_status export_blocks(Ctx *ctx, double *vals, double *D, bool solver, hipStrea
     switch (dt) {
         case PC_F64:
             hipLaunchKernelGGL(k_export<double>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->row_lane,
-                               ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
+                               ctx->row_slice, ctx->slice_row0, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
             break;
         case PC_F32:
             hipLaunchKernelGGL(k_export<float>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->row_lane,
-                               ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
+                               ctx->row_slice, ctx->slice_row0, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
             break;
         case PC_BF16:
             hipLaunchKernelGGL(k_export<bf16_t>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->row_lane,
-                               ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
+                               ctx->row_slice, ctx->slice_row0, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
             break;
     }
     PC_HIP(hipGetLastError());

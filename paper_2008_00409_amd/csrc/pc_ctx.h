@@ -84,9 +84,14 @@ struct Prof {
     }
 };
 
+struct MlpState;
+
 struct Ctx {
     std::string err;
     Prof prof;
+    double ell = 0.0;          // mean rest edge length (over the 3 edges of every triangle)
+    const double *last_x = nullptr, *last_v = nullptr;  // state of the last assembly (caller's buffers)
+    MlpState *mlp = nullptr;   // learned warm start (allocated on first use)
     int nv = 0, nt = 0, nh = 0;
     int nslices = 0;          // ceil(nv / 64)
     int64_t cap = 0;          // block capacity (upper bound of nnzb)
@@ -116,6 +121,23 @@ struct Ctx {
     int *lane_row = nullptr;  // nslices * 64 (row of each lane, -1 padding)
     int *row_lane = nullptr;  // nv
     uint8_t *slot_cnt = nullptr;  // nslices * 64
+    int *slice_row0 = nullptr;    // nslices + 1: first row of each slice
+    int *row_slice = nullptr;     // nv: slice of each row
+    int slice_cap = 0;            // slices the layout arrays can hold
+
+    // instances and work schedules (one instance unless pc_set_instances)
+    int ninst = 1;
+    std::vector<int> inst_row0_h;     // ninst + 1 instance row ranges
+    int spb = 4;                      // slices per SpMV work item (wavefronts per block)
+    int rpb = 256;                    // rows per vector work item
+    int n_sitems = 0, n_vitems = 0;
+    int4 *sitem = nullptr, *vitem = nullptr;
+    int *inst_sitem0 = nullptr, *inst_vitem0 = nullptr;
+    uint8_t *restart = nullptr;       // per-instance flags (device)
+    uint8_t *restart_h = nullptr;     // pinned host staging
+    int *maxit_d = nullptr;           // per-instance iteration budget
+    int sched_version = 0;
+    std::vector<pc_solve_info> inst_info;
     void *jval = nullptr;     // cap * 9 values of dtype (solver copy)
     size_t jval_bytes = 0;
     double *jval_hi = nullptr;  // cap * 9 FP64 values (refinement residual), when dtype != PC_F64
@@ -130,10 +152,10 @@ struct Ctx {
     double *x = nullptr, *r = nullptr, *q = nullptr, *tmp = nullptr, *bbuf = nullptr;
     float4 *p = nullptr;
     double *partials = nullptr;   // per-block partial sums (4 doubles per block)
-    double *res2 = nullptr;       // 2 doubles: true-residual check
+    double *res2 = nullptr;       // 2 doubles per instance: true-residual check
     unsigned *counter = nullptr;
-    PcgState *st = nullptr;       // device
-    PcgState *st_host = nullptr;  // pinned host
+    PcgState *st = nullptr;       // device, one per instance
+    PcgState *st_host = nullptr;  // pinned host, one per instance
     int *status_host = nullptr;   // pinned host
 
     // scan scratch
@@ -141,15 +163,14 @@ struct Ctx {
     size_t scan_tmp_elems = 0;
 
     // CG iterations captured as HIP graphs: one per inner operator (0: the
-    // solver copy, 1: the FP64 blocks), each `graph_chunk` iterations long,
-    // with event nodes around the first iteration's kernels for timing.
+    // solver copy, 1: the FP64 blocks), each `graph_chunk` iterations long.
     int graph_chunk = 0;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     const void *gkey[2] = {nullptr, nullptr};
     int gkey_dtype[2] = {-1, -1};
     int gkey_chunk[2] = {0, 0};
-    hipEvent_t gev[2][6] = {};
+    int gkey_sched[2] = {-1, -1};
 };
 
 // Error helpers (host)
@@ -174,5 +195,7 @@ pc_status update_run(Ctx *ctx, const double *dv, double *x, double *v, hipStream
 pc_status scan_excl(Ctx *ctx, const int *in, int *out, int n, hipStream_t s);
 pc_status dev_alloc(Ctx *ctx, void **p, size_t bytes);
 pc_status read_status(Ctx *ctx, hipStream_t s, int *bits);
+pc_status build_schedule(Ctx *ctx);
+pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, float *best_ms, hipStream_t s);
 
 }  // namespace pc

@@ -2,11 +2,17 @@
 // of Eq. 3 is solved by PCG each step; Sec. 3.1: SpMV is the dominant
 // operator, vector operations are element-wise).
 //
-// Solver layout: rows are grouped in slices of 64 (one wavefront); inside a
-// slice they are ordered by decreasing length, and block k of every row with
-// more than k blocks is stored contiguously (column index plane, then 9 value
-// planes), so each load instruction of the wavefront reads consecutive
-// addresses and no padding is stored.
+// Solver layout: rows are grouped in slices of up to 64 (one wavefront),
+// never across instances; inside a slice rows are ordered by decreasing
+// length, and block k of every row with more than k blocks is stored
+// contiguously (column index plane, then 9 value planes), so each load
+// instruction of the wavefront reads consecutive addresses and no padding is
+// stored.
+//
+// Several independent cloths (instances) can share one context: every kernel
+// works on a schedule of work items that never straddle instances, and each
+// instance has its own CG scalars, convergence flag and refinement sweeps,
+// so all instances advance in the same launches.
 //
 // The operator is applied in difference form
 //   y_i = m_i x_i + D_i x_i + sum_{j != i} A_ij (x_j - x_i),
@@ -18,13 +24,14 @@
 #include <algorithm>
 #include <cmath>
 
-#include "pc_ctx.h"
+#include "pc_mlp.h"
 
 namespace pc {
 
 struct SpmvArgs {
     int nv, nslices;
     const int *rowptr;
+    const int *slice_row0;
     const uint8_t *slot_cnt;
     const int *lane_row;
     const int *jcol;
@@ -63,7 +70,7 @@ template <typename TB, typename V, int UNROLL = 4>
 __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, const V &x, double y[3],
                                         double xi[3]) {
     const int row = M.lane_row[slice * WAVE + lane];
-    const int base = M.rowptr[slice * WAVE];
+    const int base = M.rowptr[M.slice_row0[slice]];
     const int my_cnt = (int)M.slot_cnt[slice * WAVE + lane];
     const int my_off = base + wave_excl_scan(my_cnt);
     const int nslots = __popcll(__ballot(my_cnt > 0));  // counts are non-increasing in the slot
@@ -115,24 +122,30 @@ __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, 
     return row;
 }
 
-__device__ __forceinline__ int slice_of_thread(int nslices) {
-    const int wpb = blockDim.x / WAVE;
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    return __builtin_amdgcn_readfirstlane(b * wpb + (int)(threadIdx.x / WAVE));
-}
 
-__device__ __forceinline__ int row_of_thread() {
+// Work schedules (built by build_schedule): SpMV items of up to `spb`
+// slices, vector items of up to `rpb` rows; items of one instance are
+// contiguous (inst_sitem0 / inst_vitem0 give the ranges).
+struct Sched {
+    int n_sitems, n_vitems, ninst;
+    const int4 *sitem;   // inst, first slice, number of slices, -
+    const int4 *vitem;   // inst, first row, end row, -
+    const int *inst_sitem0, *inst_vitem0;
+};
+
+__device__ __forceinline__ int item_of_block(int n) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
-    return b * blockDim.x + threadIdx.x;
+    return b < n ? b : -1;
 }
 
 // ---------------------------------------------------------------- reductions
 // Deterministic two-stage sums without device-scope fences: every block of a
-// producing kernel writes its NV partial sums (plain stores, block order), and
-// a one-block finalize kernel launched next adds them in block order; the
-// kernel boundary makes the partials visible.  partials layout: [q][block].
+// producing kernel writes its NV partial sums for its work item (plain
+// stores), and a finalize kernel launched next adds the items of each
+// instance in item order; the kernel boundary makes the partials visible.
+// partials layout: [q][item].
 template <int NV>
-__device__ __forceinline__ void block_partials(double (&v)[NV], double *partials) {
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *partials, int item, int nitems) {
     __shared__ double sh[NV][16];
     const int lane = lane_id(), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
 #pragma unroll
@@ -145,22 +158,22 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *partials
         const int q = threadIdx.x;
         double s = 0.0;
         for (int k = 0; k < nw; ++k) s += sh[q][k];
-        partials[(size_t)q * gridDim.x + blockIdx.x] = s;
+        partials[(size_t)q * nitems + item] = s;
     }
 }
 
-// Sum of partials[q][0..n) in a fixed order, valid in every thread of a
-// single 1024-thread block.
+// Sum of partials[q][i0..i1) in a fixed order, valid in every thread of the
+// (256-thread) block.
 template <int NV>
-__device__ __forceinline__ void finalize_sum(const double *partials, int n, double (&tot)[NV]) {
+__device__ __forceinline__ void instance_sum(const double *partials, int nitems, int i0, int i1, double (&tot)[NV]) {
     __shared__ double sh[NV][16];
     const int lane = lane_id(), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
     double loc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) loc[q] = 0.0;
-    for (int b = threadIdx.x; b < n; b += blockDim.x)
+    for (int b = i0 + threadIdx.x; b < i1; b += blockDim.x)
 #pragma unroll
-        for (int q = 0; q < NV; ++q) loc[q] += partials[(size_t)q * n + b];
+        for (int q = 0; q < NV; ++q) loc[q] += partials[(size_t)q * nitems + b];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
         const double s = wave_sum(loc[q]);
@@ -176,32 +189,38 @@ __device__ __forceinline__ void finalize_sum(const double *partials, int n, doub
 }
 
 // ---------------------------------------------------------------- kernels
-__global__ void k_state_init(PcgState *st, double tol, double rho, int maxit) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->rz = st->pq = st->alpha = st->beta = st->rr = st->bb = 0.0;
-        st->tol2 = tol * tol;
-        st->rho2 = rho * rho;
-        st->thresh = 0.0;
-        st->rr0 = 0.0;
-        st->rz0 = 0.0;
-        st->iters = 0;
-        st->maxit = maxit;
-        st->done = 0;
-        st->flags = 0;
-    }
+// Reset the state of every instance (restart == nullptr) or of the flagged ones.
+__global__ void k_state_init(int ninst, PcgState *st, const uint8_t *restart, double tol, double rho,
+                             const int *maxit) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || (restart && !restart[i])) return;
+    PcgState &S = st[i];
+    S.rz = S.pq = S.alpha = S.beta = S.rr = S.bb = 0.0;
+    S.tol2 = tol * tol;
+    S.rho2 = rho * rho;
+    S.thresh = 0.0;
+    S.rr0 = 0.0;
+    S.rz0 = 0.0;
+    S.iters = 0;
+    S.maxit = maxit[i];
+    S.done = 0;
+    S.flags = 0;
 }
 
-// q = A p and per-block partials of p.q.
+// q = A p and per-item partials of p.q.
 template <typename TB>
-__global__ void __launch_bounds__(256) k_pcg_spmv(SpmvArgs M, const float4 *p, double *q, const PcgState *st,
-                                                  double *partials) {
-    if (st->done) return;
-    const int slice = slice_of_thread(M.nslices);
+__global__ void __launch_bounds__(512) k_pcg_spmv(SpmvArgs M, Sched S, const float4 *p, double *q,
+                                                  const PcgState *st, double *partials) {
+    const int it = item_of_block(S.n_sitems);
+    if (it < 0) return;
+    const int4 I = S.sitem[it];
+    if (st[I.x].done) return;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int lane = lane_id();
     double pq = 0.0;
-    if (slice < M.nslices) {
+    if (w < I.z) {
         double y[3], xi[3];
-        const int row = spmv_row<TB>(M, slice, lane, VecF4{p}, y, xi);
+        const int row = spmv_row<TB>(M, I.y + w, lane, VecF4{p}, y, xi);
         if (row >= 0) {
             q[3 * row] = y[0];
             q[3 * row + 1] = y[1];
@@ -210,96 +229,101 @@ __global__ void __launch_bounds__(256) k_pcg_spmv(SpmvArgs M, const float4 *p, d
         }
     }
     double v[1] = {pq};
-    block_partials<1>(v, partials);
+    block_partials<1>(v, partials, it, S.n_sitems);
 }
 
-// alpha = rz / p.q; a non-positive or non-finite p.q ends the sweep.
-__global__ void __launch_bounds__(1024) k_fin_alpha(const double *partials, int n, PcgState *st) {
-    if (st->done) return;
+// alpha = rz / p.q per instance; a non-positive or non-finite p.q ends the sweep.
+__global__ void __launch_bounds__(256) k_fin_alpha(Sched S, const double *partials, PcgState *st) {
+    const int inst = blockIdx.x;
+    if (inst >= S.ninst || st[inst].done) return;
     double tot[1];
-    finalize_sum<1>(partials, n, tot);
+    instance_sum<1>(partials, S.n_sitems, S.inst_sitem0[inst], S.inst_sitem0[inst + 1], tot);
     if (threadIdx.x == 0) {
-        const double a = st->rz / tot[0];
-        st->pq = tot[0];
-        st->alpha = a;
+        PcgState &T = st[inst];
+        const double a = T.rz / tot[0];
+        T.pq = tot[0];
+        T.alpha = a;
         if (!(tot[0] > 0.0) || !isfinite(a)) {
-            st->flags |= isfinite(tot[0]) ? 1 : 2;
-            st->done = 1;
+            T.flags |= isfinite(tot[0]) ? 1 : 2;
+            T.done = 1;
         }
     }
 }
 
-// x += alpha p, r -= alpha q; partials of r.z (z = D^-1 r) and r.r.
-// Flat indexing over the 3 nv components: each thread handles UPD_PER
-// components spaced by the block size, so every load instruction of a
-// wavefront covers consecutive 8-byte elements.
-constexpr int UPD_PER = 4;
-__global__ void __launch_bounds__(256) k_pcg_update(int n3, double *x, double *r, const float *pf,
-                                                    const double *q, const float *dinv, const PcgState *st,
-                                                    double *partials) {
-    if (st->done) return;
-    const double alpha = st->alpha;
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int base = b * (256 * UPD_PER) + threadIdx.x;
+// x += alpha p, r -= alpha q over the item's rows (flat component indexing:
+// consecutive threads touch consecutive 8-byte elements); partials of r.z
+// (z = D^-1 r) and r.r.
+__global__ void __launch_bounds__(256) k_pcg_update(Sched S, double *x, double *r, const float *pf, const double *q,
+                                                    const float *dinv, const PcgState *st, double *partials) {
+    const int it = item_of_block(S.n_vitems);
+    if (it < 0) return;
+    const int4 I = S.vitem[it];
+    if (st[I.x].done) return;
+    const double alpha = st[I.x].alpha;
     double rz = 0.0, rr = 0.0;
-#pragma unroll
-    for (int u = 0; u < UPD_PER; ++u) {
-        const int k = base + u * 256;
-        if (k < n3) {
-            const int i = k / 3;
-            const double pk = pf[4 * i + (k - 3 * i)];
-            x[k] += alpha * pk;
-            const double rk = r[k] - alpha * q[k];
-            r[k] = rk;
-            rz += rk * rk * (double)dinv[k];
-            rr += rk * rk;
-        }
+    for (int k = 3 * I.y + threadIdx.x; k < 3 * I.z; k += blockDim.x) {
+        const int i = k / 3;
+        const double pk = pf[4 * i + (k - 3 * i)];
+        x[k] += alpha * pk;
+        const double rk = r[k] - alpha * q[k];
+        r[k] = rk;
+        rz += rk * rk * (double)dinv[k];
+        rr += rk * rk;
     }
     double v[2] = {rz, rr};
-    block_partials<2>(v, partials);
+    block_partials<2>(v, partials, it, S.n_vitems);
 }
 
 // beta = rz_new / rz; convergence test ||r||^2 <= thresh; iteration count.
-__global__ void __launch_bounds__(1024) k_fin_beta(const double *partials, int n, PcgState *st) {
-    if (st->done) return;
+__global__ void __launch_bounds__(256) k_fin_beta(Sched S, const double *partials, PcgState *st) {
+    const int inst = blockIdx.x;
+    if (inst >= S.ninst || st[inst].done) return;
     double tot[2];
-    finalize_sum<2>(partials, n, tot);
+    instance_sum<2>(partials, S.n_vitems, S.inst_vitem0[inst], S.inst_vitem0[inst + 1], tot);
     if (threadIdx.x == 0) {
-        st->beta = tot[0] / st->rz;
-        st->rz = tot[0];
-        st->rr = tot[1];
-        st->iters += 1;
+        PcgState &T = st[inst];
+        T.beta = tot[0] / T.rz;
+        T.rz = tot[0];
+        T.rr = tot[1];
+        T.iters += 1;
         if (!isfinite(tot[1]) || !isfinite(tot[0])) {
-            st->flags |= 2;
-            st->done = 1;
-        } else if (tot[1] <= st->thresh || st->iters >= st->maxit) {
-            st->done = 1;
+            T.flags |= 2;
+            T.done = 1;
+        } else if (tot[1] <= T.thresh || T.iters >= T.maxit) {
+            T.done = 1;
         }
     }
 }
 
-// p = D^-1 r + beta p
-__global__ void __launch_bounds__(256) k_pcg_dir(int nv, const double *r, float4 *p, const float *dinv,
+// p = D^-1 r + beta p over the item's rows.
+__global__ void __launch_bounds__(256) k_pcg_dir(Sched S, const double *r, float4 *p, const float *dinv,
                                                  const PcgState *st) {
-    if (st->done) return;
-    const double beta = st->beta;
-    const int i = row_of_thread();
-    if (i >= nv) return;
-    const float4 pv = p[i];
-    float4 o;
-    o.x = (float)(r[3 * i] * (double)dinv[3 * i] + beta * pv.x);
-    o.y = (float)(r[3 * i + 1] * (double)dinv[3 * i + 1] + beta * pv.y);
-    o.z = (float)(r[3 * i + 2] * (double)dinv[3 * i + 2] + beta * pv.z);
-    o.w = 0.0f;
-    p[i] = o;
+    const int it = item_of_block(S.n_vitems);
+    if (it < 0) return;
+    const int4 I = S.vitem[it];
+    if (st[I.x].done) return;
+    const double beta = st[I.x].beta;
+    for (int i = I.y + threadIdx.x; i < I.z; i += blockDim.x) {
+        const float4 pv = p[i];
+        float4 o;
+        o.x = (float)(r[3 * i] * (double)dinv[3 * i] + beta * pv.x);
+        o.y = (float)(r[3 * i + 1] * (double)dinv[3 * i + 1] + beta * pv.y);
+        o.z = (float)(r[3 * i + 2] * (double)dinv[3 * i + 2] + beta * pv.z);
+        o.w = 0.0f;
+        p[i] = o;
+    }
 }
 
-// Zero start: x = 0, r = b, p = D^-1 r; partials of r.z and ||b||^2.
-__global__ void __launch_bounds__(256) k_pcg_start_zero(int nv, const double *b, double *x, double *r,
-                                                        float4 *p, const float *dinv, double *partials) {
-    const int i = row_of_thread();
+// Zero start of the flagged instances (all when restart == nullptr):
+// x = 0, r = b, p = D^-1 r; partials of r.z, ||r||^2 and ||b||^2.
+__global__ void __launch_bounds__(256) k_pcg_start_zero(Sched S, const uint8_t *restart, const double *b, double *x,
+                                                        double *r, float4 *p, const float *dinv, double *partials) {
+    const int it = item_of_block(S.n_vitems);
+    if (it < 0) return;
+    const int4 I = S.vitem[it];
+    if (restart && !restart[I.x]) return;
     double rz = 0.0, rr = 0.0;
-    if (i < nv) {
+    for (int i = I.y + threadIdx.x; i < I.z; i += blockDim.x) {
         float4 o;
         float *op = &o.x;
 #pragma unroll
@@ -316,21 +340,27 @@ __global__ void __launch_bounds__(256) k_pcg_start_zero(int nv, const double *b,
         p[i] = o;
     }
     double v[3] = {rz, rr, rr};
-    block_partials<3>(v, partials);
+    block_partials<3>(v, partials, it, S.n_vitems);
 }
 
-// Residual t = b - A x for FP64 x.  MODE 0 (sweep start): r = t, p = D^-1 r;
-// partials of r.z, ||r||^2, ||b||^2.  MODE 1 (check): partials of ||t||^2,
-// ||b||^2 only.
+// Residual t = b - A x for FP64 x over the item's slices.  MODE 0 (sweep
+// start of the flagged instances): r = t, p = D^-1 r; partials of r.z,
+// ||r||^2, ||b||^2.  MODE 1 (check, all instances): partials of ||t||^2,
+// ||b||^2.
 template <typename TB, int MODE>
-__global__ void __launch_bounds__(256) k_residual(SpmvArgs M, const double *b, const double *x, double *r,
-                                                  float4 *p, const float *dinv, double *partials) {
-    const int slice = slice_of_thread(M.nslices);
+__global__ void __launch_bounds__(512) k_residual(SpmvArgs M, Sched S, const uint8_t *restart, const double *b,
+                                                  const double *x, double *r, float4 *p, const float *dinv,
+                                                  double *partials) {
+    const int it = item_of_block(S.n_sitems);
+    if (it < 0) return;
+    const int4 I = S.sitem[it];
+    if (MODE == 0 && restart && !restart[I.x]) return;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int lane = lane_id();
     double rz = 0.0, rr = 0.0, bb = 0.0;
-    if (slice < M.nslices) {
+    if (w < I.z) {
         double y[3], xi[3];
-        const int row = spmv_row<TB>(M, slice, lane, VecD3{x}, y, xi);
+        const int row = spmv_row<TB>(M, I.y + w, lane, VecD3{x}, y, xi);
         if (row >= 0) {
             float4 o;
             float *op = &o.x;
@@ -354,46 +384,59 @@ __global__ void __launch_bounds__(256) k_residual(SpmvArgs M, const double *b, c
         }
     }
     double v[3] = {rz, rr, bb};
-    block_partials<3>(v, partials);
+    block_partials<3>(v, partials, it, S.n_sitems);
 }
 
-// Sweep start: rz, ||r_0||^2, ||b||^2 -> state (threshold, early exit).
-__global__ void __launch_bounds__(1024) k_fin_start(const double *partials, int n, PcgState *st) {
+// Sweep start of the flagged instances: rz, ||r_0||^2, ||b||^2 -> state
+// (threshold, early exit when the start already meets the tolerance).
+__global__ void __launch_bounds__(256) k_fin_start(Sched S, int use_sitems, const uint8_t *restart,
+                                                   const double *partials, PcgState *st) {
+    const int inst = blockIdx.x;
+    if (inst >= S.ninst || (restart && !restart[inst])) return;
     double tot[3];
-    finalize_sum<3>(partials, n, tot);
+    if (use_sitems)
+        instance_sum<3>(partials, S.n_sitems, S.inst_sitem0[inst], S.inst_sitem0[inst + 1], tot);
+    else
+        instance_sum<3>(partials, S.n_vitems, S.inst_vitem0[inst], S.inst_vitem0[inst + 1], tot);
     if (threadIdx.x == 0) {
-        st->rz = tot[0];
-        st->rz0 = tot[0];
-        st->rr = tot[1];
-        st->bb = tot[2];
-        st->rr0 = tot[1];
-        st->thresh = fmax(st->tol2 * tot[2], st->rho2 * tot[1]);
+        PcgState &T = st[inst];
+        T.rz = tot[0];
+        T.rz0 = tot[0];
+        T.rr = tot[1];
+        T.bb = tot[2];
+        T.rr0 = tot[1];
+        T.thresh = fmax(T.tol2 * tot[2], T.rho2 * tot[1]);
         if (!isfinite(tot[1]) || !isfinite(tot[2])) {
-            st->flags |= 2;
-            st->done = 1;
-        } else if (tot[1] <= st->tol2 * tot[2] || tot[2] == 0.0) {
-            st->done = 1;
+            T.flags |= 2;
+            T.done = 1;
+        } else if (tot[1] <= T.tol2 * tot[2] || tot[2] == 0.0) {
+            T.done = 1;
         }
     }
 }
 
-// Residual check: ||t||^2, ||b||^2 -> out2.
-__global__ void __launch_bounds__(1024) k_fin_check(const double *partials, int n, double *out2) {
+// Residual check: ||t||^2, ||b||^2 of every instance -> out2[2 inst + {0,1}].
+__global__ void __launch_bounds__(256) k_fin_check(Sched S, const double *partials, double *out2) {
+    const int inst = blockIdx.x;
+    if (inst >= S.ninst) return;
     double tot[3];
-    finalize_sum<3>(partials, n, tot);
+    instance_sum<3>(partials, S.n_sitems, S.inst_sitem0[inst], S.inst_sitem0[inst + 1], tot);
     if (threadIdx.x == 0) {
-        out2[0] = tot[1];
-        out2[1] = tot[2];
+        out2[2 * inst] = tot[1];
+        out2[2 * inst + 1] = tot[2];
     }
 }
 
 // y = A x (FP64 in and out).
 template <typename TB>
-__global__ void __launch_bounds__(256) k_spmv_apply(SpmvArgs M, const double *x, double *yout) {
-    const int slice = slice_of_thread(M.nslices);
-    if (slice >= M.nslices) return;
+__global__ void __launch_bounds__(512) k_spmv_apply(SpmvArgs M, Sched S, const double *x, double *yout) {
+    const int it = item_of_block(S.n_sitems);
+    if (it < 0) return;
+    const int4 I = S.sitem[it];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    if (w >= I.z) return;
     double y[3], xi[3];
-    const int row = spmv_row<TB>(M, slice, lane_id(), VecD3{x}, y, xi);
+    const int row = spmv_row<TB>(M, I.y + w, lane_id(), VecD3{x}, y, xi);
     if (row >= 0) {
         yout[3 * row] = y[0];
         yout[3 * row + 1] = y[1];
@@ -404,6 +447,15 @@ __global__ void __launch_bounds__(256) k_spmv_apply(SpmvArgs M, const double *x,
 __global__ void k_copy_d(int64_t n, const double *src, double *dst) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
+}
+
+// Zero the rows of the flagged instances (b = 0 result).
+__global__ void k_zero_rows(Sched S, const uint8_t *flag, double *x) {
+    const int it = item_of_block(S.n_vitems);
+    if (it < 0) return;
+    const int4 I = S.vitem[it];
+    if (!flag[I.x]) return;
+    for (int k = 3 * I.y + threadIdx.x; k < 3 * I.z; k += blockDim.x) x[k] = 0.0;
 }
 
 // v += dv, x += h v; pinned vertices keep x and get v = 0.
@@ -429,6 +481,7 @@ static SpmvArgs spmv_args(Ctx *ctx, bool hi) {
     M.nv = ctx->nv;
     M.nslices = ctx->nslices;
     M.rowptr = ctx->rowptr;
+    M.slice_row0 = ctx->slice_row0;
     M.slot_cnt = ctx->slot_cnt;
     M.lane_row = ctx->lane_row;
     M.jcol = ctx->jcol;
@@ -437,90 +490,166 @@ static SpmvArgs spmv_args(Ctx *ctx, bool hi) {
     return M;
 }
 
+static Sched sched_args(Ctx *ctx) {
+    Sched S;
+    S.n_sitems = ctx->n_sitems;
+    S.n_vitems = ctx->n_vitems;
+    S.ninst = ctx->ninst;
+    S.sitem = ctx->sitem;
+    S.vitem = ctx->vitem;
+    S.inst_sitem0 = ctx->inst_sitem0;
+    S.inst_vitem0 = ctx->inst_vitem0;
+    return S;
+}
+
 static inline int pad8(int n) { return ((n + 7) / 8) * 8; }
 
+// Slices (up to 64 rows, never across instances) and work items from the
+// instance row ranges and the current spb / rpb.
+pc_status build_schedule(Ctx *ctx) {
+    const int ninst = (int)ctx->inst_row0_h.size() - 1;
+    std::vector<int> slice_row0, row_slice(ctx->nv);
+    std::vector<int4> sitems, vitems;
+    std::vector<int> isit(ninst + 1), ivit(ninst + 1);
+    for (int i = 0; i < ninst; ++i) {
+        const int r0 = ctx->inst_row0_h[i], r1 = ctx->inst_row0_h[i + 1];
+        const int s0 = (int)slice_row0.size();
+        for (int r = r0; r < r1; r += WAVE) {
+            for (int q = r; q < std::min(r + WAVE, r1); ++q) row_slice[q] = (int)slice_row0.size();
+            slice_row0.push_back(r);
+        }
+        const int s1 = (int)slice_row0.size();
+        isit[i] = (int)sitems.size();
+        for (int sl = s0; sl < s1; sl += ctx->spb) sitems.push_back(int4{i, sl, std::min(ctx->spb, s1 - sl), 0});
+        ivit[i] = (int)vitems.size();
+        for (int r = r0; r < r1; r += ctx->rpb) vitems.push_back(int4{i, r, std::min(r + ctx->rpb, r1), 0});
+    }
+    slice_row0.push_back(ctx->nv);
+    isit[ninst] = (int)sitems.size();
+    ivit[ninst] = (int)vitems.size();
+    const int nslices = (int)slice_row0.size() - 1;
+    pc_status st;
+    auto realloc = [&](void **p, size_t bytes) -> pc_status {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+        return dev_alloc(ctx, p, bytes);
+    };
+    if (nslices > ctx->slice_cap) {
+        if ((st = realloc((void **)&ctx->lane_row, sizeof(int) * (size_t)nslices * WAVE))) return st;
+        if ((st = realloc((void **)&ctx->slot_cnt, (size_t)nslices * WAVE))) return st;
+        if ((st = realloc((void **)&ctx->slice_row0, sizeof(int) * (size_t)(nslices + 1)))) return st;
+        ctx->slice_cap = nslices;
+    }
+    if ((st = realloc((void **)&ctx->sitem, sizeof(int4) * sitems.size()))) return st;
+    if ((st = realloc((void **)&ctx->vitem, sizeof(int4) * vitems.size()))) return st;
+    if ((st = realloc((void **)&ctx->inst_sitem0, sizeof(int) * (ninst + 1)))) return st;
+    if ((st = realloc((void **)&ctx->inst_vitem0, sizeof(int) * (ninst + 1)))) return st;
+    const size_t nitems = std::max(sitems.size(), vitems.size()) + 16;
+    if ((st = realloc((void **)&ctx->partials, sizeof(double) * 4 * nitems))) return st;
+    if (ninst != ctx->ninst || !ctx->st) {
+        if ((st = realloc((void **)&ctx->st, sizeof(PcgState) * ninst))) return st;
+        if ((st = realloc((void **)&ctx->res2, sizeof(double) * 2 * ninst))) return st;
+        if ((st = realloc((void **)&ctx->restart, (size_t)ninst))) return st;
+        if ((st = realloc((void **)&ctx->maxit_d, sizeof(int) * ninst))) return st;
+        if (ctx->st_host) (void)hipHostFree(ctx->st_host);
+        if (ctx->restart_h) (void)hipHostFree(ctx->restart_h);
+        ctx->st_host = nullptr;
+        ctx->restart_h = nullptr;
+        PC_HIP(hipHostMalloc((void **)&ctx->st_host, sizeof(PcgState) * ninst, hipHostMallocDefault));
+        PC_HIP(hipHostMalloc((void **)&ctx->restart_h, (size_t)ninst, hipHostMallocDefault));
+    }
+    if (!ctx->row_slice && (st = dev_alloc(ctx, (void **)&ctx->row_slice, sizeof(int) * (size_t)ctx->nv))) return st;
+    PC_HIP(hipMemcpy(ctx->slice_row0, slice_row0.data(), sizeof(int) * slice_row0.size(), hipMemcpyHostToDevice));
+    PC_HIP(hipMemcpy(ctx->row_slice, row_slice.data(), sizeof(int) * row_slice.size(), hipMemcpyHostToDevice));
+    PC_HIP(hipMemcpy(ctx->sitem, sitems.data(), sizeof(int4) * sitems.size(), hipMemcpyHostToDevice));
+    PC_HIP(hipMemcpy(ctx->vitem, vitems.data(), sizeof(int4) * vitems.size(), hipMemcpyHostToDevice));
+    PC_HIP(hipMemcpy(ctx->inst_sitem0, isit.data(), sizeof(int) * isit.size(), hipMemcpyHostToDevice));
+    PC_HIP(hipMemcpy(ctx->inst_vitem0, ivit.data(), sizeof(int) * ivit.size(), hipMemcpyHostToDevice));
+    ctx->nslices = nslices;
+    ctx->ninst = ninst;
+    ctx->n_sitems = (int)sitems.size();
+    ctx->n_vitems = (int)vitems.size();
+    ctx->inst_info.assign(ninst, pc_solve_info{});
+    ctx->sched_version += 1;
+    ctx->assembled = false;  // the solver layout depends on the slices
+    return PC_OK;
+}
+
 struct Grids {
-    int slice_blocks;  // 4 slices per 256-thread block
-    int row_blocks;    // 256 rows per block
-    int upd_blocks;    // 256 * UPD_PER components per block
+    int sblocks, sthreads;  // SpMV items: spb wavefronts each
+    int vblocks;            // vector items: 256 threads each
 };
 
 static Grids grids(Ctx *ctx) {
     Grids g;
-    g.slice_blocks = pad8((ctx->nslices + 3) / 4);
-    g.row_blocks = pad8((ctx->nv + 255) / 256);
-    g.upd_blocks = pad8((3 * ctx->nv + 256 * UPD_PER - 1) / (256 * UPD_PER));
+    g.sblocks = pad8(ctx->n_sitems);
+    g.sthreads = WAVE * ctx->spb;
+    g.vblocks = pad8(ctx->n_vitems);
     return g;
 }
 
-// One CG iteration.  With `ev` (graph capture) the three main kernels are
-// bracketed by the given event pairs instead of the sampled profiler.
 template <typename TB>
-static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Grids &g, hipStream_t s, hipEvent_t *ev = nullptr) {
-    if (ev) {
-        (void)hipEventRecord(ev[0], s);
-        hipLaunchKernelGGL(k_pcg_spmv<TB>, dim3(g.slice_blocks), dim3(256), 0, s, M, ctx->p, ctx->q, ctx->st,
-                           ctx->partials);
-        (void)hipEventRecord(ev[1], s);
-        hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(1024), 0, s, ctx->partials, g.slice_blocks, ctx->st);
-        (void)hipEventRecord(ev[2], s);
-        hipLaunchKernelGGL(k_pcg_update, dim3(g.upd_blocks), dim3(256), 0, s, 3 * ctx->nv, ctx->x, ctx->r,
-                           (const float *)ctx->p, ctx->q, ctx->dinv, ctx->st, ctx->partials);
-        (void)hipEventRecord(ev[3], s);
-        hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(1024), 0, s, ctx->partials, g.upd_blocks, ctx->st);
-        (void)hipEventRecord(ev[4], s);
-        hipLaunchKernelGGL(k_pcg_dir, dim3(g.row_blocks), dim3(256), 0, s, ctx->nv, ctx->r, ctx->p, ctx->dinv,
-                           ctx->st);
-        (void)hipEventRecord(ev[5], s);
-        return;
-    }
+static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s) {
     int slot = ctx->prof.begin(PK_SPMV, s);
-    hipLaunchKernelGGL(k_pcg_spmv<TB>, dim3(g.slice_blocks), dim3(256), 0, s, M, ctx->p, ctx->q, ctx->st,
+    hipLaunchKernelGGL(k_pcg_spmv<TB>, dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, ctx->p, ctx->q, ctx->st,
                        ctx->partials);
     ctx->prof.end(slot, s);
-    hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(1024), 0, s, ctx->partials, g.slice_blocks, ctx->st);
+    hipLaunchKernelGGL(k_fin_alpha, dim3(ctx->ninst), dim3(256), 0, s, S, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
-    hipLaunchKernelGGL(k_pcg_update, dim3(g.upd_blocks), dim3(256), 0, s, 3 * ctx->nv, ctx->x, ctx->r,
-                       (const float *)ctx->p, ctx->q, ctx->dinv, ctx->st, ctx->partials);
+    hipLaunchKernelGGL(k_pcg_update, dim3(g.vblocks), dim3(256), 0, s, S, ctx->x, ctx->r, (const float *)ctx->p,
+                       ctx->q, ctx->dinv, ctx->st, ctx->partials);
     ctx->prof.end(slot, s);
-    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(1024), 0, s, ctx->partials, g.upd_blocks, ctx->st);
+    hipLaunchKernelGGL(k_fin_beta, dim3(ctx->ninst), dim3(256), 0, s, S, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_DIR, s);
-    hipLaunchKernelGGL(k_pcg_dir, dim3(g.row_blocks), dim3(256), 0, s, ctx->nv, ctx->r, ctx->p, ctx->dinv,
-                       ctx->st);
+    hipLaunchKernelGGL(k_pcg_dir, dim3(g.vblocks), dim3(256), 0, s, S, ctx->r, ctx->p, ctx->dinv, ctx->st);
     ctx->prof.end(slot, s);
 }
 
-// Residuals always use the FP64 blocks.  mode 0 starts a sweep from x,
-// mode 1 writes ||b - A x||^2 and ||b||^2 to out2.
-static void launch_residual(Ctx *ctx, const SpmvArgs &M, const Grids &g, const double *b, const double *x,
-                            int mode, double *out2, hipStream_t s) {
+// Residuals always use the FP64 blocks.  mode 0 starts a sweep from x for
+// the flagged instances (restart == nullptr: all), mode 1 writes
+// ||b - A x||^2 and ||b||^2 of every instance to out2.
+static void launch_residual(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, const uint8_t *restart,
+                            const double *b, const double *x, int mode, double *out2, hipStream_t s) {
     using TB = double;
     if (mode == 0) {
-        hipLaunchKernelGGL((k_residual<TB, 0>), dim3(g.slice_blocks), dim3(256), 0, s, M, b, x, ctx->r, ctx->p,
-                           ctx->dinv, ctx->partials);
-        hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(1024), 0, s, ctx->partials, g.slice_blocks, ctx->st);
+        hipLaunchKernelGGL((k_residual<TB, 0>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b, x, ctx->r,
+                           ctx->p, ctx->dinv, ctx->partials);
+        hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 1, restart, ctx->partials, ctx->st);
     } else {
-        hipLaunchKernelGGL((k_residual<TB, 1>), dim3(g.slice_blocks), dim3(256), 0, s, M, b, x, ctx->r, ctx->p,
-                           ctx->dinv, ctx->partials);
-        hipLaunchKernelGGL(k_fin_check, dim3(1), dim3(1024), 0, s, ctx->partials, g.slice_blocks, out2);
+        hipLaunchKernelGGL((k_residual<TB, 1>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b, x, ctx->r,
+                           ctx->p, ctx->dinv, ctx->partials);
+        hipLaunchKernelGGL(k_fin_check, dim3(ctx->ninst), dim3(256), 0, s, S, ctx->partials, out2);
     }
+}
+
+static void launch_start_zero(Ctx *ctx, const Sched &S, const Grids &g, const uint8_t *restart, const double *b,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_start_zero, dim3(g.vblocks), dim3(256), 0, s, S, restart, b, ctx->x, ctx->r, ctx->p,
+                       ctx->dinv, ctx->partials);
+    hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 0, restart, ctx->partials, ctx->st);
 }
 
 // Capture `chunk` iterations on the context's capture stream.
 template <typename TB>
-static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Grids &g, int chunk, int variant) {
+static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, int chunk,
+                               int variant) {
     if (!ctx->cap_stream) PC_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
-    if (!ctx->gev[variant][0])
-        for (int k = 0; k < 6; ++k) PC_HIP(hipEventCreate(&ctx->gev[variant][k]));
     if (ctx->gexec[variant]) {
         (void)hipGraphExecDestroy(ctx->gexec[variant]);
         ctx->gexec[variant] = nullptr;
     }
+    const int saved = ctx->prof.every;
+    ctx->prof.every = 0;  // no profiler events inside the graph
     hipStream_t cs = ctx->cap_stream;
     PC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    for (int c = 0; c < chunk; ++c) launch_iter<TB>(ctx, M, g, cs, c == 0 ? ctx->gev[variant] : nullptr);
+    for (int c = 0; c < chunk; ++c) launch_iter<TB>(ctx, M, S, g, cs);
     hipGraph_t graph = nullptr;
-    PC_HIP(hipStreamEndCapture(cs, &graph));
+    hipError_t ec = hipStreamEndCapture(cs, &graph);
+    ctx->prof.every = saved;
+    if (ec != hipSuccess) {
+        ctx->err = std::string("hipStreamEndCapture: ") + hipGetErrorString(ec);
+        return PC_ERR_HIP;
+    }
     hipError_t e = hipGraphInstantiate(&ctx->gexec[variant], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
@@ -531,27 +660,8 @@ static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Grids &g, int 
     ctx->gkey[variant] = M.jval;
     ctx->gkey_dtype[variant] = (int)sizeof(TB);
     ctx->gkey_chunk[variant] = chunk;
+    ctx->gkey_sched[variant] = ctx->sched_version;
     return PC_OK;
-}
-
-// Add the graph's event-pair timings (first iteration of the chunk) to the
-// profiler statistics; call after the stream has been synchronised.
-static void harvest_graph_events(Ctx *ctx, int variant) {
-    if (ctx->prof.every <= 0) return;
-    const int kinds[3] = {PK_SPMV, PK_UPDATE, PK_DIR};
-    for (int q = 0; q < 3; ++q) {
-        float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ctx->gev[variant][2 * q], ctx->gev[variant][2 * q + 1]) != hipSuccess) {
-            (void)hipGetLastError();
-            continue;
-        }
-        Prof &P = ctx->prof;
-        const int k = kinds[q];
-        if (P.count[k] == 0 || ms < P.min_ms[k]) P.min_ms[k] = ms;
-        if (P.count[k] == 0 || ms > P.max_ms[k]) P.max_ms[k] = ms;
-        P.sum_ms[k] += ms;
-        P.count[k] += 1;
-    }
 }
 
 pc_status spmv_run(Ctx *ctx, const double *xin, double *y, bool solver, hipStream_t s) {
@@ -560,11 +670,18 @@ pc_status spmv_run(Ctx *ctx, const double *xin, double *y, bool solver, hipStrea
         return PC_ERR_ARG;
     }
     const SpmvArgs M = spmv_args(ctx, !solver);
+    const Sched S = sched_args(ctx);
     const Grids g = grids(ctx);
     switch (solver ? ctx->dtype : PC_F64) {
-        case PC_F64: hipLaunchKernelGGL(k_spmv_apply<double>, dim3(g.slice_blocks), dim3(256), 0, s, M, xin, y); break;
-        case PC_F32: hipLaunchKernelGGL(k_spmv_apply<float>, dim3(g.slice_blocks), dim3(256), 0, s, M, xin, y); break;
-        case PC_BF16: hipLaunchKernelGGL(k_spmv_apply<bf16_t>, dim3(g.slice_blocks), dim3(256), 0, s, M, xin, y); break;
+        case PC_F64:
+            hipLaunchKernelGGL(k_spmv_apply<double>, dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, xin, y);
+            break;
+        case PC_F32:
+            hipLaunchKernelGGL(k_spmv_apply<float>, dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, xin, y);
+            break;
+        case PC_BF16:
+            hipLaunchKernelGGL(k_spmv_apply<bf16_t>, dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, xin, y);
+            break;
     }
     PC_HIP(hipGetLastError());
     return PC_OK;
@@ -577,18 +694,33 @@ pc_status read_status(Ctx *ctx, hipStream_t s, int *bits) {
     return PC_OK;
 }
 
-// CG from the start in ctx->x (warm) or from zero, until the recursive
-// residual meets the tolerance; then the residual is recomputed from x with
-// FP64 accumulation, and if that true residual misses the tolerance (rounding
-// drift of the recurrence) CG restarts from x with the true residual, up to
-// max_sweeps times.
+static pc_status read_states(Ctx *ctx, hipStream_t s) {
+    PC_HIP(hipMemcpyAsync(ctx->st_host, ctx->st, sizeof(PcgState) * ctx->ninst, hipMemcpyDeviceToHost, s));
+    PC_HIP(hipStreamSynchronize(s));
+    return PC_OK;
+}
+
+static pc_status upload_flags(Ctx *ctx, const std::vector<uint8_t> &f, hipStream_t s) {
+    for (int i = 0; i < ctx->ninst; ++i) ctx->restart_h[i] = f[i];
+    PC_HIP(hipMemcpyAsync(ctx->restart, ctx->restart_h, (size_t)ctx->ninst, hipMemcpyHostToDevice, s));
+    return PC_OK;
+}
+
+// CG on every instance from the start in ctx->x (warm) or from zero, until
+// each instance's recursive residual meets its threshold; then the residual
+// of every instance is recomputed with the FP64 blocks, and instances whose
+// true residual misses the tolerance restart from x (iterative refinement),
+// up to max_sweeps sweeps.  Per-instance results go to ctx->inst_info; info
+// receives the aggregate (total iterations of the slowest instance, largest
+// residuals).
 template <typename TB>
 static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve_opts *o, pc_solve_info *info,
                            hipStream_t s) {
     const SpmvArgs M = spmv_args(ctx, false);
     const SpmvArgs Mhi = spmv_args(ctx, true);
+    const Sched S = sched_args(ctx);
     const Grids g = grids(ctx);
-    const int nv = ctx->nv;
+    const int nv = ctx->nv, ninst = ctx->ninst;
     const double tol = o ? o->tol : 1e-6;
     const int maxit = (o && o->maxit > 0) ? o->maxit : 20000;
     int warm = o ? o->warm : 0;
@@ -598,108 +730,289 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
     const int max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : (lowp ? 40 : 4);
     const int64_t n3 = 3 * (int64_t)nv;
 
-    if (warm)
-        hipLaunchKernelGGL(k_copy_d, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, dv, ctx->x);
-    int total_iters = 0, sweeps = 0, fallback = 0;
-    bool inner_hi = false;
-    PcgState h{};
-    double res2[2] = {0.0, 0.0};
-    double *out2 = ctx->res2;
-    for (;;) {
-        hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, ctx->st, tol, rho, maxit - total_iters);
-        if (warm)
-            launch_residual(ctx, Mhi, g, b, ctx->x, 0, nullptr, s);
-        else {
-            hipLaunchKernelGGL(k_pcg_start_zero, dim3(g.row_blocks), dim3(256), 0, s, nv, b, ctx->x, ctx->r,
-                               ctx->p, ctx->dinv, ctx->partials);
-            hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(1024), 0, s, ctx->partials, g.row_blocks, ctx->st);
+    std::vector<int> iters(ninst, 0), sweeps(ninst, 0), fallback(ninst, 0), wused(ninst, 0);
+    std::vector<uint8_t> active(ninst, 1);
+    std::vector<double> res2(2 * ninst, 0.0);
+    std::vector<int> maxit_h(ninst, maxit);
+    pc_status st;
+
+    int warm_kind = 0;
+    if (warm == 2) {
+        // learned start from the previous increment held in dv
+        if (!ctx->mlp || !ctx->last_x) {
+            ctx->err = "learned warm start requested without parameters or an assembled state";
+            return PC_ERR_ARG;
         }
+        int used = 0;
+        if ((st = mlp_start(ctx, ctx->mlp, ctx->last_x, ctx->last_v, b, dv, ctx->x, &used, s))) return st;
+        warm_kind = used;
+    } else if (warm) {
+        hipLaunchKernelGGL(k_copy_d, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, dv, ctx->x);
+        warm_kind = 1;
+    }
+    for (int i = 0; i < ninst; ++i) wused[i] = warm_kind;
+
+    // first start of every instance
+    PC_HIP(hipMemcpyAsync(ctx->maxit_d, maxit_h.data(), sizeof(int) * ninst, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_state_init, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, ctx->st,
+                       (const uint8_t *)nullptr, tol, rho, ctx->maxit_d);
+    if (warm_kind) {
+        launch_residual(ctx, Mhi, S, g, nullptr, b, ctx->x, 0, nullptr, s);
         PC_HIP(hipGetLastError());
-        PC_HIP(hipMemcpyAsync(ctx->st_host, ctx->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-        PC_HIP(hipStreamSynchronize(s));
-        h = *ctx->st_host;
-        ++sweeps;
+        if ((st = read_states(ctx, s))) return st;
+        // a start worse than zero in residual norm is replaced by the zero start
+        std::vector<uint8_t> worse(ninst, 0);
+        bool any = false;
+        for (int i = 0; i < ninst; ++i) {
+            const PcgState &h = ctx->st_host[i];
+            if (!(h.flags & 2) && h.rr0 > h.bb && h.bb > 0.0) {
+                worse[i] = 1;
+                wused[i] = 0;
+                any = true;
+            }
+        }
+        if (any) {
+            if ((st = upload_flags(ctx, worse, s))) return st;
+            hipLaunchKernelGGL(k_state_init, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, ctx->st, ctx->restart,
+                               tol, rho, ctx->maxit_d);
+            launch_start_zero(ctx, S, g, ctx->restart, b, s);
+        }
+    } else {
+        launch_start_zero(ctx, S, g, nullptr, b, s);
+    }
+    PC_HIP(hipGetLastError());
+    for (int i = 0; i < ninst; ++i) sweeps[i] = 1;
+    bool inner_hi = false;
+    int guard = 0;
+    for (;;) {
+        if ((st = read_states(ctx, s))) return st;
+        // iterate until every instance is done
         const int variant = inner_hi ? 1 : 0;
         const bool graph = ctx->graph_chunk > 0;
         if (graph) {
             const SpmvArgs &Mv = inner_hi ? Mhi : M;
             const int want_size = inner_hi ? (int)sizeof(double) : (int)sizeof(TB);
             if (!ctx->gexec[variant] || ctx->gkey[variant] != Mv.jval || ctx->gkey_dtype[variant] != want_size ||
-                ctx->gkey_chunk[variant] != ctx->graph_chunk) {
-                pc_status cst = inner_hi ? capture_chunk<double>(ctx, Mhi, g, ctx->graph_chunk, variant)
-                                         : capture_chunk<TB>(ctx, M, g, ctx->graph_chunk, variant);
-                if (cst) return cst;
+                ctx->gkey_chunk[variant] != ctx->graph_chunk || ctx->gkey_sched[variant] != ctx->sched_version) {
+                st = inner_hi ? capture_chunk<double>(ctx, Mhi, S, g, ctx->graph_chunk, variant)
+                              : capture_chunk<TB>(ctx, M, S, g, ctx->graph_chunk, variant);
+                if (st) return st;
             }
         }
-        while (!h.done && h.iters < h.maxit) {
+        for (;;) {
+            bool all_done = true;
+            int most = 0;
+            for (int i = 0; i < ninst; ++i) {
+                const PcgState &h = ctx->st_host[i];
+                if (!h.done) {
+                    all_done = false;
+                    most = std::max(most, h.iters);
+                }
+            }
+            if (all_done) break;
             if (graph) {
                 PC_HIP(hipGraphLaunch(ctx->gexec[variant], s));
             } else {
-                int chunk = check > 0 ? check : std::min(256, std::max(16, (total_iters + h.iters) / 4));
-                chunk = std::min(chunk, h.maxit - h.iters);
+                int chunk = check > 0 ? check : std::min(256, std::max(16, most / 4));
                 for (int c = 0; c < chunk; ++c) {
                     if (inner_hi)
-                        launch_iter<double>(ctx, Mhi, g, s);
+                        launch_iter<double>(ctx, Mhi, S, g, s);
                     else
-                        launch_iter<TB>(ctx, M, g, s);
+                        launch_iter<TB>(ctx, M, S, g, s);
                 }
             }
             PC_HIP(hipGetLastError());
-            PC_HIP(hipMemcpyAsync(ctx->st_host, ctx->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-            PC_HIP(hipStreamSynchronize(s));
-            if (graph)
-                harvest_graph_events(ctx, variant);
-            else
-                ctx->prof.harvest();
-            h = *ctx->st_host;
+            if ((st = read_states(ctx, s))) return st;
+            ctx->prof.harvest();
         }
-        total_iters += h.iters;
-        // true residual of the current iterate
-        launch_residual(ctx, Mhi, g, b, ctx->x, 1, out2, s);
+        for (int i = 0; i < ninst; ++i)
+            if (active[i]) iters[i] += ctx->st_host[i].iters;
+        // true residual of every instance
+        launch_residual(ctx, Mhi, S, g, nullptr, b, ctx->x, 1, ctx->res2, s);
         PC_HIP(hipGetLastError());
-        PC_HIP(hipMemcpyAsync(res2, out2, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        PC_HIP(hipMemcpyAsync(res2.data(), ctx->res2, sizeof(double) * 2 * ninst, hipMemcpyDeviceToHost, s));
         PC_HIP(hipStreamSynchronize(s));
-        const bool true_ok = res2[0] <= tol * tol * res2[1];
-        if ((h.flags & 1) && !inner_hi && ctx->hi_valid && !true_ok) {
-            // rounding of the stored blocks made the inner operator lose
-            // definiteness: continue the sweeps on the FP64 blocks
-            inner_hi = true;
-            fallback = 1;
-            h.flags = 0;
-            warm = 1;
-            continue;
+        std::vector<uint8_t> again(ninst, 0);
+        bool any = false, any_breakdown = false;
+        for (int i = 0; i < ninst; ++i) {
+            const PcgState &h = ctx->st_host[i];
+            active[i] = 0;
+            const bool ok = res2[2 * i] <= tol * tol * res2[2 * i + 1];
+            if (ok || res2[2 * i + 1] == 0.0 || (h.flags & 2) || iters[i] >= maxit) continue;
+            if (h.flags & 1) {
+                if (!inner_hi && ctx->hi_valid) {
+                    any_breakdown = true;
+                    fallback[i] = 1;
+                } else {
+                    continue;
+                }
+            } else if (sweeps[i] >= max_sweeps) {
+                continue;
+            }
+            again[i] = 1;
+            active[i] = 1;
+            any = true;
         }
-        if (h.flags || true_ok || res2[1] == 0.0 || total_iters >= maxit || sweeps >= max_sweeps) break;
-        warm = 1;
+        if (!any || ++guard > 64) break;
+        if (any_breakdown) inner_hi = true;  // low-precision operator lost definiteness: FP64 blocks from here on
+        for (int i = 0; i < ninst; ++i) {
+            if (again[i]) {
+                sweeps[i] += 1;
+                maxit_h[i] = maxit - iters[i];
+            }
+        }
+        PC_HIP(hipMemcpyAsync(ctx->maxit_d, maxit_h.data(), sizeof(int) * ninst, hipMemcpyHostToDevice, s));
+        if ((st = upload_flags(ctx, again, s))) return st;
+        hipLaunchKernelGGL(k_state_init, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, ctx->st, ctx->restart, tol,
+                           rho, ctx->maxit_d);
+        launch_residual(ctx, Mhi, S, g, ctx->restart, b, ctx->x, 0, nullptr, s);
+        PC_HIP(hipGetLastError());
+    }
+    // b = 0: the solution is 0 whatever the start
+    std::vector<uint8_t> zero(ninst, 0);
+    bool anyzero = false;
+    for (int i = 0; i < ninst; ++i)
+        if (res2[2 * i + 1] == 0.0 && !(ctx->st_host[i].flags & 2)) {
+            zero[i] = 1;
+            anyzero = true;
+            res2[2 * i] = 0.0;
+        }
+    if (anyzero) {
+        if ((st = upload_flags(ctx, zero, s))) return st;
+        hipLaunchKernelGGL(k_zero_rows, dim3(g.vblocks), dim3(256), 0, s, S, ctx->restart, ctx->x);
     }
     hipLaunchKernelGGL(k_copy_d, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, ctx->x, dv);
-    const double bnorm = sqrt(res2[1]);
-    if (res2[1] == 0.0 && !(h.flags & 2)) {  // b = 0: the solution is 0 whatever the start
-        PC_HIP(hipMemsetAsync(dv, 0, sizeof(double) * (size_t)n3, s));
-        res2[0] = 0.0;
-    }
+    PC_HIP(hipGetLastError());
     PC_HIP(hipStreamSynchronize(s));
-    const double rel_true = bnorm > 0 ? sqrt(res2[0]) / bnorm : sqrt(res2[0]);
-    if (info) {
-        info->iters = total_iters;
-        info->sweeps = sweeps;
-        info->bnorm = bnorm;
-        info->rel_res_recursive = bnorm > 0 ? sqrt(h.rr) / bnorm : 0.0;
-        info->rel_res_true = rel_true;
-        info->fallback = fallback;
+    pc_status ret = PC_OK;
+    pc_solve_info agg{};
+    double bb_all = 0.0, tt_all = 0.0;
+    for (int i = 0; i < ninst; ++i) {
+        const PcgState &h = ctx->st_host[i];
+        pc_solve_info &I = ctx->inst_info[i];
+        const double bn = sqrt(res2[2 * i + 1]);
+        I.iters = iters[i];
+        I.sweeps = sweeps[i];
+        I.bnorm = bn;
+        I.rel_res_recursive = bn > 0 ? sqrt(h.rr) / bn : 0.0;
+        I.rel_res_true = bn > 0 ? sqrt(res2[2 * i]) / bn : sqrt(res2[2 * i]);
+        I.fallback = fallback[i];
+        I.warm_used = wused[i];
+        agg.iters = std::max(agg.iters, I.iters);
+        agg.sweeps = std::max(agg.sweeps, I.sweeps);
+        agg.rel_res_recursive = std::max(agg.rel_res_recursive, I.rel_res_recursive);
+        agg.rel_res_true = std::max(agg.rel_res_true, I.rel_res_true);
+        agg.fallback |= I.fallback;
+        agg.warm_used = std::max(agg.warm_used, I.warm_used);
+        bb_all += res2[2 * i + 1];
+        tt_all += res2[2 * i];
+        if (ret == PC_OK) {
+            if (h.flags & 2) {
+                ctx->err = "non-finite value in the CG recurrence";
+                ret = PC_ERR_NONFINITE;
+            } else if ((h.flags & 1) && !(I.rel_res_true <= tol)) {
+                ctx->err = "CG breakdown: p.Ap <= 0 (matrix not positive definite)";
+                ret = PC_ERR_NOT_CONVERGED;
+            } else if (!(I.rel_res_true <= tol) && bn > 0) {
+                ctx->err = "CG did not reach the tolerance within maxit iterations";
+                ret = PC_ERR_NOT_CONVERGED;
+            }
+        }
     }
-    if (h.flags & 2) {
-        ctx->err = "non-finite value in the CG recurrence";
-        return PC_ERR_NONFINITE;
+    agg.bnorm = sqrt(bb_all);
+    if (ninst == 1) agg = ctx->inst_info[0];
+    if (info) *info = agg;
+    (void)tt_all;
+    return ret;
+}
+
+// Time `iters` CG iterations from the zero start on the assembled system
+// with the current schedule (milliseconds, HIP events on the stream).
+template <typename TB>
+static pc_status time_iters(Ctx *ctx, const double *b, int iters, float *ms, hipStream_t s) {
+    const SpmvArgs M = spmv_args(ctx, false);
+    const Sched S = sched_args(ctx);
+    const Grids g = grids(ctx);
+    const int ninst = ctx->ninst;
+    std::vector<int> big(ninst, 1 << 30);
+    PC_HIP(hipMemcpyAsync(ctx->maxit_d, big.data(), sizeof(int) * ninst, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_state_init, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, ctx->st,
+                       (const uint8_t *)nullptr, 0.0, 0.0, ctx->maxit_d);
+    launch_start_zero(ctx, S, g, nullptr, b, s);
+    if (ctx->graph_chunk > 0 &&
+        (!ctx->gexec[0] || ctx->gkey[0] != M.jval || ctx->gkey_dtype[0] != (int)sizeof(TB) ||
+         ctx->gkey_chunk[0] != ctx->graph_chunk || ctx->gkey_sched[0] != ctx->sched_version)) {
+        pc_status st = capture_chunk<TB>(ctx, M, S, g, ctx->graph_chunk, 0);
+        if (st) return st;
     }
-    if (h.flags & 1) {
-        ctx->err = "CG breakdown: p.Ap <= 0 (matrix not positive definite)";
-        return PC_ERR_NOT_CONVERGED;
+    hipEvent_t e0, e1;
+    PC_HIP(hipEventCreate(&e0));
+    PC_HIP(hipEventCreate(&e1));
+    PC_HIP(hipEventRecord(e0, s));
+    if (ctx->graph_chunk > 0) {
+        for (int done = 0; done < iters; done += ctx->graph_chunk) PC_HIP(hipGraphLaunch(ctx->gexec[0], s));
+    } else {
+        const int saved = ctx->prof.every;
+        ctx->prof.every = 0;
+        for (int c = 0; c < iters; ++c) launch_iter<TB>(ctx, M, S, g, s);
+        ctx->prof.every = saved;
     }
-    if (!(rel_true <= tol) && bnorm > 0) {
-        ctx->err = "CG did not reach the tolerance within maxit iterations";
-        return PC_ERR_NOT_CONVERGED;
+    PC_HIP(hipEventRecord(e1, s));
+    PC_HIP(hipEventSynchronize(e1));
+    PC_HIP(hipEventElapsedTime(ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return PC_OK;
+}
+
+// Autotuner: try every (slices per SpMV block, rows per vector block, graph
+// chunk) candidate on the assembled system, keep the fastest per iteration.
+pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, float *best_ms, hipStream_t s) {
+    if (!ctx->assembled) {
+        ctx->err = "pc_autotune: nothing assembled";
+        return PC_ERR_ARG;
     }
+    const int spbs[4] = {1, 2, 4, 8};
+    const int rpbs[3] = {256, 512, 1024};
+    const int chunks[2] = {0, 32};
+    float best = 1e30f;
+    int bs = ctx->spb, br = ctx->rpb, bc = ctx->graph_chunk;
+    const bool was = ctx->assembled;
+    for (int c : chunks)
+        for (int sp : spbs)
+            for (int rp : rpbs) {
+                ctx->spb = sp;
+                ctx->rpb = rp;
+                ctx->graph_chunk = c;
+                pc_status st = build_schedule(ctx);
+                ctx->assembled = was;
+                if (st) return st;
+                float ms = 0.0f;
+                switch (ctx->dtype) {
+                    case PC_F64: st = time_iters<double>(ctx, b, iters, &ms, s); break;
+                    case PC_F32: st = time_iters<float>(ctx, b, iters, &ms, s); break;
+                    case PC_BF16: st = time_iters<bf16_t>(ctx, b, iters, &ms, s); break;
+                }
+                if (st) return st;
+                if (ms < best) {
+                    best = ms;
+                    bs = sp;
+                    br = rp;
+                    bc = c;
+                }
+            }
+    ctx->spb = bs;
+    ctx->rpb = br;
+    ctx->graph_chunk = bc;
+    pc_status st = build_schedule(ctx);
+    ctx->assembled = was;
+    if (st) return st;
+    if (chosen) {
+        chosen[0] = bs;
+        chosen[1] = br;
+        chosen[2] = bc;
+    }
+    if (best_ms) *best_ms = best / (float)iters;
     return PC_OK;
 }
 

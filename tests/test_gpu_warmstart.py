@@ -1,0 +1,149 @@
+"""GPU parity of the learned warm start (features, BF16-MFMA forward and
+backward, Adam, learned CG start) against the FP64 oracle in oracle/mlp.py,
+through the C ABI.
+
+Bars: features and forward outputs within bf16 rounding of the oracle's
+values computed with the same rounding points; per-tensor gradients to 3e-2
+relative (bf16 operands, FP32 vs FP64 accumulation); the learned start
+still solves Eq. 3 to the tolerance through the oracle's matrix."""
+import numpy as np
+import pytest
+
+from gpu_helpers import random_velocity, require_gpu, sheet, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2008_00409_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def M():
+    from oracle import mlp
+    return mlp
+
+
+def mean_edge(c):
+    e = 0.0
+    for k in range(3):
+        a, b = c.tris[:, k], c.tris[:, (k + 1) % 3]
+        e += np.linalg.norm(c.rest[a] - c.rest[b], axis=1).sum()
+    return e / (3 * c.tris.shape[0])
+
+
+def random_params(M, seed):
+    p = M.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    p[3][0] *= 30.0
+    for k in range(4):
+        p[k][1] = 0.05 * rng.normal(size=p[k][1].shape)
+    return p
+
+
+def setup_case(torch, B, oracle_mod, M, nx=29, ny=23, seed=3):
+    c = sheet(nx, ny, seed=seed, flips=0.1)      # 667 vertices: 42 tiles, ragged last tile
+    P = oracle_mod.Problem.from_cloth(c)
+    v = random_velocity(c, 0.05, seed=seed)
+    A = P.assemble(c.x0, v)
+    dvp = 0.01 * np.random.default_rng(seed).normal(size=c.rest.shape)
+    dvp[c.pinned == 1] = 0
+    ctx = B.Context.from_cloth(c)
+    x_d, v_d, dvp_d = to_dev(torch, c.x0), to_dev(torch, v), to_dev(torch, dvp)
+    b_d = ctx.cloth_assemble(x_d, v_d, "f32")
+    ell = mean_edge(c)
+    X = M.features(P.rowptr, P.colidx, c.x0, v, A.b, A.diag, c.mass, c.pinned, dvp, ell, c.h)
+    return c, P, A, v, dvp, ctx, (x_d, v_d, dvp_d, b_d), ell, X
+
+
+def test_mfma_lane_layout(torch, B):
+    from paper_2008_00409_amd import meshgen as mg
+    c = mg.config_tiny()
+    ctx = B.Context.from_cloth(c)
+    try:
+        out = ctx.mfma_probe()
+        idx = np.arange(16)
+        np.testing.assert_array_equal(out[0], idx[:, None] * 16 + idx[None, :])
+        np.testing.assert_array_equal(out[1], idx[:, None] * 16 + idx[None, :])
+    finally:
+        ctx.close()
+
+
+def test_features_match_oracle(torch, B, oracle_mod, M):
+    c, P, A, v, dvp, ctx, (x_d, v_d, dvp_d, b_d), ell, X = setup_case(torch, B, oracle_mod, M)
+    try:
+        F = ctx.ws_features(x_d, v_d, b_d, dvp_d).cpu().numpy().astype(np.uint16)
+        got = (F.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        assert np.all(got[:, 27:] == 0)
+        want = M.bf16_round(X)
+        # within one bf16 ulp (values computed in FP64 on both sides, summation order differs)
+        ulp = np.maximum(np.abs(want), 1e-30) * 2.0 ** -7
+        assert np.all(np.abs(got[:, :27] - want) <= ulp + 1e-30)
+    finally:
+        ctx.close()
+
+
+def test_forward_matches_oracle(torch, B, oracle_mod, M):
+    c, P, A, v, dvp, ctx, (x_d, v_d, dvp_d, b_d), ell, X = setup_case(torch, B, oracle_mod, M)
+    try:
+        params = random_params(M, 7)
+        ctx.ws_set_params(M.flatten(params))
+        dv0 = ctx.ws_predict(x_d, v_d, b_d, dvp_d).cpu().numpy()
+        y, hs = M.forward([[M.bf16_round(W), cb] for W, cb in params], X, bf16=True)
+        want = M.start_from_output(y, dvp, c.pinned, ell / c.h)
+        corr_g = (dv0 - dvp)[c.pinned == 0]
+        corr_w = (want - dvp)[c.pinned == 0]
+        err = np.linalg.norm(corr_g - corr_w) / np.linalg.norm(corr_w)
+        assert err < 2e-2, err
+        assert np.all(dv0[c.pinned == 1] == 0)
+        # round trip of the parameters
+        np.testing.assert_array_equal(ctx.ws_get_params(), M.flatten(params).astype(np.float32))
+    finally:
+        ctx.close()
+
+
+def test_gradient_matches_oracle(torch, B, oracle_mod, M):
+    c, P, A, v, dvp, ctx, (x_d, v_d, dvp_d, b_d), ell, X = setup_case(torch, B, oracle_mod, M)
+    try:
+        params = random_params(M, 11)
+        ctx.ws_set_params(M.flatten(params))
+        g_gpu, loss_gpu = ctx.ws_gradient(x_d, v_d, b_d, dvp_d)
+        pb = [[M.bf16_round(W), cb] for W, cb in params]
+        y, hs = M.forward(pb, X, bf16=True)
+        sv = ell / c.h
+        dv0 = M.start_from_output(y, dvp, c.pinned, sv)
+        L, gy = M.energy_loss_grad(lambda z: P.spmv(A, z), A.b, A.diag, dv0, c.pinned, sv)
+        grads = M.backward(pb, X, hs, gy, bf16=True)
+        assert loss_gpu == pytest.approx(L, rel=2e-2, abs=1e-3 * abs(L))
+        g_or = M.flatten(grads)
+        o = 0
+        for a, bdim in M.SHAPES:
+            for n in (a * bdim, bdim):
+                seg_g, seg_o = g_gpu[o:o + n], g_or[o:o + n]
+                rel = np.linalg.norm(seg_g - seg_o) / max(np.linalg.norm(seg_o), 1e-30)
+                assert rel < 3e-2, (o, n, rel)
+                o += n
+    finally:
+        ctx.close()
+
+
+def test_training_lowers_the_loss_and_learned_start_solves(torch, B, oracle_mod, M):
+    c, P, A, v, dvp, ctx, (x_d, v_d, dvp_d, b_d), ell, X = setup_case(torch, B, oracle_mod, M)
+    try:
+        ctx.ws_set_params(M.flatten(M.init_params(3)))
+        losses = [ctx.ws_train_step(x_d, v_d, b_d, dvp_d, lr=3e-3) for _ in range(60)]
+        assert losses[-1] < losses[0] - 0.05 * abs(losses[0]), (losses[0], losses[-1])
+        # learned start through cloth_pcg_solve: dv holds the previous increment on entry
+        dv = dvp_d.clone()
+        dv, info = ctx.cloth_pcg_solve(b_d, dv=dv, tol=1e-7, warm="learned")
+        assert info["warm_used"] in (0, 2)
+        assert P.residual(A, dv.cpu().numpy()) <= 1e-7 * (1 + 1e-6)
+    finally:
+        ctx.close()
