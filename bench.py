@@ -98,10 +98,9 @@ def train_warm_start(binding, meshgen, steps, adam_per_step, lr, log):
     solver advances with the learned start."""
     import torch
 
-    from oracle import mlp as oracle_mlp  # only its seeded initial weights (init_params)
     c = meshgen.config_medium()
     ctx = binding.Context.from_cloth(c)
-    ctx.ws_set_params(oracle_mlp.flatten(oracle_mlp.init_params(0)))
+    ctx.ws_set_params(binding.Context.ws_init_params(0))
     x = torch.from_numpy(c.x0.copy()).cuda()
     v = torch.zeros_like(x)
     dvp = torch.zeros_like(x)

@@ -30,6 +30,9 @@ ABI_SYMBOLS = ["pc_create", "pc_destroy", "pc_set_params", "pc_last_error", "pc_
                "pc_ws_train_step", "pc_mfma_probe", "pc_get_option", "pc_set_instances", "pc_get_instance_info",
                "pc_autotune"]
 WS_PARAMS = 10307
+# Warm-start network layer shapes (inputs x outputs); the flat parameter
+# vector holds, per layer, W row-major then the bias.
+WS_SHAPES = [(27, 64), (64, 64), (64, 64), (64, 3)]
 WARM = {"zero": 0, "prev": 1, "given": 1, "learned": 2}
 PC_OPT_GRAPH_CHUNK, PC_OPT_SPMV_SLICES_PER_BLOCK, PC_OPT_VECTOR_ROWS_PER_BLOCK = 0, 1, 2
 PROFILE_KINDS = ["spmv", "cg_update", "cg_dir", "row_assemble", "row_pattern", "assemble_all", "k6", "k7"]
@@ -279,6 +282,18 @@ class Context:
         return [infos[k].as_dict() for k in range(nsteps)]
 
     # -- learned warm start --------------------------------------------------
+    @staticmethod
+    def ws_init_params(seed=0):
+        """Seeded He-normal weights and zero biases in the flat layout; the last
+        layer is scaled by 1e-2 so that an untrained network starts CG at the
+        previous step's increment."""
+        rng = np.random.default_rng(seed)
+        parts = []
+        for k, (a, b) in enumerate(WS_SHAPES):
+            W = rng.normal(size=(a, b)) * np.sqrt(2.0 / a) * (1e-2 if k == len(WS_SHAPES) - 1 else 1.0)
+            parts += [W.ravel(), np.zeros(b)]
+        return np.concatenate(parts).astype(np.float32)
+
     def ws_set_params(self, flat):
         a = np.ascontiguousarray(flat, dtype=np.float32)
         assert a.size == WS_PARAMS

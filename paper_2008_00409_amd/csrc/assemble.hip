@@ -632,8 +632,11 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
             double Fy[3][2], Sy[3];
             tri_F(ys, sh, Fy);
             tri_stress(Fy, P.mu, P.lam, Sy);
-            const double sb0 = Sy[0] * sh.b[k][0] + Sy[1] * sh.b[k][1];
-            const double sb1 = Sy[1] * sh.b[k][0] + Sy[2] * sh.b[k][1];
+            // corner k's shape gradient, selected without indexing a private array
+            const double bk0 = k == 0 ? sh.b[0][0] : (k == 1 ? sh.b[1][0] : sh.b[2][0]);
+            const double bk1 = k == 0 ? sh.b[0][1] : (k == 1 ? sh.b[1][1] : sh.b[2][1]);
+            const double sb0 = Sy[0] * bk0 + Sy[1] * bk1;
+            const double sb1 = Sy[1] * bk0 + Sy[2] * bk1;
 #pragma unroll
             for (int a = 0; a < 3; ++a) L.fk[t][a] = -a0 * (Fy[a][0] * sb0 + Fy[a][1] * sb1);
         } else {
@@ -659,7 +662,11 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
             }
             if (hinge_eval(ys, th, g)) {
                 const double s = -2.0 * P.kb * ch * (th - tb);
-                L.fk[t][0] = s * g[k].x; L.fk[t][1] = s * g[k].y; L.fk[t][2] = s * g[k].z;
+                d3 gk = g[0];
+#pragma unroll
+                for (int q = 1; q < 4; ++q)
+                    if (q == k) gk = g[q];
+                L.fk[t][0] = s * gk.x; L.fk[t][1] = s * gk.y; L.fk[t][2] = s * gk.z;
             } else {
                 L.fk[t][0] = L.fk[t][1] = L.fk[t][2] = 0.0;
             }

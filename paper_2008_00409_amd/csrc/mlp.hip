@@ -345,7 +345,7 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(int ntiles, const short *X, c
 #pragma unroll
         for (int q = 0; q < MAXT; ++q) {
             const int tile = w + 4 * q;
-            if (tile >= MLP_GRAD_TILES) break;
+            if (tile >= MLP_GRAD_TILES) continue;       // uniform per wavefront
             const GradTile T = c_tiles[tile];
             const short *Hin = T.layer == 0 ? X : (T.layer == 1 ? H1 : (T.layer == 2 ? H2 : H3));
             const int win = T.layer == 0 ? 32 : 64;
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(int ntiles, const short *X, c
 #pragma unroll
     for (int q = 0; q < MAXT; ++q) {
         const int tile = w + 4 * q;
-        if (tile >= MLP_GRAD_TILES) break;
+        if (tile >= MLP_GRAD_TILES) continue;
         float *o = part + ((int64_t)blockIdx.x * MLP_GRAD_TILES + tile) * 256;
 #pragma unroll
         for (int i = 0; i < 4; ++i) o[(4 * (l / 16) + i) * 16 + l % 16] = acc[q][i];

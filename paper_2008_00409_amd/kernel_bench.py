@@ -1,0 +1,65 @@
+"""Fixed-work kernel driver for hardware-counter runs.
+
+Runs a bounded amount of the solver's work on one workload through the C ABI
+(one assembly, then a CG solve capped at ``--iters`` iterations) plus a
+plain device copy of known size, so that a counter profiler can take the
+bytes each kernel fetches and writes per dispatch and scale them against the
+copy, whose traffic is exactly 2 x its size.
+
+    python -m paper_2008_00409_amd.kernel_bench --workload large --blocks f32 --iters 50
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "batch"])
+    ap.add_argument("--blocks", default="f32", choices=["f32", "bf16", "f64"])
+    ap.add_argument("--iters", type=int, default=50, help="CG iterations (solve capped, tolerance unreachable)")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy")
+    ap.add_argument("--copies", type=int, default=5)
+    a = ap.parse_args(argv)
+
+    import torch
+
+    from . import binding, meshgen as mg
+
+    if not torch.cuda.is_available():
+        sys.exit("kernel_bench needs a GPU")
+    c = {"large": mg.config_large, "medium": mg.config_medium, "batch": mg.config_batch}[a.workload]()
+    ctx = binding.Context.from_cloth(c)
+    if a.workload == "batch":             # many independent cloths: per-instance CG scalars
+        ctx.set_instances([r[0] for r in c.sheet_ranges] + [c.nv])
+    x = torch.from_numpy(c.x0.copy()).cuda()
+    v = torch.from_numpy(c.v0.copy()).cuda()
+    print(f"# kernel_bench {c.name}: nv={c.nv} nt={c.nt} blocks={a.blocks} iters={a.iters}", flush=True)
+    b = ctx.cloth_assemble(x, v, a.blocks)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dv, info = ctx.cloth_pcg_solve(b, tol=1e-30, maxit=a.iters, raise_on_error=False, max_sweeps=1)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    print(f"# solve: {info['iters']} iterations in {t_solve * 1e3:.1f} ms (status {info['status']})", flush=True)
+
+    n = a.copy_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.copies):
+        torch.mul(src, 1.0, out=dst)      # elementwise copy kernel: reads and writes copy_mib MiB each
+    torch.cuda.synchronize()
+    t_copy = (time.perf_counter() - t0) / a.copies
+    print(json.dumps({"workload": c.name, "nv": c.nv, "blocks": a.blocks, "cg_iters": info["iters"],
+                      "solve_ms": t_solve * 1e3, "copy_bytes_each_way": n * 4,
+                      "copy_ms": t_copy * 1e3}), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
