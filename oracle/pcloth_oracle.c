@@ -588,13 +588,54 @@ static double dotn(int n, const double *a, const double *b) {
     return s;
 }
 
-/* Jacobi-preconditioned CG on A x = b from the initial guess in x.  Stops when
- * ||r_k|| <= tol ||b|| (recursive residual) or after maxit iterations.  b = 0
- * gives x = 0 and no iterations.  Returns 0 if converged, 1 if not.
- * out[0] = iterations, out[1] = recursive relative residual, out[2] = true
- * relative residual ||b - A x|| / ||b|| at exit. */
-int or_pcg(int nv, const int32_t *rowptr, const int32_t *colidx, const double *vals,
-           const double *b, const double *diag, double *x, double tol, int maxit, double *out) {
+/* Solve the 3x3 system M z = r by Gaussian elimination with partial pivoting
+ * (M row-major, left unchanged). */
+static void solve3(const double *M, const double *r, double *z) {
+    double a[3][4];
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) a[i][j] = M[3 * i + j];
+        a[i][3] = r[i];
+    }
+    for (int k = 0; k < 3; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < 3; ++i)
+            if (fabs(a[i][k]) > fabs(a[piv][k])) piv = i;
+        if (piv != k)
+            for (int j = 0; j < 4; ++j) { double t = a[k][j]; a[k][j] = a[piv][j]; a[piv][j] = t; }
+        for (int i = k + 1; i < 3; ++i) {
+            double f = a[i][k] / a[k][k];
+            for (int j = k; j < 4; ++j) a[i][j] -= f * a[k][j];
+        }
+    }
+    for (int i = 2; i >= 0; --i) {
+        double s = a[i][3];
+        for (int j = i + 1; j < 3; ++j) s -= a[i][j] * z[j];
+        z[i] = s / a[i][i];
+    }
+}
+
+/* Preconditioner application z = P^-1 r: precond 0 is Jacobi (P = diag(A)),
+ * precond 1 is block Jacobi (P = the 3x3 diagonal blocks A_ii). */
+static void apply_precond(int nv, const int32_t *rowptr, const int32_t *colidx, const double *vals,
+                          const double *diag, int precond, const double *r, double *z) {
+    if (precond == 0) {
+        for (int i = 0; i < 3 * nv; ++i) z[i] = r[i] / diag[i];
+        return;
+    }
+    for (int i = 0; i < nv; ++i) {
+        int p = find_block(rowptr, colidx, i, i);
+        solve3(vals + 9 * (size_t)p, r + 3 * i, z + 3 * i);
+    }
+}
+
+/* Preconditioned CG on A x = b from the initial guess in x (paper Sec. 2.5;
+ * preconditioner as in apply_precond).  Stops when ||r_k|| <= tol ||b||
+ * (recursive residual) or after maxit iterations.  b = 0 gives x = 0 and no
+ * iterations.  Returns 0 if converged, 1 if not.  out[0] = iterations,
+ * out[1] = recursive relative residual, out[2] = true relative residual
+ * ||b - A x|| / ||b|| at exit. */
+int or_pcg2(int nv, const int32_t *rowptr, const int32_t *colidx, const double *vals,
+            const double *b, const double *diag, double *x, double tol, int maxit, int precond, double *out) {
     int n = 3 * nv;
     double bnorm = sqrt(dotn(n, b, b));
     if (bnorm == 0.0) {
@@ -608,7 +649,7 @@ int or_pcg(int nv, const int32_t *rowptr, const int32_t *colidx, const double *v
     double *q = (double *)malloc(sizeof(double) * n);
     block_spmv(nv, rowptr, colidx, vals, x, q);
     for (int i = 0; i < n; ++i) r[i] = b[i] - q[i];
-    for (int i = 0; i < n; ++i) z[i] = r[i] / diag[i];
+    apply_precond(nv, rowptr, colidx, vals, diag, precond, r, z);
     memcpy(p, z, sizeof(double) * n);
     double rz = dotn(n, r, z);
     double rr = dotn(n, r, r);
@@ -617,7 +658,7 @@ int or_pcg(int nv, const int32_t *rowptr, const int32_t *colidx, const double *v
         block_spmv(nv, rowptr, colidx, vals, p, q);
         double alpha = rz / dotn(n, p, q);
         for (int i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
-        for (int i = 0; i < n; ++i) z[i] = r[i] / diag[i];
+        apply_precond(nv, rowptr, colidx, vals, diag, precond, r, z);
         double rz_new = dotn(n, r, z);
         rr = dotn(n, r, r);
         double beta = rz_new / rz;
@@ -633,6 +674,12 @@ int or_pcg(int nv, const int32_t *rowptr, const int32_t *colidx, const double *v
     out[2] = sqrt(tr) / bnorm;
     free(r); free(z); free(p); free(q);
     return sqrt(rr) <= tol * bnorm ? 0 : 1;
+}
+
+/* Jacobi-preconditioned CG (or_pcg2 with precond 0). */
+int or_pcg(int nv, const int32_t *rowptr, const int32_t *colidx, const double *vals,
+           const double *b, const double *diag, double *x, double tol, int maxit, double *out) {
+    return or_pcg2(nv, rowptr, colidx, vals, b, diag, x, tol, maxit, 0, out);
 }
 
 /* Run `maxit` CG iterations unconditionally (for timing a bounded sample). */
