@@ -75,15 +75,16 @@ def cpu_baseline(cloth, gpu_iters_per_step, seconds_budget=25.0):
                        f"same tolerance")}
 
 
-def time_steps(ctx, x, v, steps, warmup, blocks, tol, warm, prof_every):
+def time_steps(ctx, x, v, steps, warmup, blocks, tol, warm, prof_every, precond="jacobi", inner_rho=0.0):
     """Run warmup then timed steps; returns (elapsed s, infos, profile)."""
     import torch
+    kw = dict(dtype=blocks, tol=tol, warm=warm, precond=precond, inner_rho=inner_rho)
     if warmup:
-        ctx.cloth_step(x, v, nsteps=warmup, dtype=blocks, tol=tol, warm=warm)
+        ctx.cloth_step(x, v, nsteps=warmup, **kw)
     ctx.profile(prof_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = ctx.cloth_step(x, v, nsteps=steps, dtype=blocks, tol=tol, warm=warm)
+    infos = ctx.cloth_step(x, v, nsteps=steps, **kw)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = ctx.profile_read()
@@ -137,6 +138,10 @@ def main():
                     help="block storage of the project configuration")
     ap.add_argument("--warm", default="learned", choices=["zero", "prev", "learned"],
                     help="CG start of the project configuration")
+    ap.add_argument("--precond", default="block", choices=["jacobi", "block"],
+                    help="preconditioner of the project configuration")
+    ap.add_argument("--inner-rho", type=float, default=0.0,
+                    help="residual reduction per refinement sweep (0: library default)")
     ap.add_argument("--workload", default="large", choices=["large", "medium"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 / zero-start reference run")
@@ -189,9 +194,10 @@ def main():
     tune = None
     if args.autotune:
         b = ctx.cloth_assemble(x, v, args.blocks)
-        tune = ctx.autotune(b, iters=64)
+        tune = ctx.autotune(b, iters=64, precond=args.precond)
         log(f"# autotune: {tune}")
-    el, infos, prof = time_steps(ctx, x, v, args.steps, args.warmup, args.blocks, tol, args.warm, args.prof_every)
+    el, infos, prof = time_steps(ctx, x, v, args.steps, args.warmup, args.blocks, tol, args.warm, args.prof_every,
+                                 args.precond, args.inner_rho)
     rowptr, colidx = ctx.pattern()
     nnzb = int(colidx.numel())
     nv, nt, nh = ctx.nv, ctx.nt, ctx.nh
@@ -202,13 +208,15 @@ def main():
     # trajectory: one more step gives the previous increment, then the next
     # system is solved from each start to the same tolerance
     v_before = v.clone()
-    ctx.cloth_step(x, v, nsteps=1, dtype=args.blocks, tol=tol, warm=args.warm)
+    ctx.cloth_step(x, v, nsteps=1, dtype=args.blocks, tol=tol, warm=args.warm, precond=args.precond,
+                   inner_rho=args.inner_rho)
     dv_prev = v - v_before
     b = ctx.cloth_assemble(x, v, args.blocks)
     paired = {}
     for mode in (["zero", "prev"] + (["learned"] if params is not None else [])):
         dv0 = torch.zeros_like(x) if mode == "zero" else dv_prev.clone()
-        _, pinfo = ctx.cloth_pcg_solve(b, dv=dv0, tol=tol, warm=mode)
+        _, pinfo = ctx.cloth_pcg_solve(b, dv=dv0, tol=tol, warm=mode, precond=args.precond,
+                                       inner_rho=args.inner_rho)
         paired[mode] = {"iters": pinfo["iters"], "start_used": pinfo["warm_used"],
                         "rel_res_true": pinfo["rel_res_true"]}
     log(f"# paired starts on one system: {paired}")
@@ -234,7 +242,7 @@ def main():
             "workload": f"{cloth.name}: {nt} triangles, {nv} vertices, {nh} hinges, nnzb {nnzb}",
             "h": cloth.h, "tol": tol, "block_storage": args.blocks, "warm_start": args.warm,
             "refinement_sweeps": [i["sweeps"] for i in infos], "starts_used": [i["warm_used"] for i in infos],
-            "preconditioner": "jacobi", "cg_iters_per_step": {"mean": float(np.mean(iters)),
+            "preconditioner": args.precond, "inner_rho": args.inner_rho, "cg_iters_per_step": {"mean": float(np.mean(iters)),
                                                                "min": int(min(iters)), "max": int(max(iters))},
             "rel_res_true_max": max(i["rel_res_true"] for i in infos),
             "schedule": tune,

@@ -99,10 +99,13 @@ typedef struct {
     int32_t maxit;         /* total CG iterations over all sweeps; default 20000 when <= 0 */
     int32_t warm;          /* 0: zero start, 1: caller's dv as start, 2: learned start predicted
                               from the caller's dv taken as the previous step's increment
-                              (needs pc_ws_set_params); a start whose residual exceeds ||b||
-                              is replaced by the zero start */
+                              (needs pc_ws_set_params; see pc_ws_predict for the safeguard) */
     int32_t check_every;   /* iterations between host convergence checks (0: auto) */
     int32_t max_sweeps;    /* refinement sweeps; 0: default (BF16 40, otherwise 4) */
+    int32_t precond;       /* 0: Jacobi, P = diag(A) (the paper's preconditioner, Sec. 2.5);
+                              1: block Jacobi, P = the 3x3 diagonal blocks A_ii, inverted in
+                              FP64 at assembly and applied in FP32 x FP64 */
+    int32_t reserved;      /* set to 0 */
 } pc_solve_opts;
 
 typedef struct {
@@ -113,7 +116,9 @@ typedef struct {
     double bnorm;              /* ||b||_2 */
     int32_t fallback;          /* 1 if the inner CG switched to the FP64 blocks after a
                                   breakdown on the low-precision copy */
-    int32_t warm_used;         /* start actually used: 0 zero, 1 given / previous, 2 learned */
+    int32_t warm_used;         /* start actually used: 0 zero, 1 given / previous increment,
+                                  2 learned (previous increment plus a nonzero step along the
+                                  network's correction) */
 } pc_solve_info;
 
 /* Create a context: copies the mesh to the device, derives the rest shape
@@ -182,6 +187,12 @@ pc_status cloth_spmv(pc_ctx *ctx, const double *x, double *y, int32_t solver_blo
 pc_status cloth_export_blocks(pc_ctx *ctx, double *vals_out, double *D_out, int32_t solver_blocks,
                               void *stream);
 
+/* Preconditioners of the last assembly: inv_diag_out (device nv*3 floats)
+ * receives 1 / diag(A); inv_blocks_out (device nv*6 floats) the inverses of
+ * the 3x3 diagonal blocks A_ii as (xx, xy, xz, yy, yz, zz).  Either may be
+ * NULL.  Enqueued on the stream. */
+pc_status cloth_export_precond(pc_ctx *ctx, float *inv_diag_out, float *inv_blocks_out, void *stream);
+
 /* Block-CSR pattern of the last assembly.  Synchronises the stream, writes
  * nnzb to *nnzb_out (host, optional) and copies rowptr (device nrows+1 int32)
  * and colidx (device nnzb int32) into the caller's buffers when they are not
@@ -200,9 +211,12 @@ pc_status pc_profile_read(pc_ctx *ctx, double *out);
 
 /* ---- Learned warm start (project addition to the paper's method) ----
  * A per-vertex MLP (27 features -> 64 -> 64 -> 64 -> 3, ReLU) predicts a
- * correction to the previous step's increment: dv0 = dv_prev + s_v y on free
- * vertices (s_v = mean rest edge length / h), used as the CG start of Eq. 3
- * after scaling by c = dv0.b / dv0.A dv0.  Features of vertex i (N(i): block
+ * correction u = s_v y to the previous step's increment on free vertices
+ * (s_v = mean rest edge length / h).  As the CG start of Eq. 3 (warm = 2) it
+ * is dv_prev + g u with the step g = u.(b - A dv_prev) / u.A u that minimises
+ * the A-norm error along u (g = 0 when u.A u <= 0), so the start is never
+ * worse in the A-norm than dv_prev itself; one step g is taken for all
+ * instances of the context.  Features of vertex i (N(i): block
  * columns of row i other than i): v/s_v, (b/m)/s_v, dv_prev/s_v, mean_N dv_prev/s_v,
  * (b/diag A)/s_v, (mean_N b/m - b_i/m_i)/s_v, (mean_N v - v_i)/s_v,
  * (mean_N x - x_i)/l, pinned, log10(mean diag A_i / m_i), |N(i)|/12.
@@ -220,6 +234,10 @@ pc_status pc_ws_features(pc_ctx *ctx, const double *x, const double *v, const do
 /* Unscaled prediction dv0 = dv_prev + s_v y (device nv*3 doubles). */
 pc_status pc_ws_predict(pc_ctx *ctx, const double *x, const double *v, const double *b, const double *dv_prev,
                         double *dv0_out, void *stream);
+/* The learned CG start used by warm = 2: dv_prev + g u (device nv*3
+ * doubles), step g to step_host (optional).  Synchronises the stream. */
+pc_status pc_ws_start(pc_ctx *ctx, const double *x, const double *v, const double *b, const double *dv_prev,
+                      double *dv0_out, double *step_host, void *stream);
 /* Loss and its gradient with respect to the parameters (host floats, same
  * layout as the parameters); no update.  Synchronises the stream. */
 pc_status pc_ws_gradient(pc_ctx *ctx, const double *x, const double *v, const double *b, const double *dv_prev,
@@ -237,8 +255,8 @@ pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
  * PC_OPT_GRAPH_CHUNK: when > 0, CG iterations are captured once into a HIP
  *   graph of that many iterations and replayed on the caller's stream; the
  *   per-instance convergence flags make iterations after convergence exit at
- *   once.  0 (default): plain launches.  pc_profile timings come from plain
- *   launches only.
+ *   once.  0 (default): plain launches.  While pc_profile sampling is on,
+ *   one chunk in 8 runs as plain launches, which the sampled events time.
  * PC_OPT_SPMV_SLICES_PER_BLOCK: 64-row slices per SpMV work item / block
  *   (1, 2, 4 (default) or 8).
  * PC_OPT_VECTOR_ROWS_PER_BLOCK: rows per work item of the CG vector kernels
@@ -250,12 +268,13 @@ pc_status pc_get_option(pc_ctx *ctx, int32_t option, int64_t *value);
 /* Autotuner: on the assembled system and right-hand side b (device nv*3),
  * time `iters` CG iterations for every candidate schedule (slices per SpMV
  * block 1/2/4/8 x rows per vector block 256/512/1024 x graph chunk 0/32)
- * with HIP events on the stream, and keep the fastest.  chosen (host,
- * optional) receives {slices per block, rows per block, graph chunk};
+ * with HIP events on the stream, and keep the fastest.  precond: the
+ * preconditioner the iterations use (as pc_solve_opts.precond).  chosen
+ * (host, optional) receives {slices per block, rows per block, graph chunk};
  * ms_per_iter (host, optional) the best time per iteration.  Overwrites the
  * solver's work vectors (not dv, not b).  Synchronises the stream. */
-pc_status pc_autotune(pc_ctx *ctx, const double *b, int32_t iters, int64_t *chosen, double *ms_per_iter,
-                      void *stream);
+pc_status pc_autotune(pc_ctx *ctx, const double *b, int32_t iters, int32_t precond, int64_t *chosen,
+                      double *ms_per_iter, void *stream);
 
 /* ---- Many independent cloths in one context (project addition) ----
  * The mesh given to pc_create is the concatenation of ninst cloths occupying

@@ -21,7 +21,9 @@ same, independently):
   26    |N(i)| / 12
 * MLP 27 -> 64 -> 64 -> 64 -> 3, ReLU on the hidden layers:
   h_k = relu(h_{k-1} W_k + c_k), y = h_3 W_4 + c_4 (W_k stored in x out).
-* Start: dv0_i = dv_prev_i + s_v y_i for free vertices, 0 for pinned ones.
+* Start: dv0_i = dv_prev_i + s_v y_i for free vertices, 0 for pinned ones
+  (the training target); as the CG start the correction u = s_v y is added
+  with the step g that minimises the A-norm error along u (line_search_start).
 * Loss (energy norm of the start's error, scaled per system):
   L = (0.5 dv0^T A dv0 - b^T dv0) / E0,  E0 = b^T D^-1 b.
   dL/dy_i = s_v (A dv0 - b)_i / E0 for free vertices, 0 otherwise.
@@ -164,6 +166,16 @@ def adam_step(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
             vh = state["v"][k][q] / (1 - b2 ** t)
             params[k][q] = params[k][q] - lr * mh / (np.sqrt(vh) + eps)
     return params
+
+
+def line_search_start(apply_A, b, dv_prev, u):
+    """Start dv_prev + g u with g = u.(b - A dv_prev) / u.A u, the minimiser of
+    the A-norm error along u (g = 0 when u.A u <= 0).  Returns (start, g)."""
+    Au = apply_A(u)
+    den = float((u * Au).sum())
+    num = float((u * b).sum()) - float((u * apply_A(dv_prev)).sum())
+    g = num / den if den > 0 and np.isfinite(num / den) else 0.0
+    return dv_prev + g * u, g
 
 
 def safeguard_scale(apply_A, b, dv0):

@@ -28,7 +28,7 @@ ABI_SYMBOLS = ["pc_create", "pc_destroy", "pc_set_params", "pc_last_error", "pc_
                "cloth_export_pattern", "pc_check", "pc_profile", "pc_profile_read", "pc_set_option",
                "pc_ws_set_params", "pc_ws_get_params", "pc_ws_features", "pc_ws_predict", "pc_ws_gradient",
                "pc_ws_train_step", "pc_mfma_probe", "pc_get_option", "pc_set_instances", "pc_get_instance_info",
-               "pc_autotune"]
+               "pc_autotune", "cloth_export_precond", "pc_ws_start"]
 WS_PARAMS = 10307
 # Warm-start network layer shapes (inputs x outputs); the flat parameter
 # vector holds, per layer, W row-major then the bias.
@@ -57,12 +57,17 @@ class PcBsr3(ctypes.Structure):
 
 class PcSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_rho", ctypes.c_double), ("maxit", ctypes.c_int32),
-                ("warm", ctypes.c_int32), ("check_every", ctypes.c_int32), ("max_sweeps", ctypes.c_int32)]
+                ("warm", ctypes.c_int32), ("check_every", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
-def solve_opts(tol=1e-6, maxit=20000, warm=False, check_every=0, inner_rho=0.0, max_sweeps=0):
+PRECOND = {"jacobi": 0, "block": 1}
+
+
+def solve_opts(tol=1e-6, maxit=20000, warm=False, check_every=0, inner_rho=0.0, max_sweeps=0, precond="jacobi"):
     w = WARM[warm] if isinstance(warm, str) else int(warm)
-    return PcSolveOpts(float(tol), float(inner_rho), int(maxit), w, int(check_every), int(max_sweeps))
+    pre = PRECOND[precond] if isinstance(precond, str) else int(precond)
+    return PcSolveOpts(float(tol), float(inner_rho), int(maxit), w, int(check_every), int(max_sweeps), pre, 0)
 
 
 class PcSolveInfo(ctypes.Structure):
@@ -100,6 +105,7 @@ def lib():
                                  ctypes.POINTER(PcSolveInfo), vp]
         L.cloth_spmv.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
         L.cloth_export_blocks.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
+        L.cloth_export_precond.argtypes = [vp, vp, vp, vp]
         L.pc_check.argtypes = [vp, vp]
         L.cloth_export_pattern.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
         L.pc_profile.argtypes = [vp, ctypes.c_int32]
@@ -108,13 +114,14 @@ def lib():
         L.pc_ws_get_params.argtypes = [vp, vp, ctypes.c_int32]
         L.pc_ws_features.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.pc_ws_predict.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.pc_ws_start.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
         L.pc_ws_gradient.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
         L.pc_ws_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
         L.pc_mfma_probe.argtypes = [vp, vp]
         L.pc_get_option.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
         L.pc_set_instances.argtypes = [vp, vp, ctypes.c_int32]
         L.pc_get_instance_info.argtypes = [vp, ctypes.POINTER(PcSolveInfo), ctypes.c_int32]
-        L.pc_autotune.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+        L.pc_autotune.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_double), vp]
         L.pc_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         for name in ABI_SYMBOLS:
@@ -240,11 +247,11 @@ class Context:
         return rowptr, colidx[:n.value]
 
     def cloth_pcg_solve(self, b, dv=None, tol=1e-6, maxit=20000, warm=False, check_every=0, raise_on_error=True,
-                        inner_rho=0.0, max_sweeps=0):
+                        inner_rho=0.0, max_sweeps=0, precond="jacobi"):
         import torch
         if dv is None:
             dv = torch.zeros((self.nv, 3), dtype=torch.float64, device=b.device)
-        o = solve_opts(tol, maxit, warm, check_every, inner_rho, max_sweeps)
+        o = solve_opts(tol, maxit, warm, check_every, inner_rho, max_sweeps, precond)
         info = PcSolveInfo()
         st = lib().cloth_pcg_solve(self.h, _dev3(b, self.nv, "b"), _dev3(dv, self.nv, "dv"), ctypes.byref(o),
                                    ctypes.byref(info), _stream())
@@ -262,6 +269,15 @@ class Context:
                                      _stream()))
         return y
 
+    def cloth_export_precond(self):
+        """(1 / diag(A) as (nv, 3), inverse diagonal blocks as (nv, 3, 3)), float32 on the device."""
+        import torch
+        dinv = torch.empty((self.nv, 3), dtype=torch.float32, device="cuda")
+        b6 = torch.empty((self.nv, 6), dtype=torch.float32, device="cuda")
+        self._check(lib().cloth_export_precond(self.h, _ptr(dinv), _ptr(b6), _stream()))
+        idx = [0, 1, 2, 1, 3, 4, 2, 4, 5]
+        return dinv, b6[:, idx].reshape(self.nv, 3, 3)
+
     def cloth_export_blocks(self, with_D=True, solver_blocks=False):
         import torch
         rowptr, colidx = self.pattern()
@@ -272,9 +288,9 @@ class Context:
         return rowptr, colidx, vals, D
 
     def cloth_step(self, x, v, nsteps=1, dtype="f32", tol=1e-6, maxit=20000, warm=False, check_every=0,
-                   inner_rho=0.0, max_sweeps=0):
+                   inner_rho=0.0, max_sweeps=0, precond="jacobi"):
         dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
-        o = solve_opts(tol, maxit, warm, check_every, inner_rho, max_sweeps)
+        o = solve_opts(tol, maxit, warm, check_every, inner_rho, max_sweeps, precond)
         infos = (PcSolveInfo * max(1, nsteps))()
         st = lib().cloth_step(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"), int(nsteps), dt,
                               ctypes.byref(o), infos, _stream())
@@ -320,6 +336,17 @@ class Context:
                                         _stream()))
         return out
 
+    def ws_start(self, x, v, b, dv_prev):
+        """The learned CG start (previous increment plus a line-searched step
+        along the network's correction) and its step."""
+        import torch
+        out = torch.empty((self.nv, 3), dtype=torch.float64, device="cuda")
+        g = ctypes.c_double()
+        self._check(lib().pc_ws_start(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"),
+                                      _dev3(b, self.nv, "b"), _dev3(dv_prev, self.nv, "dv_prev"), _ptr(out),
+                                      ctypes.byref(g), _stream()))
+        return out, g.value
+
     def ws_gradient(self, x, v, b, dv_prev):
         g = np.zeros(WS_PARAMS, dtype=np.float32)
         loss = ctypes.c_double()
@@ -353,7 +380,7 @@ class Context:
         self._check(lib().pc_set_instances(self.h, a.ctypes.data_as(ctypes.c_void_p), a.size - 1))
         self.ninst = a.size - 1
 
-    def autotune(self, b, iters=64, cache=None, key=None):
+    def autotune(self, b, iters=64, cache=None, key=None, precond="jacobi"):
         """Pick the fastest launch schedule for the assembled system (see
         pc_autotune).  With a cache path and key, a previous choice is reused
         and new choices are stored (JSON)."""
@@ -369,7 +396,8 @@ class Context:
                 return {"choice": [spb, rpb, chunk], "ms_per_iter": known[key]["ms_per_iter"], "cached": True}
         chosen = (ctypes.c_int64 * 3)()
         ms = ctypes.c_double()
-        self._check(lib().pc_autotune(self.h, _dev3(b, self.nv, "b"), int(iters), chosen, ctypes.byref(ms),
+        pre = PRECOND[precond] if isinstance(precond, str) else int(precond)
+        self._check(lib().pc_autotune(self.h, _dev3(b, self.nv, "b"), int(iters), pre, chosen, ctypes.byref(ms),
                                       _stream()))
         res = {"choice": [chosen[0], chosen[1], chosen[2]], "ms_per_iter": ms.value, "cached": False}
         if cache and key:

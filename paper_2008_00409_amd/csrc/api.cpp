@@ -64,7 +64,7 @@ static bool params_ok(const pc_params *p, std::string &err) {
 static void free_all(Ctx *c) {
     void *ptrs[] = {c->tri, c->Bm, c->A0, c->hinge, c->hcoef, c->htbar, c->mass, c->pinned, c->status,
                     c->inc_cnt, c->inc_ptr, c->inc, c->rowlen, c->rowptr, c->colidx, c->jcol, c->lane_row,
-                    c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->x, c->r, c->q, c->tmp, c->bbuf,
+                    c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
                     c->p, c->partials, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0,
                     c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d};
     for (void *p : ptrs)
@@ -175,6 +175,8 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
     ALLOC(ctx->row_lane, sizeof(int) * (size_t)nv);
     ALLOC(ctx->diag, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->dinv, sizeof(float) * 3 * (size_t)nv);
+    ALLOC(ctx->binv, sizeof(float) * 6 * (size_t)nv);
+    ALLOC(ctx->zb, sizeof(float4) * (size_t)nv);
     ALLOC(ctx->x, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->r, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->q, sizeof(double) * 3 * (size_t)nv);
@@ -276,8 +278,10 @@ pc_status pc_get_option(pc_ctx *h, int32_t option, int64_t *value) {
     }
 }
 
-pc_status pc_autotune(pc_ctx *h, const double *b, int32_t iters, int64_t *chosen, double *ms_per_iter, void *stream) {
-    if (!h || !b || iters < 1) return PC_ERR_ARG;
+pc_status pc_autotune(pc_ctx *h, const double *b, int32_t iters, int32_t precond, int64_t *chosen,
+                      double *ms_per_iter, void *stream) {
+    if (!h || !b || iters < 1 || precond < 0 || precond > 1) return PC_ERR_ARG;
+    h->c.precond = precond;
     float ms = 0.0f;
     pc_status st = autotune_run(&h->c, b, iters, chosen, &ms, (hipStream_t)stream);
     if (ms_per_iter) *ms_per_iter = ms;
@@ -365,6 +369,19 @@ pc_status pc_ws_predict(pc_ctx *h, const double *x, const double *v, const doubl
     pc_status st = mlp_features(ctx, ctx->mlp, x, v, b, dv_prev, s);
     if (st) return st;
     return mlp_forward(ctx, ctx->mlp, dv_prev, dv0_out, false, s);
+}
+
+pc_status pc_ws_start(pc_ctx *h, const double *x, const double *v, const double *b, const double *dv_prev,
+                      double *dv0_out, double *step_host, void *stream) {
+    if (!h || !dv0_out || !ws_args(&h->c, x, v, b, dv_prev)) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (!ctx->mlp || !ctx->mlp->has_params) { ctx->err = "no warm-start parameters set"; return PC_ERR_ARG; }
+    if (!ctx->assembled) { ctx->err = "pc_ws_start: nothing assembled"; return PC_ERR_ARG; }
+    int used = 0;
+    pc_status st = mlp_start(ctx, ctx->mlp, x, v, b, dv_prev, dv0_out, ctx->q, &used, (hipStream_t)stream);
+    if (st) return st;
+    if (step_host) *step_host = ctx->mlp->last_scale;
+    return PC_OK;
 }
 
 pc_status pc_ws_gradient(pc_ctx *h, const double *x, const double *v, const double *b, const double *dv_prev,
@@ -495,16 +512,21 @@ pc_status pc_check(pc_ctx *h, void *stream) {
     return PC_OK;
 }
 
+static bool opts_ok(Ctx *ctx, const pc_solve_opts *o) {
+    if (o && (!(o->tol >= 0.0) || o->warm < 0 || o->warm > 2 || !(o->inner_rho >= 0.0) || o->inner_rho >= 1.0 ||
+              o->precond < 0 || o->precond > 1)) {
+        ctx->err = "bad solve options";
+        return false;
+    }
+    return true;
+}
+
 pc_status cloth_pcg_solve(pc_ctx *h, const double *b, double *dv, const pc_solve_opts *opts, pc_solve_info *info,
                           void *stream) {
     if (!h) return PC_ERR_ARG;
     Ctx *ctx = &h->c;
     if (!b || !dv) { ctx->err = "cloth_pcg_solve: b and dv must be device pointers"; return PC_ERR_ARG; }
-    if (opts && (!(opts->tol >= 0.0) || opts->warm < 0 || opts->warm > 2 || !(opts->inner_rho >= 0.0) ||
-                 opts->inner_rho >= 1.0)) {
-        ctx->err = "bad solve options";
-        return PC_ERR_ARG;
-    }
+    if (!opts_ok(ctx, opts)) return PC_ERR_ARG;
     pc_status st = pc_check(h, stream);
     if (st) return st;
     return pcg_run(ctx, b, dv, opts, info, (hipStream_t)stream);
@@ -540,13 +562,27 @@ pc_status cloth_export_blocks(pc_ctx *h, double *vals_out, double *D_out, int32_
     return export_blocks(&h->c, vals_out, D_out, solver_blocks != 0, (hipStream_t)stream);
 }
 
+pc_status cloth_export_precond(pc_ctx *h, float *inv_diag_out, float *inv_blocks_out, void *stream) {
+    if (!h) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (!ctx->assembled) { ctx->err = "cloth_export_precond: nothing assembled"; return PC_ERR_ARG; }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nv = (size_t)ctx->nv;
+    if (inv_diag_out)
+        PC_HIP(hipMemcpyAsync(inv_diag_out, ctx->dinv, sizeof(float) * 3 * nv, hipMemcpyDeviceToDevice, s));
+    if (inv_blocks_out)
+        PC_HIP(hipMemcpyAsync(inv_blocks_out, ctx->binv, sizeof(float) * 6 * nv, hipMemcpyDeviceToDevice, s));
+    return PC_OK;
+}
+
 pc_status cloth_step(pc_ctx *h, double *x, double *v, int32_t nsteps, pc_dtype dtype, const pc_solve_opts *opts,
                      pc_solve_info *infos, void *stream) {
     if (!h) return PC_ERR_ARG;
     Ctx *ctx = &h->c;
     if (!x || !v || nsteps < 0) { ctx->err = "cloth_step: bad arguments"; return PC_ERR_ARG; }
+    if (!opts_ok(ctx, opts)) return PC_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
-    pc_solve_opts o = opts ? *opts : pc_solve_opts{1e-6, 0.0, 20000, 0, 0, 0};
+    pc_solve_opts o = opts ? *opts : pc_solve_opts{1e-6, 0.0, 20000, 0, 0, 0, 0, 0};
     // dv lives in ctx->tmp between steps (previous-step start when warm = 1)
     for (int k = 0; k < nsteps; ++k) {
         pc_status st = assemble_run(ctx, x, v, dtype, ctx->bbuf, nullptr, s);

@@ -450,6 +450,7 @@ struct AsmArgs {
     double *jval_hi;   // FP64 copy (nullptr when the solver copy is FP64)
     double *b, *diag;
     float *dinv;
+    float *binv;   // inverse diagonal blocks, 6 per row (xx, xy, xz, yy, yz, zz)
     int *status;
 };
 
@@ -585,6 +586,28 @@ __device__ void write_overflow_row(const AsmArgs &A, int i) {
         A.b[3 * i + a] = 0.0;
         A.diag[3 * i + a] = mi;
         A.dinv[3 * i + a] = (float)(1.0 / mi);
+    }
+    const float im = (float)(1.0 / mi);
+    float *bi = A.binv + 6 * (int64_t)i;
+    bi[0] = im; bi[1] = 0.0f; bi[2] = 0.0f; bi[3] = im; bi[4] = 0.0f; bi[5] = im;
+}
+
+// Inverse of the symmetric 3x3 block [[a, b, c], [b, d, e], [c, e, f]] by its
+// adjugate, written as (xx, xy, xz, yy, yz, zz).  A block that is not
+// positive definite (impossible for M + c K with K PSD, but guarded) falls
+// back to the inverse of its diagonal.
+__device__ __forceinline__ void store_block_inverse(float *out, double a, double b, double c, double d, double e,
+                                                    double f) {
+    const double c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
+    const double c11 = a * f - c * c, c12 = b * c - a * e, c22 = a * d - b * b;
+    const double det = a * c00 + b * c01 + c * c02;
+    if (det > 0.0 && a > 0.0 && c22 > 0.0 && isfinite(det)) {   // leading minors positive
+        const double id = 1.0 / det;
+        out[0] = (float)(c00 * id); out[1] = (float)(c01 * id); out[2] = (float)(c02 * id);
+        out[3] = (float)(c11 * id); out[4] = (float)(c12 * id); out[5] = (float)(c22 * id);
+    } else {
+        out[0] = (float)(1.0 / a); out[1] = 0.0f; out[2] = 0.0f;
+        out[3] = (float)(1.0 / d); out[4] = 0.0f; out[5] = (float)(1.0 / f);
     }
 }
 
@@ -739,7 +762,7 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
     const d3 vi = ld3(A.v, i);
     d3 dvv = mk(0.0, 0.0, 0.0);
     if (active && !isdiag) dvv = ld3(A.v, col) - vi;
-    double red[15];
+    double red[18];
     red[0] = acc[0] * dvv.x + acc[1] * dvv.y + acc[2] * dvv.z;
     red[1] = acc[3] * dvv.x + acc[4] * dvv.y + acc[5] * dvv.z;
     red[2] = acc[6] * dvv.x + acc[7] * dvv.y + acc[8] * dvv.z;
@@ -748,8 +771,13 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
     red[5] = acc[8];
 #pragma unroll
     for (int q = 0; q < 9; ++q) red[6 + q] = colpin ? acc[q] : 0.0;
+    // off-diagonal entries of sum_j K_ij (symmetrised): the diagonal block is
+    // A_ii = m_i I - c sum_{j != i} K_ij since every element's block rows sum to zero
+    red[15] = 0.5 * (acc[1] + acc[3]);
+    red[16] = 0.5 * (acc[2] + acc[6]);
+    red[17] = 0.5 * (acc[5] + acc[7]);
 #pragma unroll
-    for (int q = 0; q < 15; ++q) red[q] = wave_sum(red[q]);
+    for (int q = 0; q < 18; ++q) red[q] = wave_sum(red[q]);
 
     const double mi = A.mass[i];
     double blk[9];
@@ -778,6 +806,10 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
         A.dinv[3 * i] = (float)(1.0 / d0);
         A.dinv[3 * i + 1] = (float)(1.0 / d1);
         A.dinv[3 * i + 2] = (float)(1.0 / d2);
+        const double o01 = rowpin ? 0.0 : -P.c * red[15];
+        const double o02 = rowpin ? 0.0 : -P.c * red[16];
+        const double o12 = rowpin ? 0.0 : -P.c * red[17];
+        store_block_inverse(A.binv + 6 * (int64_t)i, d0, o01, o02, d1, o12, d2);
     } else {
 #pragma unroll
         for (int q = 0; q < 9; ++q) blk[q] = (rowpin || colpin) ? 0.0 : P.c * acc[q];
@@ -891,7 +923,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     a.row_lane = ctx->row_lane; a.slot_cnt = ctx->slot_cnt; a.jval = ctx->jval;
     a.row_slice = ctx->row_slice; a.slice_row0 = ctx->slice_row0;
     a.jval_hi = dtype != PC_F64 ? ctx->jval_hi : nullptr;
-    a.b = b; a.diag = diag_out ? diag_out : ctx->diag; a.dinv = ctx->dinv; a.status = ctx->status;
+    a.b = b; a.diag = diag_out ? diag_out : ctx->diag; a.dinv = ctx->dinv; a.binv = ctx->binv; a.status = ctx->status;
     const int nb = ((nv + 7) / 8) * 8;
     int slot = ctx->prof.begin(PK_ROW_PAT, s);
     hipLaunchKernelGGL(k_row_pattern, dim3(nb), dim3(64), 0, s, a);

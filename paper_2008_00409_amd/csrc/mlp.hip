@@ -165,7 +165,7 @@ struct FwdArgs {
     const double *dvp;
     const uint8_t *pinned;
     double sv;
-    double *dv0;          // start: dv_prev + s_v y (free), 0 (pinned)
+    double *dv0;          // start: dv_prev + s_v y (free), 0 (pinned); dvp == nullptr: s_v y
 };
 
 // One wavefront per 16-vertex tile, grid-stride over tiles; weights stay in
@@ -230,7 +230,8 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(FwdArgs F) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double ya = (double)(y[a] + b4[a]);
-                F.dv0[3 * vtx + a] = F.pinned[vtx] ? 0.0 : F.dvp[3 * vtx + a] + F.sv * ya;
+                const double base = F.dvp ? F.dvp[3 * vtx + a] : 0.0;
+                F.dv0[3 * vtx + a] = F.pinned[vtx] ? 0.0 : base + F.sv * ya;
             }
         }
     }
@@ -455,9 +456,17 @@ __global__ void k_ws_dots_final(int nb, const double *part, double *out) {
     }
 }
 
-__global__ void k_scale_d(int64_t n, double *x, const double *num_den) {
+// Line search along the network's correction u from the previous increment:
+// x = dv_prev + g u with g = (u.b - w.dv_prev) / u.w, w = A u (A symmetric,
+// so w.dv_prev = u.A dv_prev); g = 0 when u.w is not positive.
+__device__ __forceinline__ double line_step(const double *d) {
+    const double g = (d[0] - d[2]) / d[1];
+    return (d[1] > 0.0 && isfinite(g)) ? g : 0.0;
+}
+
+__global__ void k_line_start(int64_t n, const double *dvp, const double *u, const double *dots, double *x) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] *= num_den[0] / num_den[1];
+    if (i < n) x[i] = dvp[i] + line_step(dots) * u[i];
 }
 
 // ---------------------------------------------------------------- host side
@@ -668,32 +677,34 @@ pc_status mlp_adam(Ctx *ctx, MlpState *M, double lr, hipStream_t s) {
     return PC_OK;
 }
 
-// Learned start: dv0 = dv_prev + s_v MLP(features), scaled by the factor that
-// minimises its A-norm error, c = dv0.b / dv0.A dv0.  Returns in *used 2
-// when the start is kept, 0 when c <= 0 (the caller then starts from zero).
+// Learned start: the network's correction u = s_v MLP(features) is added to
+// the previous increment with the step g that minimises the A-norm error of
+// dv_prev + g u (one SpMV with the FP64 blocks), so the start is never worse
+// in the A-norm than the previous increment itself.  u goes through u_buf
+// (nv * 3 doubles of scratch).  *used = 2 when g != 0, 1 otherwise.
 pc_status mlp_start(Ctx *ctx, MlpState *M, const double *x, const double *v, const double *b, const double *dvp,
-                    double *dv0, int *used, hipStream_t s) {
+                    double *dv0, double *u_buf, int *used, hipStream_t s) {
     pc_status st;
-    *used = 0;
+    *used = 1;
     if (!M->has_params) {
         ctx->err = "no warm-start parameters set";
         return PC_ERR_ARG;
     }
     if ((st = mlp_features(ctx, M, x, v, b, dvp, s))) return st;
-    if ((st = mlp_forward(ctx, M, dvp, dv0, false, s))) return st;
+    if ((st = mlp_forward(ctx, M, nullptr, u_buf, false, s))) return st;
     if (!M->Ad && (st = dev_alloc(ctx, (void **)&M->Ad, sizeof(double) * 3 * (size_t)ctx->nv))) return st;
-    if ((st = spmv_run(ctx, dv0, M->Ad, false, s))) return st;
-    // dots: [dv0.b, dv0.A dv0, -]
-    if ((st = dots3(ctx, M, dv0, b, dv0, M->Ad, dv0, dv0, nullptr, M->dots, s))) return st;
+    if ((st = spmv_run(ctx, u_buf, M->Ad, false, s))) return st;
+    // dots: [u.b, u.w, w.dv_prev]
+    if ((st = dots3(ctx, M, u_buf, b, u_buf, M->Ad, M->Ad, dvp, nullptr, M->dots, s))) return st;
+    const int64_t n3 = 3 * (int64_t)ctx->nv;
+    hipLaunchKernelGGL(k_line_start, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, dvp, u_buf, M->dots, dv0);
+    PC_HIP(hipGetLastError());
     double d[3];
     PC_HIP(hipMemcpyAsync(d, M->dots, sizeof(d), hipMemcpyDeviceToHost, s));
     PC_HIP(hipStreamSynchronize(s));
-    if (!(d[1] > 0.0) || !(d[0] > 0.0) || !std::isfinite(d[0] / d[1])) return PC_OK;
-    const int64_t n3 = 3 * (int64_t)ctx->nv;
-    hipLaunchKernelGGL(k_scale_d, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, dv0, M->dots);
-    PC_HIP(hipGetLastError());
-    M->last_scale = d[0] / d[1];
-    *used = 2;
+    const double g = (d[0] - d[2]) / d[1];
+    M->last_scale = (d[1] > 0.0 && std::isfinite(g)) ? g : 0.0;
+    *used = M->last_scale != 0.0 ? 2 : 1;
     return PC_OK;
 }
 

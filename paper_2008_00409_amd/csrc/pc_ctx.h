@@ -146,11 +146,14 @@ struct Ctx {
     bool assembled = false;
     bool have_prev_dv = false;  // ctx->tmp holds the previous step's dv
     double *diag = nullptr;   // nv * 3
-    float *dinv = nullptr;    // nv * 3
+    float *dinv = nullptr;    // nv * 3: 1 / diag(A)
+    float *binv = nullptr;    // nv * 6: inverse of the diagonal block A_ii (xx, xy, xz, yy, yz, zz)
 
     // solver vectors
     double *x = nullptr, *r = nullptr, *q = nullptr, *tmp = nullptr, *bbuf = nullptr;
     float4 *p = nullptr;
+    float4 *zb = nullptr;         // preconditioned residual (block Jacobi)
+    int precond = 0;              // preconditioner of the current / last solve
     double *partials = nullptr;   // per-block partial sums (4 doubles per block)
     double *res2 = nullptr;       // 2 doubles per instance: true-residual check
     unsigned *counter = nullptr;
@@ -171,6 +174,7 @@ struct Ctx {
     int gkey_dtype[2] = {-1, -1};
     int gkey_chunk[2] = {0, 0};
     int gkey_sched[2] = {-1, -1};
+    int gkey_pre[2] = {-1, -1};
 };
 
 // Error helpers (host)

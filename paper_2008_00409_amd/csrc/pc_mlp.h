@@ -36,7 +36,7 @@ pc_status mlp_gradient(Ctx *ctx, MlpState *M, const double *x, const double *v, 
                        double *loss, hipStream_t s);
 pc_status mlp_adam(Ctx *ctx, MlpState *M, double lr, hipStream_t s);
 pc_status mlp_start(Ctx *ctx, MlpState *M, const double *x, const double *v, const double *b, const double *dvp,
-                    double *dv0, int *used, hipStream_t s);
+                    double *dv0, double *u_buf, int *used, hipStream_t s);
 pc_status mlp_probe(Ctx *ctx, float *host_out);
 void mlp_free(MlpState *M);
 

@@ -138,6 +138,31 @@ __device__ __forceinline__ int item_of_block(int n) {
     return b < n ? b : -1;
 }
 
+// Preconditioner z = P^-1 r: kind 0 Jacobi (dinv, 3 per row), kind 1 block
+// Jacobi (binv, the inverse diagonal block, 6 per row: xx, xy, xz, yy, yz,
+// zz).  z holds the block-Jacobi z of the current residual (FP32).
+struct PreArgs {
+    int kind;
+    const float *dinv;
+    const float *binv;
+    float4 *z;
+};
+
+__device__ __forceinline__ void precond3(const PreArgs &P, int i, double r0, double r1, double r2, double z[3]) {
+    if (P.kind == 0) {
+        z[0] = r0 * (double)P.dinv[3 * i];
+        z[1] = r1 * (double)P.dinv[3 * i + 1];
+        z[2] = r2 * (double)P.dinv[3 * i + 2];
+    } else {
+        const float2 *b = (const float2 *)(P.binv + 6 * (int64_t)i);
+        const float2 b01 = b[0], b23 = b[1], b45 = b[2];
+        const double xx = b01.x, xy = b01.y, xz = b23.x, yy = b23.y, yz = b45.x, zz = b45.y;
+        z[0] = xx * r0 + xy * r1 + xz * r2;
+        z[1] = xy * r0 + yy * r1 + yz * r2;
+        z[2] = xz * r0 + yz * r1 + zz * r2;
+    }
+}
+
 // ---------------------------------------------------------------- reductions
 // Deterministic two-stage sums without device-scope fences: every block of a
 // producing kernel writes its NV partial sums for its work item (plain
@@ -252,23 +277,51 @@ __global__ void __launch_bounds__(256) k_fin_alpha(Sched S, const double *partia
 
 // x += alpha p, r -= alpha q over the item's rows (flat component indexing:
 // consecutive threads touch consecutive 8-byte elements); partials of r.z
-// (z = D^-1 r) and r.r.
+// (z = P^-1 r) and r.r.  Block Jacobi stages each 256-row chunk of r in LDS,
+// then one thread per row applies the inverse block and stores z.
 __global__ void __launch_bounds__(256) k_pcg_update(Sched S, double *x, double *r, const float *pf, const double *q,
-                                                    const float *dinv, const PcgState *st, double *partials) {
+                                                    PreArgs P, const PcgState *st, double *partials) {
+    __shared__ double rs[3 * 256];
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
     if (st[I.x].done) return;
     const double alpha = st[I.x].alpha;
     double rz = 0.0, rr = 0.0;
-    for (int k = 3 * I.y + threadIdx.x; k < 3 * I.z; k += blockDim.x) {
-        const int i = k / 3;
-        const double pk = pf[4 * i + (k - 3 * i)];
-        x[k] += alpha * pk;
-        const double rk = r[k] - alpha * q[k];
-        r[k] = rk;
-        rz += rk * rk * (double)dinv[k];
-        rr += rk * rk;
+    if (P.kind == 0) {
+        for (int k = 3 * I.y + threadIdx.x; k < 3 * I.z; k += blockDim.x) {
+            const int i = k / 3;
+            const double pk = pf[4 * i + (k - 3 * i)];
+            x[k] += alpha * pk;
+            const double rk = r[k] - alpha * q[k];
+            r[k] = rk;
+            rz += rk * rk * (double)P.dinv[k];
+            rr += rk * rk;
+        }
+    } else {
+        for (int r0 = I.y; r0 < I.z; r0 += 256) {
+            const int nr = min(256, I.z - r0);
+            for (int k = threadIdx.x; k < 3 * nr; k += blockDim.x) {
+                const int kk = 3 * r0 + k;
+                const int i = kk / 3;
+                const double pk = pf[4 * i + (kk - 3 * i)];
+                x[kk] += alpha * pk;
+                const double rk = r[kk] - alpha * q[kk];
+                r[kk] = rk;
+                rs[k] = rk;
+                rr += rk * rk;
+            }
+            __syncthreads();
+            if ((int)threadIdx.x < nr) {
+                const int t = threadIdx.x, i = r0 + t;
+                const double a0 = rs[3 * t], a1 = rs[3 * t + 1], a2 = rs[3 * t + 2];
+                double z[3];
+                precond3(P, i, a0, a1, a2, z);
+                rz += a0 * z[0] + a1 * z[1] + a2 * z[2];
+                P.z[i] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
+            }
+            __syncthreads();
+        }
     }
     double v[2] = {rz, rr};
     block_partials<2>(v, partials, it, S.n_vitems);
@@ -295,8 +348,9 @@ __global__ void __launch_bounds__(256) k_fin_beta(Sched S, const double *partial
     }
 }
 
-// p = D^-1 r + beta p over the item's rows.
-__global__ void __launch_bounds__(256) k_pcg_dir(Sched S, const double *r, float4 *p, const float *dinv,
+// p = P^-1 r + beta p over the item's rows (Jacobi: from r and dinv; block
+// Jacobi: from the z stored by the update).
+__global__ void __launch_bounds__(256) k_pcg_dir(Sched S, const double *r, float4 *p, PreArgs P,
                                                  const PcgState *st) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
@@ -305,39 +359,42 @@ __global__ void __launch_bounds__(256) k_pcg_dir(Sched S, const double *r, float
     const double beta = st[I.x].beta;
     for (int i = I.y + threadIdx.x; i < I.z; i += blockDim.x) {
         const float4 pv = p[i];
+        double z0, z1, z2;
+        if (P.kind == 0) {
+            z0 = r[3 * i] * (double)P.dinv[3 * i];
+            z1 = r[3 * i + 1] * (double)P.dinv[3 * i + 1];
+            z2 = r[3 * i + 2] * (double)P.dinv[3 * i + 2];
+        } else {
+            const float4 zv = P.z[i];
+            z0 = zv.x; z1 = zv.y; z2 = zv.z;
+        }
         float4 o;
-        o.x = (float)(r[3 * i] * (double)dinv[3 * i] + beta * pv.x);
-        o.y = (float)(r[3 * i + 1] * (double)dinv[3 * i + 1] + beta * pv.y);
-        o.z = (float)(r[3 * i + 2] * (double)dinv[3 * i + 2] + beta * pv.z);
+        o.x = (float)(z0 + beta * pv.x);
+        o.y = (float)(z1 + beta * pv.y);
+        o.z = (float)(z2 + beta * pv.z);
         o.w = 0.0f;
         p[i] = o;
     }
 }
 
 // Zero start of the flagged instances (all when restart == nullptr):
-// x = 0, r = b, p = D^-1 r; partials of r.z, ||r||^2 and ||b||^2.
+// x = 0, r = b, p = P^-1 r; partials of r.z, ||r||^2 and ||b||^2.
 __global__ void __launch_bounds__(256) k_pcg_start_zero(Sched S, const uint8_t *restart, const double *b, double *x,
-                                                        double *r, float4 *p, const float *dinv, double *partials) {
+                                                        double *r, float4 *p, PreArgs P, double *partials) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
     if (restart && !restart[I.x]) return;
     double rz = 0.0, rr = 0.0;
     for (int i = I.y + threadIdx.x; i < I.z; i += blockDim.x) {
-        float4 o;
-        float *op = &o.x;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double ra = b[3 * i + a];
-            x[3 * i + a] = 0.0;
-            r[3 * i + a] = ra;
-            const double z = ra * (double)dinv[3 * i + a];
-            op[a] = (float)z;
-            rz += ra * z;
-            rr += ra * ra;
-        }
-        o.w = 0.0f;
-        p[i] = o;
+        const double r0 = b[3 * i], r1 = b[3 * i + 1], r2 = b[3 * i + 2];
+        double z[3];
+        precond3(P, i, r0, r1, r2, z);
+        x[3 * i] = 0.0; x[3 * i + 1] = 0.0; x[3 * i + 2] = 0.0;
+        r[3 * i] = r0; r[3 * i + 1] = r1; r[3 * i + 2] = r2;
+        rz += r0 * z[0] + r1 * z[1] + r2 * z[2];
+        rr += r0 * r0 + r1 * r1 + r2 * r2;
+        p[i] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
     }
     double v[3] = {rz, rr, rr};
     block_partials<3>(v, partials, it, S.n_vitems);
@@ -349,7 +406,7 @@ __global__ void __launch_bounds__(256) k_pcg_start_zero(Sched S, const uint8_t *
 // ||b||^2.
 template <typename TB, int MODE>
 __global__ void __launch_bounds__(512) k_residual(SpmvArgs M, Sched S, const uint8_t *restart, const double *b,
-                                                  const double *x, double *r, float4 *p, const float *dinv,
+                                                  const double *x, double *r, float4 *p, PreArgs P,
                                                   double *partials) {
     const int it = item_of_block(S.n_sitems);
     if (it < 0) return;
@@ -362,24 +419,20 @@ __global__ void __launch_bounds__(512) k_residual(SpmvArgs M, Sched S, const uin
         double y[3], xi[3];
         const int row = spmv_row<TB>(M, I.y + w, lane, VecD3{x}, y, xi);
         if (row >= 0) {
-            float4 o;
-            float *op = &o.x;
+            double t[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double ba = b[3 * row + a];
-                const double ta = ba - y[a];
-                rr += ta * ta;
+                t[a] = ba - y[a];
+                rr += t[a] * t[a];
                 bb += ba * ba;
-                if (MODE == 0) {
-                    r[3 * row + a] = ta;
-                    const double z = ta * (double)dinv[3 * row + a];
-                    op[a] = (float)z;
-                    rz += ta * z;
-                }
             }
             if (MODE == 0) {
-                o.w = 0.0f;
-                p[row] = o;
+                double z[3];
+                precond3(P, row, t[0], t[1], t[2], z);
+                r[3 * row] = t[0]; r[3 * row + 1] = t[1]; r[3 * row + 2] = t[2];
+                rz += t[0] * z[0] + t[1] * z[1] + t[2] * z[2];
+                p[row] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
             }
         }
     }
@@ -504,6 +557,15 @@ static Sched sched_args(Ctx *ctx) {
 
 static inline int pad8(int n) { return ((n + 7) / 8) * 8; }
 
+static PreArgs pre_args(Ctx *ctx) {
+    PreArgs P;
+    P.kind = ctx->precond;
+    P.dinv = ctx->dinv;
+    P.binv = ctx->binv;
+    P.z = ctx->zb;
+    return P;
+}
+
 // Slices (up to 64 rows, never across instances) and work items from the
 // instance row ranges and the current spb / rpb.
 pc_status build_schedule(Ctx *ctx) {
@@ -597,11 +659,11 @@ static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids
     hipLaunchKernelGGL(k_fin_alpha, dim3(ctx->ninst), dim3(256), 0, s, S, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
     hipLaunchKernelGGL(k_pcg_update, dim3(g.vblocks), dim3(256), 0, s, S, ctx->x, ctx->r, (const float *)ctx->p,
-                       ctx->q, ctx->dinv, ctx->st, ctx->partials);
+                       ctx->q, pre_args(ctx), ctx->st, ctx->partials);
     ctx->prof.end(slot, s);
     hipLaunchKernelGGL(k_fin_beta, dim3(ctx->ninst), dim3(256), 0, s, S, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_DIR, s);
-    hipLaunchKernelGGL(k_pcg_dir, dim3(g.vblocks), dim3(256), 0, s, S, ctx->r, ctx->p, ctx->dinv, ctx->st);
+    hipLaunchKernelGGL(k_pcg_dir, dim3(g.vblocks), dim3(256), 0, s, S, ctx->r, ctx->p, pre_args(ctx), ctx->st);
     ctx->prof.end(slot, s);
 }
 
@@ -613,11 +675,11 @@ static void launch_residual(Ctx *ctx, const SpmvArgs &M, const Sched &S, const G
     using TB = double;
     if (mode == 0) {
         hipLaunchKernelGGL((k_residual<TB, 0>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b, x, ctx->r,
-                           ctx->p, ctx->dinv, ctx->partials);
+                           ctx->p, pre_args(ctx), ctx->partials);
         hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 1, restart, ctx->partials, ctx->st);
     } else {
         hipLaunchKernelGGL((k_residual<TB, 1>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b, x, ctx->r,
-                           ctx->p, ctx->dinv, ctx->partials);
+                           ctx->p, pre_args(ctx), ctx->partials);
         hipLaunchKernelGGL(k_fin_check, dim3(ctx->ninst), dim3(256), 0, s, S, ctx->partials, out2);
     }
 }
@@ -625,7 +687,7 @@ static void launch_residual(Ctx *ctx, const SpmvArgs &M, const Sched &S, const G
 static void launch_start_zero(Ctx *ctx, const Sched &S, const Grids &g, const uint8_t *restart, const double *b,
                               hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_start_zero, dim3(g.vblocks), dim3(256), 0, s, S, restart, b, ctx->x, ctx->r, ctx->p,
-                       ctx->dinv, ctx->partials);
+                       pre_args(ctx), ctx->partials);
     hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 0, restart, ctx->partials, ctx->st);
 }
 
@@ -661,6 +723,7 @@ static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Sched &S, cons
     ctx->gkey_dtype[variant] = (int)sizeof(TB);
     ctx->gkey_chunk[variant] = chunk;
     ctx->gkey_sched[variant] = ctx->sched_version;
+    ctx->gkey_pre[variant] = ctx->precond;
     return PC_OK;
 }
 
@@ -744,7 +807,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
             return PC_ERR_ARG;
         }
         int used = 0;
-        if ((st = mlp_start(ctx, ctx->mlp, ctx->last_x, ctx->last_v, b, dv, ctx->x, &used, s))) return st;
+        if ((st = mlp_start(ctx, ctx->mlp, ctx->last_x, ctx->last_v, b, dv, ctx->x, ctx->q, &used, s))) return st;
         warm_kind = used;
     } else if (warm) {
         hipLaunchKernelGGL(k_copy_d, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, dv, ctx->x);
@@ -757,26 +820,10 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
     hipLaunchKernelGGL(k_state_init, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, ctx->st,
                        (const uint8_t *)nullptr, tol, rho, ctx->maxit_d);
     if (warm_kind) {
+        // the start is used as given: its residual norm is no guide to the
+        // CG iterations it saves (a start accurate in the slowly converging
+        // smooth modes can have a residual above ||b||)
         launch_residual(ctx, Mhi, S, g, nullptr, b, ctx->x, 0, nullptr, s);
-        PC_HIP(hipGetLastError());
-        if ((st = read_states(ctx, s))) return st;
-        // a start worse than zero in residual norm is replaced by the zero start
-        std::vector<uint8_t> worse(ninst, 0);
-        bool any = false;
-        for (int i = 0; i < ninst; ++i) {
-            const PcgState &h = ctx->st_host[i];
-            if (!(h.flags & 2) && h.rr0 > h.bb && h.bb > 0.0) {
-                worse[i] = 1;
-                wused[i] = 0;
-                any = true;
-            }
-        }
-        if (any) {
-            if ((st = upload_flags(ctx, worse, s))) return st;
-            hipLaunchKernelGGL(k_state_init, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, ctx->st, ctx->restart,
-                               tol, rho, ctx->maxit_d);
-            launch_start_zero(ctx, S, g, ctx->restart, b, s);
-        }
     } else {
         launch_start_zero(ctx, S, g, nullptr, b, s);
     }
@@ -784,6 +831,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
     for (int i = 0; i < ninst; ++i) sweeps[i] = 1;
     bool inner_hi = false;
     int guard = 0;
+    long long nchunk = 0;
     for (;;) {
         if ((st = read_states(ctx, s))) return st;
         // iterate until every instance is done
@@ -793,7 +841,8 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
             const SpmvArgs &Mv = inner_hi ? Mhi : M;
             const int want_size = inner_hi ? (int)sizeof(double) : (int)sizeof(TB);
             if (!ctx->gexec[variant] || ctx->gkey[variant] != Mv.jval || ctx->gkey_dtype[variant] != want_size ||
-                ctx->gkey_chunk[variant] != ctx->graph_chunk || ctx->gkey_sched[variant] != ctx->sched_version) {
+                ctx->gkey_chunk[variant] != ctx->graph_chunk || ctx->gkey_sched[variant] != ctx->sched_version ||
+                ctx->gkey_pre[variant] != ctx->precond) {
                 st = inner_hi ? capture_chunk<double>(ctx, Mhi, S, g, ctx->graph_chunk, variant)
                               : capture_chunk<TB>(ctx, M, S, g, ctx->graph_chunk, variant);
                 if (st) return st;
@@ -810,10 +859,13 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
                 }
             }
             if (all_done) break;
-            if (graph) {
+            // with profiling on, one chunk in 8 runs as plain launches so that
+            // the sampled events time the same kernels the graph replays
+            const bool sample = ctx->prof.every > 0 && (nchunk++ % 8) == 0;
+            if (graph && !sample) {
                 PC_HIP(hipGraphLaunch(ctx->gexec[variant], s));
             } else {
-                int chunk = check > 0 ? check : std::min(256, std::max(16, most / 4));
+                int chunk = graph ? ctx->graph_chunk : (check > 0 ? check : std::min(256, std::max(16, most / 4)));
                 for (int c = 0; c < chunk; ++c) {
                     if (inner_hi)
                         launch_iter<double>(ctx, Mhi, S, g, s);
@@ -1022,6 +1074,7 @@ pc_status pcg_run(Ctx *ctx, const double *b, double *dv, const pc_solve_opts *o,
         ctx->err = "cloth_pcg_solve: nothing assembled";
         return PC_ERR_ARG;
     }
+    ctx->precond = o ? o->precond : 0;
     switch (ctx->dtype) {
         case PC_F64: return pcg_typed<double>(ctx, b, dv, o, info, s);
         case PC_F32: return pcg_typed<float>(ctx, b, dv, o, info, s);

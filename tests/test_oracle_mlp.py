@@ -137,3 +137,25 @@ def test_energy_training_reduces_the_loss(M, oracle_mod):
         losses.append(L)
         M.adam_step(params, M.backward(params, X, hs, gy), state, lr=3e-3)
     assert losses[-1] < losses[0] - 0.1 * abs(losses[0])
+
+
+def test_line_search_start_minimises_energy_along_the_correction(M, oracle_mod):
+    """The start dv_prev + g u is the minimiser of the quadratic energy
+    E(x) = x.A x / 2 - b.x on the line dv_prev + t u: E there is below E at
+    dv_prev and at every other t, and dE/dt vanishes at g."""
+    c, P, A, x, v = small_system(oracle_mod)
+    apply_A = lambda z: P.spmv(A, z)
+    rng = np.random.default_rng(9)
+    dvp = 0.01 * rng.normal(size=x.shape)
+    u = 0.01 * rng.normal(size=x.shape)
+    u[c.pinned == 1] = 0
+    E = lambda z: 0.5 * float((z * apply_A(z)).sum()) - float((A.b * z).sum())
+    s0, g = M.line_search_start(apply_A, A.b, dvp, u)
+    assert E(s0) <= E(dvp)
+    for t in np.linspace(g - 1.0, g + 1.0, 11):
+        assert E(s0) <= E(dvp + t * u) + 1e-15 * abs(E(s0))
+    # stationarity: u.(A s0 - b) = 0
+    assert abs(float((u * (apply_A(s0) - A.b)).sum())) <= 1e-9 * abs(float((u * A.b).sum()))
+    # zero correction: g = 0 and the start is dv_prev
+    s1, g1 = M.line_search_start(apply_A, A.b, dvp, np.zeros_like(u))
+    assert g1 == 0.0 and np.array_equal(s1, dvp)
