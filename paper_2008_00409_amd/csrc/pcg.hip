@@ -39,13 +39,33 @@ struct SpmvArgs {
     const double *mass;
 };
 
-// Streamed (read-once per product) loads bypass cache retention so that the
-// gathered vector stays resident.
-__device__ __forceinline__ double ld_stream(const double *p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ float ld_stream(const float *p) { return __builtin_nontemporal_load(p); }
-__device__ __forceinline__ bf16_t ld_stream(const bf16_t *p) {
-    return bf16_t{__builtin_nontemporal_load(&p->bits)};
+// Tuning knobs of the SpMV row loop (compile time):
+//   PC_SPMV_NT      1: block values and column indices are read with the
+//                   non-temporal hint, so the gathered vector stays cached
+//   PC_SPMV_UNROLL  slots whose loads are issued together
+//   PC_SPMV_PIPE    1: the loads of the next group of slots are issued
+//                   before the arithmetic of the current group
+#ifndef PC_SPMV_NT
+#define PC_SPMV_NT 0
+#endif
+#ifndef PC_SPMV_UNROLL
+#define PC_SPMV_UNROLL 4
+#endif
+#ifndef PC_SPMV_PIPE
+#define PC_SPMV_PIPE 0
+#endif
+
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T *p) {
+#if PC_SPMV_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
 }
+__device__ __forceinline__ double ld_stream(const double *p) { return ld_nt(p); }
+__device__ __forceinline__ float ld_stream(const float *p) { return ld_nt(p); }
+__device__ __forceinline__ bf16_t ld_stream(const bf16_t *p) { return bf16_t{ld_nt(&p->bits)}; }
 
 struct VecF4 {
     const float4 *p;
@@ -66,7 +86,53 @@ struct VecD3 {
 // per-slot values are read with readlane instead of memory loads; slots are
 // processed UNROLL at a time with all column-index and value loads of the
 // group issued before the gathers of x, to keep several loads in flight.
-template <typename TB, typename V, int UNROLL = 4>
+// The loop body is branch-free so that the compiler can keep every load of
+// a group in flight: lanes past a slot's row count (and slots past the
+// row's last) load a valid neighbouring element and their contribution is
+// masked afterwards; the diagonal slot gathers x_i itself.
+template <typename TB, int UNROLL>
+struct SlotGroup {
+    int jc[UNROLL];
+    TB v[UNROLL][9];
+    bool act[UNROLL];
+
+    __device__ __forceinline__ void load(const SpmvArgs &M, int k, int nslots, int lane, int my_cnt, int my_off) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int kk = min(k + u, nslots - 1);
+            const int c = __builtin_amdgcn_readlane(my_cnt, kk);   // >= 1 since kk < nslots
+            const int off = __builtin_amdgcn_readlane(my_off, kk);
+            act[u] = (k + u < nslots) && lane < c;
+            const int l = min(lane, c - 1);
+            jc[u] = ld_nt(M.jcol + off + l);
+            const TB *vp = (const TB *)M.jval + 9 * (int64_t)off + l;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) v[u][e] = ld_stream(vp + (int64_t)e * c);
+        }
+    }
+
+    template <typename V>
+    __device__ __forceinline__ void apply(const V &x, int row, double x0, double x1, double x2, double &a0,
+                                          double &a1, double &a2) const {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            double d0, d1, d2;
+            x.load(jc[u], d0, d1, d2);
+            const bool off_diag = jc[u] != row;
+            d0 -= off_diag ? x0 : 0.0;
+            d1 -= off_diag ? x1 : 0.0;
+            d2 -= off_diag ? x2 : 0.0;
+            d0 = act[u] ? d0 : 0.0;
+            d1 = act[u] ? d1 : 0.0;
+            d2 = act[u] ? d2 : 0.0;
+            a0 += to_f64(v[u][0]) * d0 + to_f64(v[u][1]) * d1 + to_f64(v[u][2]) * d2;
+            a1 += to_f64(v[u][3]) * d0 + to_f64(v[u][4]) * d1 + to_f64(v[u][5]) * d2;
+            a2 += to_f64(v[u][6]) * d0 + to_f64(v[u][7]) * d1 + to_f64(v[u][8]) * d2;
+        }
+    }
+};
+
+template <typename TB, typename V, int UNROLL = PC_SPMV_UNROLL>
 __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, const V &x, double y[3],
                                         double xi[3]) {
     const int row = M.lane_row[slice * WAVE + lane];
@@ -77,39 +143,22 @@ __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, 
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (row >= 0) x.load(row, x0, x1, x2);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#if PC_SPMV_PIPE
+    SlotGroup<TB, UNROLL> cur;
+    cur.load(M, 0, nslots, lane, my_cnt, my_off);
     for (int k = 0; k < nslots; k += UNROLL) {
-        int jc[UNROLL];
-        TB v[UNROLL][9];
-        bool act[UNROLL];
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            const int kk = min(k + u, WAVE - 1);
-            const int c = __builtin_amdgcn_readlane(my_cnt, kk);
-            const int off = __builtin_amdgcn_readlane(my_off, kk);
-            act[u] = (k + u < nslots) && lane < c;
-            jc[u] = row;
-            if (act[u]) {
-                jc[u] = __builtin_nontemporal_load(M.jcol + off + lane);
-                const TB *vp = (const TB *)M.jval + 9 * (int64_t)off + lane;
-#pragma unroll
-                for (int e = 0; e < 9; ++e) v[u][e] = ld_stream(vp + (int64_t)e * c);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            if (!act[u]) continue;
-            double d0, d1, d2;
-            if (jc[u] == row) {
-                d0 = x0; d1 = x1; d2 = x2;
-            } else {
-                x.load(jc[u], d0, d1, d2);
-                d0 -= x0; d1 -= x1; d2 -= x2;
-            }
-            a0 += to_f64(v[u][0]) * d0 + to_f64(v[u][1]) * d1 + to_f64(v[u][2]) * d2;
-            a1 += to_f64(v[u][3]) * d0 + to_f64(v[u][4]) * d1 + to_f64(v[u][5]) * d2;
-            a2 += to_f64(v[u][6]) * d0 + to_f64(v[u][7]) * d1 + to_f64(v[u][8]) * d2;
-        }
+        SlotGroup<TB, UNROLL> nxt;
+        nxt.load(M, k + UNROLL, nslots, lane, my_cnt, my_off);
+        cur.apply(x, row, x0, x1, x2, a0, a1, a2);
+        cur = nxt;
     }
+#else
+    for (int k = 0; k < nslots; k += UNROLL) {
+        SlotGroup<TB, UNROLL> g;
+        g.load(M, k, nslots, lane, my_cnt, my_off);
+        g.apply(x, row, x0, x1, x2, a0, a1, a2);
+    }
+#endif
     if (row >= 0) {
         const double m = M.mass[row];
         y[0] = a0 + m * x0;
