@@ -65,7 +65,7 @@ static void free_all(Ctx *c) {
     void *ptrs[] = {c->tri, c->Bm, c->A0, c->hinge, c->hcoef, c->htbar, c->mass, c->pinned, c->status,
                     c->inc_cnt, c->inc_ptr, c->inc, c->rowlen, c->rowptr, c->colidx, c->jcol, c->lane_row,
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
-                    c->p, c->partials, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0,
+                    c->p, c->partials, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase,
                     c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -171,7 +171,6 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
     ALLOC(ctx->rowlen, sizeof(int) * (size_t)nv);
     ALLOC(ctx->rowptr, sizeof(int) * (size_t)(nv + 1));
     ALLOC(ctx->colidx, sizeof(int) * (size_t)ctx->cap);
-    ALLOC(ctx->jcol, sizeof(int) * (size_t)ctx->cap);
     ALLOC(ctx->row_lane, sizeof(int) * (size_t)nv);
     ALLOC(ctx->diag, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->dinv, sizeof(float) * 3 * (size_t)nv);

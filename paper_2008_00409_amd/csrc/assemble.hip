@@ -444,7 +444,7 @@ struct AsmArgs {
     const double *x, *v;
     DevParams prm;
     int *rowlen, *rowptr, *colidx, *jcol;
-    const int *row_lane, *row_slice, *slice_row0;
+    const int *row_lane, *row_slice, *slice_row0, *slice_vbase;
     const uint8_t *slot_cnt;
     void *jval;
     double *jval_hi;   // FP64 copy (nullptr when the solver copy is FP64)
@@ -542,10 +542,12 @@ __global__ void __launch_bounds__(64) k_row_pattern(AsmArgs A) {
 // Solver layout of one slice (up to 64 consecutive rows of one instance):
 // rows ordered by decreasing length (ties by row), lane_row / row_lane give
 // the order, slot_cnt[k] = rows with more than k blocks.  Block k of the row
-// in lane l of slice s then sits at rowptr[slice_row0[s]] +
-// sum_{k' < k} slot_cnt[k'] + l.
+// in lane l of slice s then sits at slice_vbase[s] +
+// sum_{k' < k} slot_width(slot_cnt[k']) + l (slice_vbase: exclusive scan of
+// slice_psize, the padded block count of each slice).
 __global__ void __launch_bounds__(64) k_slice_layout(int nslices, const int *slice_row0, const int *rowlen,
-                                                     int *lane_row, int *row_lane, uint8_t *slot_cnt) {
+                                                     int *lane_row, int *row_lane, uint8_t *slot_cnt,
+                                                     int *slice_psize) {
     const int s = blockIdx.x;
     if (s >= nslices) return;
     const int t = threadIdx.x;
@@ -564,6 +566,8 @@ __global__ void __launch_bounds__(64) k_slice_layout(int nslices, const int *sli
         if (t == k) c = __popcll(bal);
     }
     slot_cnt[s * WAVE + t] = (uint8_t)c;
+    const int padded = wave_sum_int(slot_width(c));
+    if (t == 0) slice_psize[s] = padded;
 }
 
 // A row that overflowed the per-row limits has length 1 (set by the pattern
@@ -572,15 +576,14 @@ __global__ void __launch_bounds__(64) k_slice_layout(int nslices, const int *sli
 template <typename TB>
 __device__ void write_overflow_row(const AsmArgs &A, int i) {
     const int s = A.row_slice[i];
-    const int64_t seg = A.rowptr[A.slice_row0[s]];
-    const int cnt = (int)A.slot_cnt[s * WAVE];
+    const int64_t seg = A.slice_vbase[s];
+    const int w = slot_width((int)A.slot_cnt[s * WAVE]);
     const int lane = A.row_lane[i];
     A.colidx[A.rowptr[i]] = i;
     A.jcol[seg + lane] = i;
-    TB *val = (TB *)A.jval + 9 * seg + lane;
-    for (int q = 0; q < 9; ++q) val[(int64_t)q * cnt] = from_f64<TB>(0.0);
-    if (A.jval_hi)
-        for (int q = 0; q < 9; ++q) A.jval_hi[9 * seg + lane + (int64_t)q * cnt] = 0.0;
+    const double zero[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    BlockIO<TB>::store((TB *)A.jval + 9 * seg, w, lane, zero);
+    if (A.jval_hi) BlockIO<double>::store(A.jval_hi + 9 * seg, w, lane, zero);
     const double mi = A.mass[i];
     for (int a = 0; a < 3; ++a) {
         A.b[3 * i + a] = 0.0;
@@ -817,21 +820,15 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
 
     // block-CSR pattern and solver layout
     const int s = A.row_slice[i];
-    const int cnt = (int)A.slot_cnt[s * WAVE + t];
-    const int off = wave_excl_scan(cnt);
+    const int w = slot_width((int)A.slot_cnt[s * WAVE + t]);
+    const int off = wave_excl_scan(w);
     if (active) {
         A.colidx[A.rowptr[i] + t] = col;
-        const int64_t seg = (int64_t)A.rowptr[A.slice_row0[s]] + off;
+        const int64_t seg = (int64_t)A.slice_vbase[s] + off;
         const int lane = A.row_lane[i];
         A.jcol[seg + lane] = col;
-        TB *val = (TB *)A.jval + 9 * seg + lane;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) val[(int64_t)q * cnt] = from_f64<TB>(blk[q]);
-        if (A.jval_hi) {
-            double *hv = A.jval_hi + 9 * seg + lane;
-#pragma unroll
-            for (int q = 0; q < 9; ++q) hv[(int64_t)q * cnt] = blk[q];
-        }
+        BlockIO<TB>::store((TB *)A.jval + 9 * seg, w, lane, blk);
+        if (A.jval_hi) BlockIO<double>::store(A.jval_hi + 9 * seg, w, lane, blk);
     }
 }
 
@@ -839,25 +836,27 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
 // A_ii = m_i I + D_i - sum_{j != i} A_ij; optionally D_i.
 template <typename TB>
 __global__ void __launch_bounds__(64) k_export(int nv, const int *rowptr, const int *row_lane, const int *row_slice,
-                                               const int *slice_row0, const uint8_t *slot_cnt, const int *jcol,
+                                               const int *slice_vbase, const uint8_t *slot_cnt, const int *jcol,
                                                const void *jval, const double *mass, double *out, double *Dout) {
     const int i = blockIdx.x;
     if (i >= nv) return;
     const int t = threadIdx.x;
     const int s = row_slice[i];
-    const int cnt = (int)slot_cnt[s * WAVE + t];
-    const int off = wave_excl_scan(cnt);
+    const int w = slot_width((int)slot_cnt[s * WAVE + t]);
+    const int off = wave_excl_scan(w);
     const int len = rowptr[i + 1] - rowptr[i];
     const bool active = t < len;
     double blk[9];
     int col = -1;
     if (active) {
-        const int64_t seg = (int64_t)rowptr[slice_row0[s]] + off;
+        // element-wise reads through val_index (the solver reads whole blocks
+        // through BlockIO; the two must agree)
+        const int64_t seg = (int64_t)slice_vbase[s] + off;
         const int lane = row_lane[i];
         col = jcol[seg + lane];
-        const TB *val = (const TB *)jval + 9 * seg + lane;
+        const TB *val = (const TB *)jval + 9 * seg;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) blk[q] = to_f64(val[(int64_t)q * cnt]);
+        for (int q = 0; q < 9; ++q) blk[q] = to_f64(val[val_index<TB>(q, w, lane)]);
     } else {
 #pragma unroll
         for (int q = 0; q < 9; ++q) blk[q] = 0.0;
@@ -890,7 +889,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     const int nv = ctx->nv, nt = ctx->nt, nh = ctx->nh;
     const int TB = 256;
     pc_status st;
-    const size_t need = (size_t)ctx->cap * 9 * dtype_size(dtype);
+    const size_t need = (size_t)ctx->vcap * 9 * dtype_size(dtype);
     if (need > ctx->jval_bytes) {
         if (ctx->jval) (void)hipFree(ctx->jval);
         ctx->jval = nullptr;
@@ -901,8 +900,12 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     ctx->dtype = dtype;
     ctx->last_x = x;
     ctx->last_v = v;
-    if (dtype != PC_F64 && !ctx->jval_hi) {
-        if ((st = dev_alloc(ctx, (void **)&ctx->jval_hi, (size_t)ctx->cap * 9 * sizeof(double)))) return st;
+    if (dtype != PC_F64 && ctx->hi_blocks < ctx->vcap) {
+        if (ctx->jval_hi) (void)hipFree(ctx->jval_hi);
+        ctx->jval_hi = nullptr;
+        ctx->hi_blocks = 0;
+        if ((st = dev_alloc(ctx, (void **)&ctx->jval_hi, (size_t)ctx->vcap * 9 * sizeof(double)))) return st;
+        ctx->hi_blocks = ctx->vcap;
     }
     ctx->hi_valid = dtype != PC_F64;
     // 1. incidence buckets
@@ -921,7 +924,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     a.pinned = ctx->pinned; a.x = x; a.v = v; a.prm = ctx->prm;
     a.rowlen = ctx->rowlen; a.rowptr = ctx->rowptr; a.colidx = ctx->colidx; a.jcol = ctx->jcol;
     a.row_lane = ctx->row_lane; a.slot_cnt = ctx->slot_cnt; a.jval = ctx->jval;
-    a.row_slice = ctx->row_slice; a.slice_row0 = ctx->slice_row0;
+    a.row_slice = ctx->row_slice; a.slice_row0 = ctx->slice_row0; a.slice_vbase = ctx->slice_vbase;
     a.jval_hi = dtype != PC_F64 ? ctx->jval_hi : nullptr;
     a.b = b; a.diag = diag_out ? diag_out : ctx->diag; a.dinv = ctx->dinv; a.binv = ctx->binv; a.status = ctx->status;
     const int nb = ((nv + 7) / 8) * 8;
@@ -931,7 +934,8 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     if ((st = scan_excl(ctx, ctx->rowlen, ctx->rowptr, nv, s))) return st;
     // 3. solver layout
     hipLaunchKernelGGL(k_slice_layout, dim3(ctx->nslices), dim3(64), 0, s, ctx->nslices, ctx->slice_row0,
-                       ctx->rowlen, ctx->lane_row, ctx->row_lane, ctx->slot_cnt);
+                       ctx->rowlen, ctx->lane_row, ctx->row_lane, ctx->slot_cnt, ctx->slice_psize);
+    if ((st = scan_excl(ctx, ctx->slice_psize, ctx->slice_vbase, ctx->nslices, s))) return st;
     // 4. values
     slot = ctx->prof.begin(PK_ROW_ASM, s);
     switch (dtype) {
@@ -958,15 +962,15 @@ pc_status export_blocks(Ctx *ctx, double *vals, double *D, bool solver, hipStrea
     switch (dt) {
         case PC_F64:
             hipLaunchKernelGGL(k_export<double>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->row_lane,
-                               ctx->row_slice, ctx->slice_row0, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
+                               ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
             break;
         case PC_F32:
             hipLaunchKernelGGL(k_export<float>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->row_lane,
-                               ctx->row_slice, ctx->slice_row0, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
+                               ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
             break;
         case PC_BF16:
             hipLaunchKernelGGL(k_export<bf16_t>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->row_lane,
-                               ctx->row_slice, ctx->slice_row0, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
+                               ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
             break;
     }
     PC_HIP(hipGetLastError());

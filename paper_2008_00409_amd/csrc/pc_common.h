@@ -117,4 +117,83 @@ template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double v) {
     return bf16_t{(uint16_t)((u + rounding) >> 16)};
 }
 
+// ---------------------------------------------------------------- solver block storage
+// Slot k of a 64-row slice (the k-th block of every row with more than k
+// blocks, c rows) is stored for w = slot_width(c) lanes, a multiple of 8, so
+// that every slot starts 16-byte aligned (its first block has index voff, a
+// multiple of 8, and its values start at element 9 voff).  Inside the slot
+// the first 8 values of each block are 16-byte chunks (CE = 16 / sizeof(TB)
+// values per chunk; chunk plane q holds values CE q .. CE q + CE - 1 of every
+// lane) and value 8 has a plane of its own:
+//   value e < 8 of lane l at  q w CE + l CE + e % CE   (q = e / CE),
+//   value 8       of lane l at  8 w + l.
+__host__ __device__ __forceinline__ int slot_width(int c) { return (c + 7) & ~7; }
+
+template <typename TB>
+__device__ __forceinline__ int64_t val_index(int e, int w, int l) {
+    constexpr int CE = 16 / (int)sizeof(TB);
+    return e < 8 ? (int64_t)(e / CE) * w * CE + (int64_t)l * CE + (e % CE) : 8 * (int64_t)w + l;
+}
+
+// Whole-block load / store of lane l in a slot of width w whose values start
+// at seg (16-byte aligned): vector accesses of the chunks, one scalar access
+// for value 8.  R is the register type the loads convert to.
+template <typename TB> struct BlockIO;
+
+template <> struct BlockIO<float> {
+    typedef float R;
+    __device__ __forceinline__ static void load(const float *seg, int w, int l, float v[9]) {
+        const float4 a = reinterpret_cast<const float4 *>(seg)[l];
+        const float4 b = reinterpret_cast<const float4 *>(seg + 4 * (int64_t)w)[l];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        v[8] = seg[8 * (int64_t)w + l];
+    }
+    __device__ __forceinline__ static void store(float *seg, int w, int l, const double b[9]) {
+        reinterpret_cast<float4 *>(seg)[l] = make_float4((float)b[0], (float)b[1], (float)b[2], (float)b[3]);
+        reinterpret_cast<float4 *>(seg + 4 * (int64_t)w)[l] =
+            make_float4((float)b[4], (float)b[5], (float)b[6], (float)b[7]);
+        seg[8 * (int64_t)w + l] = (float)b[8];
+    }
+};
+
+template <> struct BlockIO<bf16_t> {
+    typedef float R;
+    __device__ __forceinline__ static void load(const bf16_t *seg, int w, int l, float v[9]) {
+        const uint4 a = reinterpret_cast<const uint4 *>(seg)[l];
+        v[0] = __uint_as_float(a.x << 16); v[1] = __uint_as_float(a.x & 0xffff0000u);
+        v[2] = __uint_as_float(a.y << 16); v[3] = __uint_as_float(a.y & 0xffff0000u);
+        v[4] = __uint_as_float(a.z << 16); v[5] = __uint_as_float(a.z & 0xffff0000u);
+        v[6] = __uint_as_float(a.w << 16); v[7] = __uint_as_float(a.w & 0xffff0000u);
+        v[8] = __uint_as_float(((unsigned)seg[8 * (int64_t)w + l].bits) << 16);
+    }
+    __device__ __forceinline__ static void store(bf16_t *seg, int w, int l, const double b[9]) {
+        unsigned u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            u[q] = (unsigned)from_f64<bf16_t>(b[2 * q]).bits | ((unsigned)from_f64<bf16_t>(b[2 * q + 1]).bits << 16);
+        reinterpret_cast<uint4 *>(seg)[l] = make_uint4(u[0], u[1], u[2], u[3]);
+        seg[8 * (int64_t)w + l] = from_f64<bf16_t>(b[8]);
+    }
+};
+
+template <> struct BlockIO<double> {
+    typedef double R;
+    __device__ __forceinline__ static void load(const double *seg, int w, int l, double v[9]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double2 a = reinterpret_cast<const double2 *>(seg + 2 * (int64_t)q * w)[l];
+            v[2 * q] = a.x;
+            v[2 * q + 1] = a.y;
+        }
+        v[8] = seg[8 * (int64_t)w + l];
+    }
+    __device__ __forceinline__ static void store(double *seg, int w, int l, const double b[9]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            reinterpret_cast<double2 *>(seg + 2 * (int64_t)q * w)[l] = make_double2(b[2 * q], b[2 * q + 1]);
+        seg[8 * (int64_t)w + l] = b[8];
+    }
+};
+
 }  // namespace pc

@@ -123,7 +123,12 @@ struct Ctx {
     uint8_t *slot_cnt = nullptr;  // nslices * 64
     int *slice_row0 = nullptr;    // nslices + 1: first row of each slice
     int *row_slice = nullptr;     // nv: slice of each row
+    int *slice_psize = nullptr;   // nslices: stored (padded) blocks of each slice
+    int *slice_vbase = nullptr;   // nslices + 1: first stored block of each slice
     int slice_cap = 0;            // slices the layout arrays can hold
+    int64_t vcap = 0;             // stored-block capacity: cap + padding bound of the slices
+    int64_t jcol_blocks = 0;      // blocks jcol can hold
+    int64_t hi_blocks = 0;        // blocks jval_hi can hold
 
     // instances and work schedules (one instance unless pc_set_instances)
     int ninst = 1;

@@ -31,7 +31,7 @@ namespace pc {
 struct SpmvArgs {
     int nv, nslices;
     const int *rowptr;
-    const int *slice_row0;
+    const int *slice_vbase;
     const uint8_t *slot_cnt;
     const int *lane_row;
     const int *jcol;
@@ -40,32 +40,15 @@ struct SpmvArgs {
 };
 
 // Tuning knobs of the SpMV row loop (compile time):
-//   PC_SPMV_NT      1: block values and column indices are read with the
-//                   non-temporal hint, so the gathered vector stays cached
 //   PC_SPMV_UNROLL  slots whose loads are issued together
 //   PC_SPMV_PIPE    1: the loads of the next group of slots are issued
 //                   before the arithmetic of the current group
-#ifndef PC_SPMV_NT
-#define PC_SPMV_NT 0
-#endif
 #ifndef PC_SPMV_UNROLL
-#define PC_SPMV_UNROLL 4
+#define PC_SPMV_UNROLL 2
 #endif
 #ifndef PC_SPMV_PIPE
-#define PC_SPMV_PIPE 0
+#define PC_SPMV_PIPE 1
 #endif
-
-template <typename T>
-__device__ __forceinline__ T ld_nt(const T *p) {
-#if PC_SPMV_NT
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
-__device__ __forceinline__ double ld_stream(const double *p) { return ld_nt(p); }
-__device__ __forceinline__ float ld_stream(const float *p) { return ld_nt(p); }
-__device__ __forceinline__ bf16_t ld_stream(const bf16_t *p) { return bf16_t{ld_nt(&p->bits)}; }
 
 struct VecF4 {
     const float4 *p;
@@ -89,11 +72,13 @@ struct VecD3 {
 // The loop body is branch-free so that the compiler can keep every load of
 // a group in flight: lanes past a slot's row count (and slots past the
 // row's last) load a valid neighbouring element and their contribution is
-// masked afterwards; the diagonal slot gathers x_i itself.
+// masked afterwards; the diagonal slot gathers x_i itself.  Each block is
+// read with 16-byte loads (BlockIO).
 template <typename TB, int UNROLL>
 struct SlotGroup {
+    typedef typename BlockIO<TB>::R R;
     int jc[UNROLL];
-    TB v[UNROLL][9];
+    R v[UNROLL][9];
     bool act[UNROLL];
 
     __device__ __forceinline__ void load(const SpmvArgs &M, int k, int nslots, int lane, int my_cnt, int my_off) {
@@ -104,13 +89,10 @@ struct SlotGroup {
             const int off = __builtin_amdgcn_readlane(my_off, kk);
             act[u] = (k + u < nslots) && lane < c;
             const int l = min(lane, c - 1);
-            jc[u] = ld_nt(M.jcol + off + l);
-            const TB *vp = (const TB *)M.jval + 9 * (int64_t)off + l;
-#pragma unroll
-            for (int e = 0; e < 9; ++e) v[u][e] = ld_stream(vp + (int64_t)e * c);
+            jc[u] = M.jcol[off + l];
+            BlockIO<TB>::load((const TB *)M.jval + 9 * (int64_t)off, slot_width(c), l, v[u]);
         }
     }
-
     template <typename V>
     __device__ __forceinline__ void apply(const V &x, int row, double x0, double x1, double x2, double &a0,
                                           double &a1, double &a2) const {
@@ -136,9 +118,8 @@ template <typename TB, typename V, int UNROLL = PC_SPMV_UNROLL>
 __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, const V &x, double y[3],
                                         double xi[3]) {
     const int row = M.lane_row[slice * WAVE + lane];
-    const int base = M.rowptr[M.slice_row0[slice]];
     const int my_cnt = (int)M.slot_cnt[slice * WAVE + lane];
-    const int my_off = base + wave_excl_scan(my_cnt);
+    const int my_off = M.slice_vbase[slice] + wave_excl_scan(slot_width(my_cnt));
     const int nslots = __popcll(__ballot(my_cnt > 0));  // counts are non-increasing in the slot
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (row >= 0) x.load(row, x0, x1, x2);
@@ -583,7 +564,7 @@ static SpmvArgs spmv_args(Ctx *ctx, bool hi) {
     M.nv = ctx->nv;
     M.nslices = ctx->nslices;
     M.rowptr = ctx->rowptr;
-    M.slice_row0 = ctx->slice_row0;
+    M.slice_vbase = ctx->slice_vbase;
     M.slot_cnt = ctx->slot_cnt;
     M.lane_row = ctx->lane_row;
     M.jcol = ctx->jcol;
@@ -649,7 +630,21 @@ pc_status build_schedule(Ctx *ctx) {
         if ((st = realloc((void **)&ctx->lane_row, sizeof(int) * (size_t)nslices * WAVE))) return st;
         if ((st = realloc((void **)&ctx->slot_cnt, (size_t)nslices * WAVE))) return st;
         if ((st = realloc((void **)&ctx->slice_row0, sizeof(int) * (size_t)(nslices + 1)))) return st;
+        if ((st = realloc((void **)&ctx->slice_psize, sizeof(int) * (size_t)nslices))) return st;
+        if ((st = realloc((void **)&ctx->slice_vbase, sizeof(int) * (size_t)(nslices + 1)))) return st;
         ctx->slice_cap = nslices;
+    }
+    // stored blocks: the pattern's blocks plus at most 7 padding lanes in each
+    // of the (at most 64) slots of every slice
+    const int64_t vcap = ctx->cap + (int64_t)7 * WAVE * nslices;
+    if (vcap >= ((int64_t)1 << 31) / 9) {
+        ctx->err = "stored block capacity exceeds int32 indexing";
+        return PC_ERR_CAPACITY;
+    }
+    ctx->vcap = vcap;
+    if (vcap > ctx->jcol_blocks) {
+        if ((st = realloc((void **)&ctx->jcol, sizeof(int) * (size_t)vcap))) return st;
+        ctx->jcol_blocks = vcap;
     }
     if ((st = realloc((void **)&ctx->sitem, sizeof(int4) * sitems.size()))) return st;
     if ((st = realloc((void **)&ctx->vitem, sizeof(int4) * vitems.size()))) return st;
