@@ -171,11 +171,16 @@ def main():
         ctx = binding.Context.from_cloth(cloth)
         x = torch.from_numpy(cloth.x0.copy()).cuda()
         v = torch.from_numpy(cloth.v0.copy()).cuda()
+        tune_plain = None
+        if args.autotune:   # the same launch-schedule search as the project configuration
+            tune_plain = ctx.autotune(ctx.cloth_assemble(x, v, "f32"), iters=64, precond="jacobi")
+            log(f"# autotune (plain): {tune_plain}")
         el, infos, prof = time_steps(ctx, x, v, args.steps, args.warmup, "f32", tol, "zero", args.prof_every)
         rowptr, colidx = ctx.pattern()
         nnzb = int(colidx.numel())
         sp = prof.get("spmv", {}).get("mean_ms", float("nan"))
         rec_plain = {"steps_per_s": args.steps / el, "block_storage": "f32", "warm_start": "zero",
+                     "preconditioner": "jacobi", "schedule": tune_plain,
                      "cg_iters_per_step": [i["iters"] for i in infos],
                      "rel_res_true_max": max(i["rel_res_true"] for i in infos),
                      "spmv_mean_ms": sp, "spmv_GBs": spmv_bytes(ctx.nv, nnzb, "f32") / (sp * 1e-3) / 1e9}

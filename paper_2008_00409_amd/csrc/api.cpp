@@ -65,7 +65,7 @@ static void free_all(Ctx *c) {
     void *ptrs[] = {c->tri, c->Bm, c->A0, c->hinge, c->hcoef, c->htbar, c->mass, c->pinned, c->status,
                     c->inc_cnt, c->inc_ptr, c->inc, c->rowlen, c->rowptr, c->colidx, c->jcol, c->lane_row,
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
-                    c->p, c->partials, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase,
+                    c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase,
                     c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -236,7 +236,7 @@ pc_status pc_set_option(pc_ctx *h, int32_t option, int64_t value) {
                 ctx->err = "graph chunk must be in [0, 4096]";
                 return PC_ERR_ARG;
             }
-            ctx->graph_chunk = (int)value;
+            ctx->graph_chunk = (int)((value + 1) & ~1LL);   // even: a replay keeps the iteration parity
             return PC_OK;
         case PC_OPT_SPMV_SLICES_PER_BLOCK: {
             if (value != 1 && value != 2 && value != 4 && value != 8) {

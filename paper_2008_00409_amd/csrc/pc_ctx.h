@@ -11,8 +11,12 @@
 
 namespace pc {
 
+// CG scalars of one instance.  rz is double-buffered by iteration parity:
+// the iteration of parity P reads rzp[P] and its direction kernel, in which
+// every block computes beta itself, writes rzp[1 - P], so no block reads a
+// value another block of the same launch is writing.
 struct PcgState {
-    double rz, pq, alpha, beta, rr, bb, tol2, rz0;
+    double rzp[2], alpha, rr, bb, tol2, rz0;
     double rho2;     // inner reduction factor squared (refinement sweeps)
     double thresh;   // stop when ||r||^2 <= thresh = max(tol^2 ||b||^2, rho^2 ||r_0||^2)
     double rr0;      // ||r_0||^2 of this sweep
@@ -133,8 +137,8 @@ struct Ctx {
     // instances and work schedules (one instance unless pc_set_instances)
     int ninst = 1;
     std::vector<int> inst_row0_h;     // ninst + 1 instance row ranges
-    int spb = 4;                      // slices per SpMV work item (wavefronts per block)
-    int rpb = 256;                    // rows per vector work item
+    int spb = 8;                      // slices per SpMV work item (wavefronts per block)
+    int rpb = 512;                    // rows per vector work item
     int n_sitems = 0, n_vitems = 0;
     int4 *sitem = nullptr, *vitem = nullptr;
     int *inst_sitem0 = nullptr, *inst_vitem0 = nullptr;
@@ -159,7 +163,9 @@ struct Ctx {
     float4 *p = nullptr;
     float4 *zb = nullptr;         // preconditioned residual (block Jacobi)
     int precond = 0;              // preconditioner of the current / last solve
-    double *partials = nullptr;   // per-block partial sums (4 doubles per block)
+    double *partials = nullptr;   // per-block partial sums (4 doubles per block): SpMV, starts, checks
+    double *partials_u = nullptr; // per-block partial sums of the CG update (2 doubles per block)
+    int cg_par = 0;               // parity of the next CG iteration launched
     double *res2 = nullptr;       // 2 doubles per instance: true-residual check
     unsigned *counter = nullptr;
     PcgState *st = nullptr;       // device, one per instance

@@ -250,7 +250,7 @@ __global__ void k_state_init(int ninst, PcgState *st, const uint8_t *restart, do
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ninst || (restart && !restart[i])) return;
     PcgState &S = st[i];
-    S.rz = S.pq = S.alpha = S.beta = S.rr = S.bb = 0.0;
+    S.rzp[0] = S.rzp[1] = S.alpha = S.rr = S.bb = 0.0;
     S.tol2 = tol * tol;
     S.rho2 = rho * rho;
     S.thresh = 0.0;
@@ -287,16 +287,17 @@ __global__ void __launch_bounds__(512) k_pcg_spmv(SpmvArgs M, Sched S, const flo
     block_partials<1>(v, partials, it, S.n_sitems);
 }
 
-// alpha = rz / p.q per instance; a non-positive or non-finite p.q ends the sweep.
-__global__ void __launch_bounds__(256) k_fin_alpha(Sched S, const double *partials, PcgState *st) {
+// alpha = rz / p.q per instance; a non-positive or non-finite p.q ends the
+// sweep.  (A single block: summing the SpMV partials in every block of the
+// update measured slower than this extra launch.)
+__global__ void __launch_bounds__(256) k_fin_alpha(Sched S, int par, const double *partials, PcgState *st) {
     const int inst = blockIdx.x;
     if (inst >= S.ninst || st[inst].done) return;
     double tot[1];
     instance_sum<1>(partials, S.n_sitems, S.inst_sitem0[inst], S.inst_sitem0[inst + 1], tot);
     if (threadIdx.x == 0) {
         PcgState &T = st[inst];
-        const double a = T.rz / tot[0];
-        T.pq = tot[0];
+        const double a = T.rzp[par] / tot[0];
         T.alpha = a;
         if (!(tot[0] > 0.0) || !isfinite(a)) {
             T.flags |= isfinite(tot[0]) ? 1 : 2;
@@ -310,7 +311,7 @@ __global__ void __launch_bounds__(256) k_fin_alpha(Sched S, const double *partia
 // (z = P^-1 r) and r.r.  Block Jacobi stages each 256-row chunk of r in LDS,
 // then one thread per row applies the inverse block and stores z.
 __global__ void __launch_bounds__(256) k_pcg_update(Sched S, double *x, double *r, const float *pf, const double *q,
-                                                    PreArgs P, const PcgState *st, double *partials) {
+                                                    PreArgs P, const PcgState *st, double *part_u) {
     __shared__ double rs[3 * 256];
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
@@ -354,39 +355,39 @@ __global__ void __launch_bounds__(256) k_pcg_update(Sched S, double *x, double *
         }
     }
     double v[2] = {rz, rr};
-    block_partials<2>(v, partials, it, S.n_vitems);
+    block_partials<2>(v, part_u, it, S.n_vitems);
 }
 
-// beta = rz_new / rz; convergence test ||r||^2 <= thresh; iteration count.
-__global__ void __launch_bounds__(256) k_fin_beta(Sched S, const double *partials, PcgState *st) {
-    const int inst = blockIdx.x;
-    if (inst >= S.ninst || st[inst].done) return;
-    double tot[2];
-    instance_sum<2>(partials, S.n_vitems, S.inst_vitem0[inst], S.inst_vitem0[inst + 1], tot);
-    if (threadIdx.x == 0) {
-        PcgState &T = st[inst];
-        T.beta = tot[0] / T.rz;
-        T.rz = tot[0];
-        T.rr = tot[1];
-        T.iters += 1;
-        if (!isfinite(tot[1]) || !isfinite(tot[0])) {
-            T.flags |= 2;
-            T.done = 1;
-        } else if (tot[1] <= T.thresh || T.iters >= T.maxit) {
-            T.done = 1;
-        }
-    }
-}
-
-// p = P^-1 r + beta p over the item's rows (Jacobi: from r and dinv; block
-// Jacobi: from the z stored by the update).
-__global__ void __launch_bounds__(256) k_pcg_dir(Sched S, const double *r, float4 *p, PreArgs P,
-                                                 const PcgState *st) {
+// beta = rz_new / rz (every block from the update's partials, fixed order),
+// then p = P^-1 r + beta p over the item's rows (Jacobi: from r and dinv;
+// block Jacobi: from the z stored by the update).  The first block of each
+// instance advances the instance state: rzp[1 - par] = rz_new, ||r||^2, the
+// iteration count and the convergence test ||r||^2 <= thresh.  Blocks that
+// see the instance converged skip the direction (it is not used again).
+__global__ void __launch_bounds__(256) k_pcg_dir(Sched S, int par, const double *r, float4 *p, PreArgs P,
+                                                 PcgState *st, const double *part_u) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
     if (st[I.x].done) return;
-    const double beta = st[I.x].beta;
+    double tot[2];
+    instance_sum<2>(part_u, S.n_vitems, S.inst_vitem0[I.x], S.inst_vitem0[I.x + 1], tot);
+    const double beta = tot[0] / st[I.x].rzp[par];
+    const bool bad = !isfinite(tot[1]) || !isfinite(tot[0]);
+    const bool conv = tot[1] <= st[I.x].thresh;
+    if (it == S.inst_vitem0[I.x] && threadIdx.x == 0) {
+        PcgState &T = st[I.x];
+        T.rzp[1 - par] = tot[0];
+        T.rr = tot[1];
+        T.iters += 1;
+        if (bad) {
+            T.flags |= 2;
+            T.done = 1;
+        } else if (conv || T.iters >= T.maxit) {
+            T.done = 1;
+        }
+    }
+    if (bad || conv) return;
     for (int i = I.y + threadIdx.x; i < I.z; i += blockDim.x) {
         const float4 pv = p[i];
         double z0, z1, z2;
@@ -472,7 +473,7 @@ __global__ void __launch_bounds__(512) k_residual(SpmvArgs M, Sched S, const uin
 
 // Sweep start of the flagged instances: rz, ||r_0||^2, ||b||^2 -> state
 // (threshold, early exit when the start already meets the tolerance).
-__global__ void __launch_bounds__(256) k_fin_start(Sched S, int use_sitems, const uint8_t *restart,
+__global__ void __launch_bounds__(256) k_fin_start(Sched S, int use_sitems, int par, const uint8_t *restart,
                                                    const double *partials, PcgState *st) {
     const int inst = blockIdx.x;
     if (inst >= S.ninst || (restart && !restart[inst])) return;
@@ -483,7 +484,7 @@ __global__ void __launch_bounds__(256) k_fin_start(Sched S, int use_sitems, cons
         instance_sum<3>(partials, S.n_vitems, S.inst_vitem0[inst], S.inst_vitem0[inst + 1], tot);
     if (threadIdx.x == 0) {
         PcgState &T = st[inst];
-        T.rz = tot[0];
+        T.rzp[par] = tot[0];
         T.rz0 = tot[0];
         T.rr = tot[1];
         T.bb = tot[2];
@@ -652,6 +653,7 @@ pc_status build_schedule(Ctx *ctx) {
     if ((st = realloc((void **)&ctx->inst_vitem0, sizeof(int) * (ninst + 1)))) return st;
     const size_t nitems = std::max(sitems.size(), vitems.size()) + 16;
     if ((st = realloc((void **)&ctx->partials, sizeof(double) * 4 * nitems))) return st;
+    if ((st = realloc((void **)&ctx->partials_u, sizeof(double) * 2 * nitems))) return st;
     if (ninst != ctx->ninst || !ctx->st) {
         if ((st = realloc((void **)&ctx->st, sizeof(PcgState) * ninst))) return st;
         if ((st = realloc((void **)&ctx->res2, sizeof(double) * 2 * ninst))) return st;
@@ -694,21 +696,33 @@ static Grids grids(Ctx *ctx) {
     return g;
 }
 
+// One CG iteration of parity par (the parity selects the rz slot, see
+// PcgState): SpMV with its partials, alpha, update, direction (beta from
+// the update partials, state advance).
 template <typename TB>
-static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s) {
+static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s, int par) {
     int slot = ctx->prof.begin(PK_SPMV, s);
     hipLaunchKernelGGL(k_pcg_spmv<TB>, dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, ctx->p, ctx->q, ctx->st,
                        ctx->partials);
     ctx->prof.end(slot, s);
-    hipLaunchKernelGGL(k_fin_alpha, dim3(ctx->ninst), dim3(256), 0, s, S, ctx->partials, ctx->st);
+    hipLaunchKernelGGL(k_fin_alpha, dim3(ctx->ninst), dim3(256), 0, s, S, par, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
     hipLaunchKernelGGL(k_pcg_update, dim3(g.vblocks), dim3(256), 0, s, S, ctx->x, ctx->r, (const float *)ctx->p,
-                       ctx->q, pre_args(ctx), ctx->st, ctx->partials);
+                       ctx->q, pre_args(ctx), ctx->st, ctx->partials_u);
     ctx->prof.end(slot, s);
-    hipLaunchKernelGGL(k_fin_beta, dim3(ctx->ninst), dim3(256), 0, s, S, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_DIR, s);
-    hipLaunchKernelGGL(k_pcg_dir, dim3(g.vblocks), dim3(256), 0, s, S, ctx->r, ctx->p, pre_args(ctx), ctx->st);
+    hipLaunchKernelGGL(k_pcg_dir, dim3(g.vblocks), dim3(256), 0, s, S, par, ctx->r, ctx->p, pre_args(ctx), ctx->st,
+                       ctx->partials_u);
     ctx->prof.end(slot, s);
+}
+
+// Plain launches of n iterations continuing the context's parity.
+template <typename TB>
+static void launch_iters(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s, int n) {
+    for (int c = 0; c < n; ++c) {
+        launch_iter<TB>(ctx, M, S, g, s, ctx->cg_par);
+        ctx->cg_par ^= 1;
+    }
 }
 
 // Residuals always use the FP64 blocks.  mode 0 starts a sweep from x for
@@ -720,7 +734,8 @@ static void launch_residual(Ctx *ctx, const SpmvArgs &M, const Sched &S, const G
     if (mode == 0) {
         hipLaunchKernelGGL((k_residual<TB, 0>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b, x, ctx->r,
                            ctx->p, pre_args(ctx), ctx->partials);
-        hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 1, restart, ctx->partials, ctx->st);
+        hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 1, ctx->cg_par, restart, ctx->partials,
+                           ctx->st);
     } else {
         hipLaunchKernelGGL((k_residual<TB, 1>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b, x, ctx->r,
                            ctx->p, pre_args(ctx), ctx->partials);
@@ -732,10 +747,19 @@ static void launch_start_zero(Ctx *ctx, const Sched &S, const Grids &g, const ui
                               hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_start_zero, dim3(g.vblocks), dim3(256), 0, s, S, restart, b, ctx->x, ctx->r, ctx->p,
                        pre_args(ctx), ctx->partials);
-    hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 0, restart, ctx->partials, ctx->st);
+    hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 0, ctx->cg_par, restart, ctx->partials,
+                       ctx->st);
 }
 
-// Capture `chunk` iterations on the context's capture stream.
+static bool graph_stale(const Ctx *ctx, int variant, const SpmvArgs &M, int elem_size) {
+    return !ctx->gexec[variant] || ctx->gkey[variant] != M.jval || ctx->gkey_dtype[variant] != elem_size ||
+           ctx->gkey_chunk[variant] != ctx->graph_chunk || ctx->gkey_sched[variant] != ctx->sched_version ||
+           ctx->gkey_pre[variant] != ctx->precond;
+}
+
+// Capture `chunk` (even) iterations on the context's capture stream; the
+// captured parities start at 0, so a replay must start at parity 0 and
+// leaves the parity unchanged.
 template <typename TB>
 static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, int chunk,
                                int variant) {
@@ -748,7 +772,7 @@ static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Sched &S, cons
     ctx->prof.every = 0;  // no profiler events inside the graph
     hipStream_t cs = ctx->cap_stream;
     PC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    for (int c = 0; c < chunk; ++c) launch_iter<TB>(ctx, M, S, g, cs);
+    for (int c = 0; c < chunk; ++c) launch_iter<TB>(ctx, M, S, g, cs, c & 1);
     hipGraph_t graph = nullptr;
     hipError_t ec = hipStreamEndCapture(cs, &graph);
     ctx->prof.every = saved;
@@ -843,6 +867,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
     std::vector<int> maxit_h(ninst, maxit);
     pc_status st;
 
+    ctx->cg_par = 0;
     int warm_kind = 0;
     if (warm == 2) {
         // learned start from the previous increment held in dv
@@ -884,9 +909,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
         if (graph) {
             const SpmvArgs &Mv = inner_hi ? Mhi : M;
             const int want_size = inner_hi ? (int)sizeof(double) : (int)sizeof(TB);
-            if (!ctx->gexec[variant] || ctx->gkey[variant] != Mv.jval || ctx->gkey_dtype[variant] != want_size ||
-                ctx->gkey_chunk[variant] != ctx->graph_chunk || ctx->gkey_sched[variant] != ctx->sched_version ||
-                ctx->gkey_pre[variant] != ctx->precond) {
+            if (graph_stale(ctx, variant, Mv, want_size)) {
                 st = inner_hi ? capture_chunk<double>(ctx, Mhi, S, g, ctx->graph_chunk, variant)
                               : capture_chunk<TB>(ctx, M, S, g, ctx->graph_chunk, variant);
                 if (st) return st;
@@ -906,16 +929,15 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
             // with profiling on, one chunk in 8 runs as plain launches so that
             // the sampled events time the same kernels the graph replays
             const bool sample = ctx->prof.every > 0 && (nchunk++ % 8) == 0;
-            if (graph && !sample) {
+            if (graph && !sample && ctx->cg_par == 0) {
                 PC_HIP(hipGraphLaunch(ctx->gexec[variant], s));
             } else {
                 int chunk = graph ? ctx->graph_chunk : (check > 0 ? check : std::min(256, std::max(16, most / 4)));
-                for (int c = 0; c < chunk; ++c) {
-                    if (inner_hi)
-                        launch_iter<double>(ctx, Mhi, S, g, s);
-                    else
-                        launch_iter<TB>(ctx, M, S, g, s);
-                }
+                if (graph && ctx->cg_par != 0) chunk = 1;   // back to even parity for the graph
+                if (inner_hi)
+                    launch_iters<double>(ctx, Mhi, S, g, s, chunk);
+                else
+                    launch_iters<TB>(ctx, M, S, g, s, chunk);
             }
             PC_HIP(hipGetLastError());
             if ((st = read_states(ctx, s))) return st;
@@ -1034,10 +1056,9 @@ static pc_status time_iters(Ctx *ctx, const double *b, int iters, float *ms, hip
     PC_HIP(hipMemcpyAsync(ctx->maxit_d, big.data(), sizeof(int) * ninst, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_state_init, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, ctx->st,
                        (const uint8_t *)nullptr, 0.0, 0.0, ctx->maxit_d);
+    ctx->cg_par = 0;
     launch_start_zero(ctx, S, g, nullptr, b, s);
-    if (ctx->graph_chunk > 0 &&
-        (!ctx->gexec[0] || ctx->gkey[0] != M.jval || ctx->gkey_dtype[0] != (int)sizeof(TB) ||
-         ctx->gkey_chunk[0] != ctx->graph_chunk || ctx->gkey_sched[0] != ctx->sched_version)) {
+    if (ctx->graph_chunk > 0 && graph_stale(ctx, 0, M, (int)sizeof(TB))) {
         pc_status st = capture_chunk<TB>(ctx, M, S, g, ctx->graph_chunk, 0);
         if (st) return st;
     }
@@ -1050,7 +1071,7 @@ static pc_status time_iters(Ctx *ctx, const double *b, int iters, float *ms, hip
     } else {
         const int saved = ctx->prof.every;
         ctx->prof.every = 0;
-        for (int c = 0; c < iters; ++c) launch_iter<TB>(ctx, M, S, g, s);
+        launch_iters<TB>(ctx, M, S, g, s, iters);
         ctx->prof.every = saved;
     }
     PC_HIP(hipEventRecord(e1, s));
@@ -1069,7 +1090,7 @@ pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, fl
         return PC_ERR_ARG;
     }
     const int spbs[4] = {1, 2, 4, 8};
-    const int rpbs[3] = {256, 512, 1024};
+    const int rpbs[3] = {512, 1024, 2048};
     const int chunks[2] = {0, 32};
     float best = 1e30f;
     int bs = ctx->spb, br = ctx->rpb, bc = ctx->graph_chunk;

@@ -21,6 +21,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="large", choices=["large", "medium", "batch"])
     ap.add_argument("--blocks", default="f32", choices=["f32", "bf16", "f64"])
     ap.add_argument("--iters", type=int, default=50, help="CG iterations (solve capped, tolerance unreachable)")
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "block"])
+    ap.add_argument("--spb", type=int, default=0, help="slices per SpMV block (0: library default)")
+    ap.add_argument("--rpb", type=int, default=0, help="rows per vector block (0: library default)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy")
     ap.add_argument("--copies", type=int, default=5)
     a = ap.parse_args(argv)
@@ -35,13 +38,19 @@ def main(argv=None):
     ctx = binding.Context.from_cloth(c)
     if a.workload == "batch":             # many independent cloths: per-instance CG scalars
         ctx.set_instances([r[0] for r in c.sheet_ranges] + [c.nv])
+    if a.spb:
+        ctx.set_option(binding.PC_OPT_SPMV_SLICES_PER_BLOCK, a.spb)
+    if a.rpb:
+        ctx.set_option(binding.PC_OPT_VECTOR_ROWS_PER_BLOCK, a.rpb)
     x = torch.from_numpy(c.x0.copy()).cuda()
     v = torch.from_numpy(c.v0.copy()).cuda()
-    print(f"# kernel_bench {c.name}: nv={c.nv} nt={c.nt} blocks={a.blocks} iters={a.iters}", flush=True)
+    print(f"# kernel_bench {c.name}: nv={c.nv} nt={c.nt} blocks={a.blocks} precond={a.precond} iters={a.iters}",
+          flush=True)
     b = ctx.cloth_assemble(x, v, a.blocks)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    dv, info = ctx.cloth_pcg_solve(b, tol=1e-30, maxit=a.iters, raise_on_error=False, max_sweeps=1)
+    dv, info = ctx.cloth_pcg_solve(b, tol=1e-30, maxit=a.iters, raise_on_error=False, max_sweeps=1,
+                                   precond=a.precond)
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t0
     print(f"# solve: {info['iters']} iterations in {t_solve * 1e3:.1f} ms (status {info['status']})", flush=True)
