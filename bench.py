@@ -1,12 +1,21 @@
 """Benchmark: implicit steps/s and CG iterations to 1e-6 at 1.65M triangles.
 
 One step = dynamic assembly of A and b (pattern rebuild, element evaluation,
-block reduce), Jacobi-PCG to ||r|| <= 1e-6 ||b|| and the state update, on the
-three stacked irregular sheets (3 x 550,000 triangles, 828,153 vertices,
-h = 0.01 s), synthetic seeded input.  Prints one JSON line.
+block reduce), preconditioned CG to ||b - A dv|| <= 1e-6 ||b|| (true residual
+with FP64 blocks) and the state update, on three stacked irregular sheets
+(3 x 550,000 triangles, 828,153 vertices, h = 0.01 s), seeded synthetic input
+resident in HBM.  Two configurations run on the same workload:
+
+  plain   the paper's solver: FP32 blocks, FP64 vectors, Jacobi, zero start
+  value   the project configuration: BF16 blocks with FP64 refinement sweeps,
+          block-Jacobi, learned warm start (network trained online first)
+
+Both use the autotuned launch schedule.  Prints one JSON line (stdout);
+progress goes to stderr.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--blocks f32|bf16|f64]
-       [--no-cpu-baseline] [--workload large|medium]
+       [--precond jacobi|block] [--warm zero|prev|learned] [--workload large|medium|batch]
+       [--no-plain] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -23,6 +32,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BLOCK_BYTES = {"f64": 72, "f32": 36, "bf16": 18}
+KERNEL_TB = {"f64": "double", "f32": "float", "bf16": "pc::bf16_t"}
+# committed counter summaries (profiles/) giving HBM bytes per launch
+TRAFFIC_FILES = {"k_pcg_spmv<pc::bf16_t>": "k_pcg_spmv_bf16_stacked-3x501x551_traffic.md",
+                 "k_pcg_spmv<float>": "k_pcg_spmv_f32_stacked-3x501x551_traffic.md"}
 
 
 def spmv_bytes(nv, nnzb, blocks):
@@ -30,13 +43,6 @@ def spmv_bytes(nv, nnzb, blocks):
     stored block and its column index once, the input vector once per row
     (float4), the FP64 output, the FP64 mass, and the row pointers."""
     return nnzb * (BLOCK_BYTES[blocks] + 4) + nv * (16 + 24 + 8) + 4 * (nv + 1)
-
-
-def cg_vector_bytes(nv):
-    """Algorithmic bytes of the two CG vector kernels per iteration:
-    update reads x, p, r, q, D^-1 and writes x, r; direction reads r, D^-1, p
-    and writes p (x, r, q FP64 x3; p float4; D^-1 float x3)."""
-    return nv * ((24 + 16 + 24 + 24 + 12 + 24 + 24) + (24 + 12 + 16 + 16))
 
 
 def assembly_bytes(nv, nt, nh, nnzb, blocks):
@@ -129,22 +135,59 @@ def train_warm_start(binding, meshgen, steps, adam_per_step, lr, log):
                     "workload": c.name}
 
 
+def read_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when there is none or the SpMV sources changed since it was
+    taken (the summary records a hash of them)."""
+    import re
+
+    from paper_2008_00409_amd.profile_summary import spmv_source_hash
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES.get(kernel, "-"))
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_b = re.search(r"^traffic_bytes_per_launch: (\d+)", txt, re.M)
+    m_k = re.search(r"^kernel: (.+)$", txt, re.M)
+    m_h = re.search(r"^spmv_source_hash: (\w+)", txt, re.M)
+    if not (m_b and m_k and m_h) or m_k.group(1).strip() != kernel or m_h.group(1) != spmv_source_hash():
+        return None
+    return int(m_b.group(1))
+
+
+def make_cloth(meshgen, workload):
+    if workload == "large":
+        return meshgen.config_large()
+    if workload == "medium":
+        return meshgen.config_medium()
+    return meshgen.config_batch()
+
+
+def new_context(binding, cloth):
+    ctx = binding.Context.from_cloth(cloth)
+    if len(cloth.sheet_ranges) > 1 and cloth.name.startswith("batch"):
+        # independent cloths: per-instance CG scalars, convergence and sweeps
+        ctx.set_instances([r[0] for r in cloth.sheet_ranges] + [cloth.nv])
+    return ctx
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--blocks", default="bf16", choices=["f32", "bf16", "f64"],
-                    help="block storage of the project configuration")
+    ap.add_argument("--blocks", default=None, choices=["f32", "bf16", "f64"],
+                    help="block storage of the project configuration (default: bf16; f32 for the batch)")
     ap.add_argument("--warm", default="learned", choices=["zero", "prev", "learned"],
                     help="CG start of the project configuration")
     ap.add_argument("--precond", default="block", choices=["jacobi", "block"],
                     help="preconditioner of the project configuration")
     ap.add_argument("--inner-rho", type=float, default=0.0,
                     help="residual reduction per refinement sweep (0: library default)")
-    ap.add_argument("--workload", default="large", choices=["large", "medium"])
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "batch"],
+                    help="large: 3 stacked sheets, 1.65M triangles (the headline); batch: 64 uneven "
+                         "independent sheets, ~1.5M triangles in one launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 / zero-start reference run")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 / Jacobi / zero-start run")
     ap.add_argument("--prof-every", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=30)
     ap.add_argument("--autotune", type=int, default=1)
@@ -153,6 +196,8 @@ def main():
         print(f"bench.py runs on one GPU only: the whole 1.65M-triangle workload fits in one MI355X "
               f"and nothing is sharded (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
+    if args.blocks is None:
+        args.blocks = "f32" if args.workload == "batch" else "bf16"
 
     import torch
 
@@ -163,12 +208,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t0 = time.perf_counter()
-    cloth = meshgen.config_large() if args.workload == "large" else meshgen.config_medium()
+    cloth = make_cloth(meshgen, args.workload)
     log(f"# workload {cloth.name}: nv={cloth.nv} nt={cloth.nt} ({time.perf_counter() - t0:.1f} s)")
     tol = cloth.tol
     rec_plain = None
     if not args.no_plain:
-        ctx = binding.Context.from_cloth(cloth)
+        ctx = new_context(binding, cloth)
         x = torch.from_numpy(cloth.x0.copy()).cuda()
         v = torch.from_numpy(cloth.v0.copy()).cuda()
         tune_plain = None
@@ -178,12 +223,12 @@ def main():
         el, infos, prof = time_steps(ctx, x, v, args.steps, args.warmup, "f32", tol, "zero", args.prof_every)
         rowptr, colidx = ctx.pattern()
         nnzb = int(colidx.numel())
-        sp = prof.get("spmv", {}).get("mean_ms", float("nan"))
+        sp = prof.get("spmv", {}).get("median_ms", float("nan"))
         rec_plain = {"steps_per_s": args.steps / el, "block_storage": "f32", "warm_start": "zero",
                      "preconditioner": "jacobi", "schedule": tune_plain,
                      "cg_iters_per_step": [i["iters"] for i in infos],
                      "rel_res_true_max": max(i["rel_res_true"] for i in infos),
-                     "spmv_mean_ms": sp, "spmv_GBs": spmv_bytes(ctx.nv, nnzb, "f32") / (sp * 1e-3) / 1e9}
+                     "spmv_median_ms": sp, "spmv_GBs": spmv_bytes(ctx.nv, nnzb, "f32") / (sp * 1e-3) / 1e9}
         log(f"# plain: {rec_plain['steps_per_s']:.3f} steps/s, iters {rec_plain['cg_iters_per_step']}")
         ctx.close()
         del x, v
@@ -191,7 +236,7 @@ def main():
     params = None
     if args.warm == "learned":
         params, train_info = train_warm_start(binding, meshgen, args.train_steps, 3, 1e-3, log)
-    ctx = binding.Context.from_cloth(cloth)
+    ctx = new_context(binding, cloth)
     if params is not None:
         ctx.ws_set_params(params)
     x = torch.from_numpy(cloth.x0.copy()).cuda()
@@ -209,6 +254,11 @@ def main():
     iters = [i["iters"] for i in infos]
     log(f"# timed: {args.steps} steps in {el:.3f} s, iters {iters}, sweeps {[i['sweeps'] for i in infos]}, "
         f"starts {[i['warm_used'] for i in infos]}, true residuals {[float('%.2e' % i['rel_res_true']) for i in infos]}")
+    per_instance = None
+    if getattr(ctx, "ninst", 1) > 1:
+        ii = [d["iters"] for d in ctx.instance_info()]
+        per_instance = {"instances": len(ii), "iters_min": min(ii), "iters_median": float(np.median(ii)),
+                        "iters_max": max(ii)}
     # paired comparison of the starts on one further system of the same
     # trajectory: one more step gives the previous increment, then the next
     # system is solved from each start to the same tolerance
@@ -226,10 +276,12 @@ def main():
                         "rel_res_true": pinfo["rel_res_true"]}
     log(f"# paired starts on one system: {paired}")
     spmv = prof.get("spmv", {})
-    spmv_ms = spmv.get("mean_ms", float("nan"))
-    ach = spmv_bytes(nv, nnzb, args.blocks) / (spmv_ms * 1e-3) / 1e9 if spmv_ms == spmv_ms else None
+    spmv_ms = spmv.get("median_ms", float("nan"))
+    kname = f"k_pcg_spmv<{KERNEL_TB[args.blocks]}>"
+    alg = spmv_bytes(nv, nnzb, args.blocks)
+    ach = alg / (spmv_ms * 1e-3) / 1e9 if spmv_ms == spmv_ms and spmv_ms > 0 else None
     asm = prof.get("assemble_all", {})
-    asm_ms = asm.get("mean_ms", float("nan"))
+    asm_ms = asm.get("median_ms", float("nan"))
     rec = {
         "metric": "implicit steps/s + CG iters to 1e-6 residual @1.65M tris, learned vs plain",
         "value": args.steps / el,
@@ -247,33 +299,32 @@ def main():
             "workload": f"{cloth.name}: {nt} triangles, {nv} vertices, {nh} hinges, nnzb {nnzb}",
             "h": cloth.h, "tol": tol, "block_storage": args.blocks, "warm_start": args.warm,
             "refinement_sweeps": [i["sweeps"] for i in infos], "starts_used": [i["warm_used"] for i in infos],
-            "preconditioner": args.precond, "inner_rho": args.inner_rho, "cg_iters_per_step": {"mean": float(np.mean(iters)),
-                                                               "min": int(min(iters)), "max": int(max(iters))},
+            "preconditioner": args.precond, "inner_rho": args.inner_rho,
+            "cg_iters_per_step": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
             "rel_res_true_max": max(i["rel_res_true"] for i in infos),
             "schedule": tune,
+            "per_instance": per_instance,
         },
         "plain": rec_plain,
         "paired_starts": paired,
         "speedup_vs_plain": (args.steps / el) / rec_plain["steps_per_s"] if rec_plain else None,
         "training": train_info,
         "roofline": {
-            "bound": "hbm", "kernel": f"k_pcg_spmv<{args.blocks}>",
+            "bound": "hbm", "kernel": kname,
             "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (ach / HBM_PEAK_GBS) if ach else None, "traffic": None,
-            "mean_launch_ms": spmv_ms, "samples": spmv.get("samples", 0),
-            "algorithmic_bytes_per_launch": spmv_bytes(nv, nnzb, args.blocks),
+            "frac": (ach / HBM_PEAK_GBS) if ach else None, "traffic": read_traffic(kname),
+            "median_launch_ms": spmv_ms, "samples": spmv.get("samples", 0),
+            "algorithmic_bytes_per_launch": alg,
         },
-        "kernels": {k: {"mean_ms": round(vv["mean_ms"], 5), "samples": vv["samples"]} for k, vv in prof.items()},
+        "kernels": {k: {"median_ms": round(vv["median_ms"], 5), "mean_ms": round(vv["mean_ms"], 5),
+                        "samples": vv["samples"]} for k, vv in prof.items()},
         "assembly": {
-            "mean_ms": asm_ms,
+            "median_ms": asm_ms,
             "compulsory_bytes": assembly_bytes(nv, nt, nh, nnzb, args.blocks),
             "compulsory_GBs": assembly_bytes(nv, nt, nh, nnzb, args.blocks) / (asm_ms * 1e-3) / 1e9
-            if asm_ms == asm_ms else None,
+            if asm_ms == asm_ms and asm_ms > 0 else None,
         },
     }
-    cg = prof.get("cg_update", {}).get("mean_ms", 0) + prof.get("cg_dir", {}).get("mean_ms", 0)
-    if cg:
-        rec["cg_vector_GBs"] = cg_vector_bytes(nv) / (cg * 1e-3) / 1e9
     ctx.close()
     if not args.no_cpu_baseline:
         log("# cpu baseline (oracle)...")

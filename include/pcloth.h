@@ -205,7 +205,8 @@ pc_status cloth_export_pattern(pc_ctx *ctx, int32_t *rowptr_out, int32_t *colidx
  * sampling off; any call resets the statistics).  pc_profile_read synchronises
  * the device and writes, for each kind k in 0..7 (0 SpMV in CG, 1 CG vector
  * update, 2 CG direction update, 3 row assembly, 4 row pattern, 5 whole
- * assembly), out[4k..4k+3] = {samples, mean ms, min ms, max ms} (host, 32). */
+ * assembly), out[5k..5k+4] = {samples, mean ms, min ms, max ms, median ms}
+ * (host, 40 doubles; the median is over the first 65536 samples). */
 pc_status pc_profile(pc_ctx *ctx, int32_t every);
 pc_status pc_profile_read(pc_ctx *ctx, double *out);
 

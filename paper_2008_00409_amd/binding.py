@@ -421,10 +421,11 @@ class Context:
         self._check(lib().pc_profile(self.h, int(every)))
 
     def profile_read(self):
-        out = (ctypes.c_double * 32)()
+        out = (ctypes.c_double * 40)()
         self._check(lib().pc_profile_read(self.h, out))
-        return {PROFILE_KINDS[k]: {"samples": int(out[4 * k]), "mean_ms": out[4 * k + 1], "min_ms": out[4 * k + 2],
-                                   "max_ms": out[4 * k + 3]} for k in range(8) if out[4 * k] > 0}
+        return {PROFILE_KINDS[k]: {"samples": int(out[5 * k]), "mean_ms": out[5 * k + 1], "min_ms": out[5 * k + 2],
+                                   "max_ms": out[5 * k + 3], "median_ms": out[5 * k + 4]}
+                for k in range(8) if out[5 * k] > 0}
 
     def check(self):
         self._check(lib().pc_check(self.h, _stream()))

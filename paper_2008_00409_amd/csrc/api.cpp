@@ -219,10 +219,11 @@ pc_status pc_profile_read(pc_ctx *h, double *out) {
     ctx->prof.harvest();
     for (int k = 0; k < PK_NKINDS; ++k) {
         const long long n = ctx->prof.count[k];
-        out[4 * k] = (double)n;
-        out[4 * k + 1] = n ? ctx->prof.sum_ms[k] / n : 0.0;
-        out[4 * k + 2] = ctx->prof.min_ms[k];
-        out[4 * k + 3] = ctx->prof.max_ms[k];
+        out[5 * k] = (double)n;
+        out[5 * k + 1] = n ? ctx->prof.sum_ms[k] / n : 0.0;
+        out[5 * k + 2] = ctx->prof.min_ms[k];
+        out[5 * k + 3] = ctx->prof.max_ms[k];
+        out[5 * k + 4] = ctx->prof.median(k);
     }
     return PC_OK;
 }

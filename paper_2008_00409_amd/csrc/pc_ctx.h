@@ -4,6 +4,7 @@
 
 #include <string>
 #include <utility>
+#include <algorithm>
 #include <vector>
 
 #include "pc_common.h"
@@ -37,6 +38,7 @@ struct Prof {
     std::vector<std::pair<int, int>> pending;  // (kind, slot)
     double sum_ms[PK_NKINDS] = {}, min_ms[PK_NKINDS] = {}, max_ms[PK_NKINDS] = {};
     long long count[PK_NKINDS] = {};
+    std::vector<float> kept[PK_NKINDS];   // up to 1 << 16 samples per kind, for the median
 
     void init(int nslots) {
         if (!pool.empty()) return;
@@ -55,6 +57,7 @@ struct Prof {
             sum_ms[k] = min_ms[k] = max_ms[k] = 0.0;
             count[k] = 0;
             tick[k] = 0;
+            kept[k].clear();
         }
     }
     // returns a slot (>= 0) when this launch is sampled; records the start event
@@ -81,10 +84,17 @@ struct Prof {
                 if (count[k] == 0 || ms > max_ms[k]) max_ms[k] = ms;
                 sum_ms[k] += ms;
                 count[k] += 1;
+                if (kept[k].size() < (1u << 16)) kept[k].push_back(ms);
             }
             free_slots.push_back(kp.second);
         }
         pending.clear();
+    }
+    double median(int k) const {
+        if (kept[k].empty()) return 0.0;
+        std::vector<float> v = kept[k];
+        std::nth_element(v.begin(), v.begin() + v.size() / 2, v.end());
+        return v[v.size() / 2];
     }
 };
 

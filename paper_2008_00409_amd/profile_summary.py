@@ -1,0 +1,129 @@
+"""Summaries of rocprofv3 result databases (SQLite, rocpd format) as short
+Markdown tables.
+
+    python -m paper_2008_00409_amd.profile_summary trace <results.db> [--top 15]
+        per-kernel calls, mean / min / max duration and share of GPU time
+
+    python -m paper_2008_00409_amd.profile_summary pmc <fetch.db> <write.db> --kernel NAME
+            --copy-kernel NAME --copy-bytes N
+        FETCH_SIZE and WRITE_SIZE per dispatch of one kernel (median over its
+        full dispatches), scaled by what the same counters read for a plain
+        copy kernel that moves N bytes each way; prints the scale factors and
+        the HBM bytes per launch
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import os
+import sqlite3
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# Sources the SpMV kernel is built from: a traffic figure stays valid only
+# while they are unchanged.
+SPMV_SOURCES = ["csrc/pcg.hip", "csrc/pc_common.h"]
+
+
+def spmv_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in SPMV_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_rows(db):
+    con = sqlite3.connect(db)
+    return con.execute("select name, start, end from kernels").fetchall()
+
+
+def trace_table(db, top=15):
+    rows = kernel_rows(db)
+    per = {}
+    for name, s, e in rows:
+        per.setdefault(name, []).append((e - s) / 1e3)
+    total = sum(sum(v) for v in per.values())
+    out = ["| kernel | calls | mean us | mean us, full launches | min us | max us | share |",
+           "|---|---|---|---|---|---|---|"]
+    for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        short = name.split("(")[0].replace("void ", "")
+        out.append(f"| `{short}` | {len(v)} | {statistics.mean(v):.2f} | {full_mean(v):.2f} | {min(v):.2f} | "
+                   f"{max(v):.2f} | {100 * sum(v) / total:.1f}% |")
+    return "\n".join(out)
+
+
+def counter_values(db, kernel_sub, counter):
+    con = sqlite3.connect(db)
+    q = "select kernel_name, dispatch_id, value from counters_collection where counter_name = ?"
+    vals = {}
+    for name, did, val in con.execute(q, (counter,)).fetchall():
+        if kernel_sub in name:
+            vals[did] = vals.get(did, 0.0) + val
+    return list(vals.values())
+
+
+def full_mean(vals):
+    """Mean over launches that did the full work: CG launches after an
+    instance has converged exit at once, so launches shorter than a quarter
+    of the 90th percentile are left out."""
+    p90 = sorted(vals)[int(0.9 * (len(vals) - 1))]
+    full = [v for v in vals if v >= 0.25 * p90]
+    return statistics.mean(full)
+
+
+def full_median(vals):
+    """Median over dispatches that did the full work (at least half of the
+    largest value: launches that exit early after convergence are left out)."""
+    if not vals:
+        return float("nan")
+    mx = max(vals)
+    return statistics.median([v for v in vals if v >= 0.5 * mx])
+
+
+def pmc_table(fetch_db, write_db, kernel, copy_kernel, copy_bytes):
+    f_k = full_median(counter_values(fetch_db, kernel, "FETCH_SIZE"))
+    w_k = full_median(counter_values(write_db, kernel, "WRITE_SIZE"))
+    f_c = full_median(counter_values(fetch_db, copy_kernel, "FETCH_SIZE"))
+    w_c = full_median(counter_values(write_db, copy_kernel, "WRITE_SIZE"))
+    kib = copy_bytes / 1024.0
+    sf, sw = kib / f_c, kib / w_c
+    fetch = f_k * sf * 1024.0
+    write = w_k * sw * 1024.0
+    lines = [
+        "| quantity | value |", "|---|---|",
+        f"| copy kernel FETCH_SIZE (KiB / dispatch) | {f_c:.0f} (true {kib:.0f}: scale {sf:.3f}) |",
+        f"| copy kernel WRITE_SIZE (KiB / dispatch) | {w_c:.0f} (true {kib:.0f}: scale {sw:.3f}) |",
+        f"| `{kernel}` FETCH_SIZE (KiB / dispatch, raw) | {f_k:.0f} |",
+        f"| `{kernel}` WRITE_SIZE (KiB / dispatch, raw) | {w_k:.0f} |",
+        f"| `{kernel}` HBM bytes fetched / launch (scaled) | {fetch:.0f} |",
+        f"| `{kernel}` HBM bytes written / launch (scaled) | {write:.0f} |",
+        "",
+        f"traffic_bytes_per_launch: {fetch + write:.0f}",
+        f"kernel: {kernel}",
+        f"spmv_source_hash: {spmv_source_hash()}",
+    ]
+    return "\n".join(lines)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--top", type=int, default=15)
+    p = sub.add_parser("pmc")
+    p.add_argument("fetch_db")
+    p.add_argument("write_db")
+    p.add_argument("--kernel", required=True)
+    p.add_argument("--copy-kernel", required=True)
+    p.add_argument("--copy-bytes", type=float, required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "trace":
+        print(trace_table(a.db, a.top))
+    else:
+        print(pmc_table(a.fetch_db, a.write_db, a.kernel, a.copy_kernel, a.copy_bytes))
+
+
+if __name__ == "__main__":
+    main()
