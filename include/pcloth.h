@@ -262,10 +262,14 @@ pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
  * PC_OPT_SPMV_SLICES_PER_BLOCK: 64-row slices per SpMV work item / block
  *   (1, 2, 4 or 8 (default)).
  * PC_OPT_VECTOR_ROWS_PER_BLOCK: rows per work item of the CG vector kernels
- *   (multiple of 64 in [64, 4096], default 512).  Every block of the vector
- *   kernels sums its instance's partials of the previous kernel, so fewer,
- *   larger work items cost less per iteration on large instances. */
-typedef enum { PC_OPT_GRAPH_CHUNK = 0, PC_OPT_SPMV_SLICES_PER_BLOCK = 1, PC_OPT_VECTOR_ROWS_PER_BLOCK = 2 } pc_option;
+ *   (multiple of 64 in [64, 4096], default 512).  Every block of the direction
+ *   kernel sums its instance's partials of the update kernel, so fewer,
+ *   larger work items cost less per iteration on large instances.
+ * PC_OPT_LDS_WINDOW: 1 (default): each SpMV work item whose block columns
+ *   span at most 4096 rows first copies that window of the search direction
+ *   to LDS and gathers from there; 0: all gathers from global memory. */
+typedef enum { PC_OPT_GRAPH_CHUNK = 0, PC_OPT_SPMV_SLICES_PER_BLOCK = 1, PC_OPT_VECTOR_ROWS_PER_BLOCK = 2,
+               PC_OPT_LDS_WINDOW = 3 } pc_option;
 pc_status pc_set_option(pc_ctx *ctx, int32_t option, int64_t value);
 pc_status pc_get_option(pc_ctx *ctx, int32_t option, int64_t *value);
 

@@ -898,6 +898,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
         ctx->jval_bytes = need;
     }
     ctx->dtype = dtype;
+    ctx->win_valid = false;
     ctx->last_x = x;
     ctx->last_v = v;
     if (dtype != PC_F64 && ctx->hi_blocks < ctx->vcap) {

@@ -196,6 +196,14 @@ struct Ctx {
     int gkey_chunk[2] = {0, 0};
     int gkey_sched[2] = {-1, -1};
     int gkey_pre[2] = {-1, -1};
+    int gkey_win[2] = {-1, -1};
+
+    // column windows of the SpMV work items (p staged in LDS)
+    int2 *sitem_win = nullptr;
+    int win_items = 0;            // items sitem_win can hold
+    bool win_valid = false;
+    bool use_win = true;          // PC_OPT_LDS_WINDOW
+    int win_cap = 0;              // LDS window rows of the SpMV launches (0: global gathers)
 };
 
 // Error helpers (host)

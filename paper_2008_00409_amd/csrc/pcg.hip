@@ -57,6 +57,16 @@ struct VecF4 {
         a = v.x; b = v.y; c = v.z;
     }
 };
+// p staged in LDS: the window [lo, lo + n) of rows that the work item's
+// columns span (see k_item_windows).
+struct VecLds {
+    const float4 *w;
+    int lo;
+    __device__ __forceinline__ void load(int i, double &a, double &b, double &c) const {
+        const float4 v = w[i - lo];
+        a = v.x; b = v.y; c = v.z;
+    }
+};
 struct VecD3 {
     const double *p;
     __device__ __forceinline__ void load(int i, double &a, double &b, double &c) const {
@@ -262,20 +272,67 @@ __global__ void k_state_init(int ninst, PcgState *st, const uint8_t *restart, do
     S.flags = 0;
 }
 
-// q = A p and per-item partials of p.q.
+// Column window of every SpMV work item: the smallest and largest block
+// column of its rows (block-CSR columns are ascending, so the first and last
+// of each row suffice).  One block per item.
+__global__ void __launch_bounds__(256) k_item_windows(Sched S, const int *slice_row0, const int *rowptr,
+                                                      const int *colidx, int2 *win) {
+    __shared__ int sh[2][4];
+    const int it = blockIdx.x;
+    if (it >= S.n_sitems) return;
+    const int4 I = S.sitem[it];
+    const int r0 = slice_row0[I.y], r1 = slice_row0[I.y + I.z];
+    int lo = 0x7fffffff, hi = -1;
+    for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
+        lo = min(lo, colidx[rowptr[i]]);
+        hi = max(hi, colidx[rowptr[i + 1] - 1]);
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        lo = min(lo, __shfl_xor(lo, m, WAVE));
+        hi = max(hi, __shfl_xor(hi, m, WAVE));
+    }
+    const int w = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+        sh[0][w] = lo;
+        sh[1][w] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)blockDim.x / WAVE; ++k) {
+            lo = min(lo, sh[0][k]);
+            hi = max(hi, sh[1][k]);
+        }
+        win[it] = make_int2(lo, hi);
+    }
+}
+
+// q = A p and per-item partials of p.q.  When the item's column window fits
+// in win_cap rows, p[window] is first copied to LDS with coalesced loads and
+// the rows gather from there; otherwise they gather from global memory.
 template <typename TB>
 __global__ void __launch_bounds__(512) k_pcg_spmv(SpmvArgs M, Sched S, const float4 *p, double *q,
-                                                  const PcgState *st, double *partials) {
+                                                  const PcgState *st, double *partials, const int2 *win,
+                                                  int win_cap) {
+    extern __shared__ float4 pwin[];
     const int it = item_of_block(S.n_sitems);
     if (it < 0) return;
     const int4 I = S.sitem[it];
     if (st[I.x].done) return;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int lane = lane_id();
+    int2 W = make_int2(0, -1);
+    if (win_cap > 0) W = win[it];
+    const int wn = W.y - W.x + 1;
+    const bool use_lds = win_cap > 0 && wn > 0 && wn <= win_cap;   // uniform per block
+    if (use_lds) {
+        for (int k = threadIdx.x; k < wn; k += blockDim.x) pwin[k] = p[W.x + k];
+        __syncthreads();
+    }
     double pq = 0.0;
     if (w < I.z) {
         double y[3], xi[3];
-        const int row = spmv_row<TB>(M, I.y + w, lane, VecF4{p}, y, xi);
+        const int row = use_lds ? spmv_row<TB>(M, I.y + w, lane, VecLds{pwin, W.x}, y, xi)
+                                : spmv_row<TB>(M, I.y + w, lane, VecF4{p}, y, xi);
         if (row >= 0) {
             q[3 * row] = y[0];
             q[3 * row + 1] = y[1];
@@ -679,6 +736,7 @@ pc_status build_schedule(Ctx *ctx) {
     ctx->n_vitems = (int)vitems.size();
     ctx->inst_info.assign(ninst, pc_solve_info{});
     ctx->sched_version += 1;
+    ctx->win_valid = false;
     ctx->assembled = false;  // the solver layout depends on the slices
     return PC_OK;
 }
@@ -696,14 +754,47 @@ static Grids grids(Ctx *ctx) {
     return g;
 }
 
+// Column windows of the SpMV items (after an assembly or a schedule change)
+// and the LDS window capacity: the largest window up to PC_WIN_MAX rows;
+// items with wider windows gather from global memory.  Synchronises.
+#ifndef PC_WIN_MAX
+#define PC_WIN_MAX 4096
+#endif
+static pc_status ensure_windows(Ctx *ctx, hipStream_t s) {
+    if (ctx->win_valid) return PC_OK;
+    if (ctx->win_items < ctx->n_sitems) {
+        if (ctx->sitem_win) (void)hipFree(ctx->sitem_win);
+        ctx->sitem_win = nullptr;
+        ctx->win_items = 0;
+        pc_status st = dev_alloc(ctx, (void **)&ctx->sitem_win, sizeof(int2) * (size_t)ctx->n_sitems);
+        if (st) return st;
+        ctx->win_items = ctx->n_sitems;
+    }
+    const Sched S = sched_args(ctx);
+    hipLaunchKernelGGL(k_item_windows, dim3(ctx->n_sitems), dim3(256), 0, s, S, ctx->slice_row0, ctx->rowptr,
+                       ctx->colidx, ctx->sitem_win);
+    PC_HIP(hipGetLastError());
+    std::vector<int2> w(ctx->n_sitems);
+    PC_HIP(hipMemcpyAsync(w.data(), ctx->sitem_win, sizeof(int2) * w.size(), hipMemcpyDeviceToHost, s));
+    PC_HIP(hipStreamSynchronize(s));
+    int cap = 0;
+    for (const int2 &v : w) {
+        const int n = v.y - v.x + 1;
+        if (n <= PC_WIN_MAX) cap = std::max(cap, n);
+    }
+    ctx->win_cap = ctx->use_win ? cap : 0;
+    ctx->win_valid = true;
+    return PC_OK;
+}
+
 // One CG iteration of parity par (the parity selects the rz slot, see
 // PcgState): SpMV with its partials, alpha, update, direction (beta from
 // the update partials, state advance).
 template <typename TB>
 static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s, int par) {
     int slot = ctx->prof.begin(PK_SPMV, s);
-    hipLaunchKernelGGL(k_pcg_spmv<TB>, dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, ctx->p, ctx->q, ctx->st,
-                       ctx->partials);
+    hipLaunchKernelGGL(k_pcg_spmv<TB>, dim3(g.sblocks), dim3(g.sthreads), sizeof(float4) * (size_t)ctx->win_cap, s, M,
+                       S, ctx->p, ctx->q, ctx->st, ctx->partials, ctx->sitem_win, ctx->win_cap);
     ctx->prof.end(slot, s);
     hipLaunchKernelGGL(k_fin_alpha, dim3(ctx->ninst), dim3(256), 0, s, S, par, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
@@ -754,7 +845,7 @@ static void launch_start_zero(Ctx *ctx, const Sched &S, const Grids &g, const ui
 static bool graph_stale(const Ctx *ctx, int variant, const SpmvArgs &M, int elem_size) {
     return !ctx->gexec[variant] || ctx->gkey[variant] != M.jval || ctx->gkey_dtype[variant] != elem_size ||
            ctx->gkey_chunk[variant] != ctx->graph_chunk || ctx->gkey_sched[variant] != ctx->sched_version ||
-           ctx->gkey_pre[variant] != ctx->precond;
+           ctx->gkey_pre[variant] != ctx->precond || ctx->gkey_win[variant] != ctx->win_cap;
 }
 
 // Capture `chunk` (even) iterations on the context's capture stream; the
@@ -792,6 +883,7 @@ static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Sched &S, cons
     ctx->gkey_chunk[variant] = chunk;
     ctx->gkey_sched[variant] = ctx->sched_version;
     ctx->gkey_pre[variant] = ctx->precond;
+    ctx->gkey_win[variant] = ctx->win_cap;
     return PC_OK;
 }
 
@@ -857,6 +949,8 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
     int warm = o ? o->warm : 0;
     const int check = (o && o->check_every > 0) ? o->check_every : 0;
     const bool lowp = ctx->dtype == PC_BF16;
+    pc_status wst = ensure_windows(ctx, s);
+    if (wst) return wst;
     const double rho = (o && o->inner_rho > 0.0) ? o->inner_rho : (lowp ? 1e-2 : 0.0);
     const int max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : (lowp ? 40 : 4);
     const int64_t n3 = 3 * (int64_t)nv;
@@ -1056,6 +1150,8 @@ static pc_status time_iters(Ctx *ctx, const double *b, int iters, float *ms, hip
     PC_HIP(hipMemcpyAsync(ctx->maxit_d, big.data(), sizeof(int) * ninst, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_state_init, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, ctx->st,
                        (const uint8_t *)nullptr, 0.0, 0.0, ctx->maxit_d);
+    pc_status wst = ensure_windows(ctx, s);
+    if (wst) return wst;
     ctx->cg_par = 0;
     launch_start_zero(ctx, S, g, nullptr, b, s);
     if (ctx->graph_chunk > 0 && graph_stale(ctx, 0, M, (int)sizeof(TB))) {
