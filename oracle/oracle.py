@@ -54,6 +54,7 @@ def lib():
         L.or_stretch_energy.restype = ctypes.c_double
         L.or_bend_energy.restype = ctypes.c_double
         L.or_hinge_angle.restype = ctypes.c_double
+        L.or_contact_energy.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -147,6 +148,44 @@ def bend_K(x12, ch, tbar, kb, exact=False):
     return K
 
 
+def contact_energy(x12, c, n, eta, kc):
+    x12, c, n = _f64(x12), _f64(c), _f64(n)
+    return lib().or_contact_energy(_p(x12, _f64p), _p(c, _f64p), _p(n, _f64p), ctypes.c_double(eta),
+                                   ctypes.c_double(kc))
+
+
+def contact_force(x12, c, n, eta, kc):
+    x12, c, n = _f64(x12), _f64(c), _f64(n)
+    f = np.zeros(12)
+    lib().or_contact_force(_p(x12, _f64p), _p(c, _f64p), _p(n, _f64p), ctypes.c_double(eta), ctypes.c_double(kc),
+                           _p(f, _f64p))
+    return f
+
+
+def contact_K(x12, c, n, eta, kc):
+    x12, c, n = _f64(x12), _f64(c), _f64(n)
+    K = np.zeros((12, 12))
+    lib().or_contact_K(_p(x12, _f64p), _p(c, _f64p), _p(n, _f64p), ctypes.c_double(eta), ctypes.c_double(kc),
+                       _p(K, _f64p))
+    return K
+
+
+@dataclass
+class Contacts:
+    """Proximity pairs of one step (the collision query's output): vertices
+    (nc, 4) int32, weights (nc, 4) summing to zero per pair, unit normals
+    (nc, 3), thickness eta and stiffness kc."""
+    verts: np.ndarray
+    weights: np.ndarray
+    normals: np.ndarray
+    eta: float
+    kc: float
+
+    @property
+    def n(self):
+        return int(self.verts.shape[0])
+
+
 # ------------------------------------------------------------------ topology
 def build_hinges(nv, tris):
     tris = _i32(tris)
@@ -169,13 +208,15 @@ def rest_hinges(X, hinges):
     return ch, tb
 
 
-def pattern(nv, tris, hinges):
+def pattern(nv, tris, hinges, cverts=None):
     tris, hinges = _i32(tris), _i32(hinges)
-    cap = 9 * tris.shape[0] + 16 * hinges.shape[0] + nv
+    cverts = _i32(np.zeros((0, 4)) if cverts is None else cverts)
+    nc = cverts.shape[0]
+    cap = 9 * tris.shape[0] + 16 * hinges.shape[0] + 16 * nc + nv
     rowptr = np.zeros(nv + 1, dtype=np.int32)
     colidx = np.zeros(cap, dtype=np.int32)
-    nnzb = lib().or_pattern(int(nv), tris.shape[0], _p(tris, _i32p), hinges.shape[0],
-                            _p(hinges, _i32p), _p(rowptr, _i32p), _p(colidx, _i32p), cap)
+    nnzb = lib().or_pattern2(int(nv), tris.shape[0], _p(tris, _i32p), hinges.shape[0],
+                             _p(hinges, _i32p), nc, _p(cverts, _i32p), _p(rowptr, _i32p), _p(colidx, _i32p), cap)
     if nnzb < 0:
         raise RuntimeError("pattern capacity")
     return rowptr, colidx[:nnzb].copy()
@@ -228,7 +269,18 @@ class Problem:
         self.B, self.A0 = rest_triangles(self.rest, self.tris)
         self.hinges = build_hinges(self.nv, self.tris)
         self.ch, self.tbar = rest_hinges(self.rest, self.hinges)
+        self.contacts = None
         self.rowptr, self.colidx = pattern(self.nv, self.tris, self.hinges)
+
+    def set_contacts(self, contacts: "Contacts | None"):
+        """Proximity pairs for the following assemblies; the pattern gains
+        every pair of their vertices (None removes them)."""
+        if contacts is not None:
+            contacts = Contacts(_i32(contacts.verts).reshape(-1, 4), _f64(contacts.weights).reshape(-1, 4),
+                                _f64(contacts.normals).reshape(-1, 3), float(contacts.eta), float(contacts.kc))
+        self.contacts = contacts
+        cv = contacts.verts if contacts is not None else None
+        self.rowptr, self.colidx = pattern(self.nv, self.tris, self.hinges, cv)
 
     @classmethod
     def from_cloth(cls, c, mat: Material | None = None):
@@ -259,9 +311,16 @@ class Problem:
         diag = np.zeros((self.nv, 3))
         D = np.zeros((self.nv, 3, 3))
         P = self.params()
-        st = lib().or_assemble(self.nv, self.nt, _p(self.tris, _i32p), _p(self.B, _f64p),
+        C = self.contacts
+        nc = C.n if C is not None else 0
+        cv = C.verts if nc else np.zeros((1, 4), np.int32)
+        cw = C.weights if nc else np.zeros((1, 4))
+        cn = C.normals if nc else np.zeros((1, 3))
+        st = lib().or_assemble2(self.nv, self.nt, _p(self.tris, _i32p), _p(self.B, _f64p),
                                _p(self.A0, _f64p), self.H, _p(self.hinges, _i32p),
-                               _p(self.ch, _f64p), _p(self.tbar, _f64p), _p(self.mass, _f64p),
+                               _p(self.ch, _f64p), _p(self.tbar, _f64p), nc, _p(cv, _i32p), _p(cw, _f64p),
+                               _p(cn, _f64p), ctypes.c_double(C.eta if nc else 0.0),
+                               ctypes.c_double(C.kc if nc else 0.0), _p(self.mass, _f64p),
                                _p(self.pinned, _u8p), ctypes.byref(P), _p(x, _f64p), _p(v, _f64p),
                                _p(self.rowptr, _i32p), _p(self.colidx, _i32p), _p(vals, _f64p),
                                _p(b, _f64p), _p(diag, _f64p), _p(D, _f64p))

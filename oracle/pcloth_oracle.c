@@ -310,6 +310,46 @@ void or_bend_K(const double *x12, double ch, double tbar, double kb, int exact, 
         for (int j = 0; j < 12; ++j) K[i * 12 + j] += c * th * 0.5 * (Hs[i * 12 + j] + Hs[j * 12 + i]);
 }
 
+/* ------------------------------------------------------------------ contact */
+/* Proximity (repulsion) element between 4 vertices: a vertex-face pair
+ * (p; a, b, c) with c = (1, -w_a, -w_b, -w_c) from the closest point's
+ * barycentric weights, or an edge-edge pair (a, b; c, d) with
+ * c = (1 - s, s, -(1 - t), -t) from the closest points' parameters.  The
+ * weights (which sum to zero) and the unit normal n come with the pair from
+ * the proximity query and are constants of the step.  Gap g = n . sum_k c_k x_k;
+ * energy kc/2 (eta - g)^2 while g < eta (eta: thickness), zero otherwise. */
+static double contact_gap(const double *x12, const double *c, const double *n) {
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 4; ++k)
+        for (int a = 0; a < 3; ++a) s[a] += c[k] * x12[3 * k + a];
+    return dot3(n, s);
+}
+
+double or_contact_energy(const double *x12, const double *c, const double *n, double eta, double kc) {
+    double g = contact_gap(x12, c, n);
+    return g < eta ? 0.5 * kc * (eta - g) * (eta - g) : 0.0;
+}
+
+/* f_k = -dE/dx_k = kc (eta - g) c_k n while g < eta. */
+void or_contact_force(const double *x12, const double *c, const double *n, double eta, double kc, double *f12) {
+    double g = contact_gap(x12, c, n);
+    double m = g < eta ? kc * (eta - g) : 0.0;
+    for (int k = 0; k < 4; ++k)
+        for (int a = 0; a < 3; ++a) f12[3 * k + a] = m * c[k] * n[a];
+}
+
+/* K = d2E/dx2 (12 x 12, row major): blocks kc c_k c_l n n^T while g < eta
+ * (g is linear in x, so this is the exact Hessian and it is PSD). */
+void or_contact_K(const double *x12, const double *c, const double *n, double eta, double kc, double *K) {
+    double g = contact_gap(x12, c, n);
+    for (int i = 0; i < 144; ++i) K[i] = 0.0;
+    if (!(g < eta)) return;
+    for (int k = 0; k < 4; ++k)
+        for (int l = 0; l < 4; ++l)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) K[(3 * k + a) * 12 + 3 * l + b] = kc * c[k] * c[l] * n[a] * n[b];
+}
+
 /* ------------------------------------------------------------------ topology */
 typedef struct { int64_t key; int32_t tri; int32_t corner; } dir_edge;
 
@@ -386,13 +426,14 @@ static int cmp_i64(const void *pa, const void *pb) {
     return a < b ? -1 : (a > b ? 1 : 0);
 }
 
-/* Block pattern: every (row, col) pair of vertices that share an element (the
- * diagonal included), sorted and de-duplicated.  Returns nnzb (or -1 if cap is
+/* Block pattern: every (row, col) pair of vertices that share an element
+ * (triangle, hinge or contact; the diagonal included), sorted and
+ * de-duplicated.  Returns nnzb (or -1 if cap is
  * too small); rowptr has nv+1 entries. */
-int or_pattern(int nv, int nt, const int32_t *tris, int H, const int32_t *hinges,
-               int32_t *rowptr, int32_t *colidx, int cap) {
-    size_t nkeys = (size_t)9 * nt + (size_t)16 * H;
-    int64_t *keys = (int64_t *)malloc(sizeof(int64_t) * nkeys);
+int or_pattern2(int nv, int nt, const int32_t *tris, int H, const int32_t *hinges, int nc, const int32_t *cverts,
+                int32_t *rowptr, int32_t *colidx, int cap) {
+    size_t nkeys = (size_t)9 * nt + (size_t)16 * H + (size_t)16 * nc;
+    int64_t *keys = (int64_t *)malloc(sizeof(int64_t) * (nkeys ? nkeys : 1));
     size_t m = 0;
     for (int t = 0; t < nt; ++t)
         for (int k = 0; k < 3; ++k)
@@ -400,6 +441,9 @@ int or_pattern(int nv, int nt, const int32_t *tris, int H, const int32_t *hinges
     for (int h = 0; h < H; ++h)
         for (int k = 0; k < 4; ++k)
             for (int l = 0; l < 4; ++l) keys[m++] = (int64_t)hinges[4 * h + k] * nv + hinges[4 * h + l];
+    for (int e = 0; e < nc; ++e)
+        for (int k = 0; k < 4; ++k)
+            for (int l = 0; l < 4; ++l) keys[m++] = (int64_t)cverts[4 * e + k] * nv + cverts[4 * e + l];
     qsort(keys, nkeys, sizeof(int64_t), cmp_i64);
     int nnzb = 0;
     for (int r = 0; r <= nv; ++r) rowptr[r] = 0;
@@ -415,6 +459,11 @@ int or_pattern(int nv, int nt, const int32_t *tris, int H, const int32_t *hinges
     return nnzb;
 }
 
+int or_pattern(int nv, int nt, const int32_t *tris, int H, const int32_t *hinges,
+               int32_t *rowptr, int32_t *colidx, int cap) {
+    return or_pattern2(nv, nt, tris, H, hinges, 0, NULL, rowptr, colidx, cap);
+}
+
 static int find_block(const int32_t *rowptr, const int32_t *colidx, int row, int col) {
     int lo = rowptr[row], hi = rowptr[row + 1] - 1;
     while (lo <= hi) {
@@ -426,10 +475,18 @@ static int find_block(const int32_t *rowptr, const int32_t *colidx, int row, int
 }
 
 /* ------------------------------------------------------------------ assembly */
+typedef struct {
+    int nc;
+    const int32_t *verts;    /* nc x 4 */
+    const double *w;         /* nc x 4 weights c_k (sum zero) */
+    const double *n;         /* nc x 3 unit normals */
+    double eta, kc;          /* thickness, stiffness */
+} or_contacts;
 /* Internal + gravity force at positions y (nv x 3). */
 static void total_force(int nv, int nt, const int32_t *tris, const double *Bt, const double *A0,
                         int H, const int32_t *hinges, const double *ch, const double *tbar,
-                        const double *mass, const or_params *P, const double *y, double *f) {
+                        const or_contacts *C, const double *mass, const or_params *P, const double *y,
+                        double *f) {
     for (int i = 0; i < nv; ++i)
         for (int a = 0; a < 3; ++a) f[3 * i + a] = mass[i] * P->g[a];
     double *ft = (double *)malloc(sizeof(double) * 9 * (size_t)nt);
@@ -452,6 +509,13 @@ static void total_force(int nv, int nt, const int32_t *tris, const double *Bt, c
     for (int h = 0; h < H; ++h)
         for (int k = 0; k < 4; ++k)
             for (int a = 0; a < 3; ++a) f[3 * hinges[4 * h + k] + a] += fh[12 * h + 3 * k + a];
+    for (int e = 0; e < C->nc; ++e) {
+        double x12[12], fc[12];
+        for (int k = 0; k < 4; ++k) memcpy(x12 + 3 * k, y + 3 * C->verts[4 * e + k], 3 * sizeof(double));
+        or_contact_force(x12, C->w + 4 * e, C->n + 3 * e, C->eta, C->kc, fc);
+        for (int k = 0; k < 4; ++k)
+            for (int a = 0; a < 3; ++a) f[3 * C->verts[4 * e + k] + a] += fc[3 * k + a];
+    }
     free(ft);
     free(fh);
 }
@@ -461,7 +525,7 @@ static void total_force(int nv, int nt, const int32_t *tris, const double *Bt, c
  * hinges).  Returns -1 if a block is missing from the pattern. */
 static int stiffness(int nv, int nt, const int32_t *tris, const double *Bt, const double *A0,
                      int H, const int32_t *hinges, const double *ch, const double *tbar,
-                     const or_params *P, const double *x, const int32_t *rowptr,
+                     const or_contacts *C, const or_params *P, const double *x, const int32_t *rowptr,
                      const int32_t *colidx, double *vals) {
     int nnzb = rowptr[nv];
     memset(vals, 0, sizeof(double) * 9 * (size_t)nnzb);
@@ -496,6 +560,18 @@ static int stiffness(int nv, int nt, const int32_t *tris, const double *Bt, cons
                 for (int a = 0; a < 3; ++a)
                     for (int b = 0; b < 3; ++b) vals[9 * s + 3 * a + b] += Kh[144 * h + (3 * k + a) * 12 + 3 * l + b];
             }
+    for (int e = 0; e < C->nc && !status; ++e) {
+        double x12[12], Kc[144];
+        for (int k = 0; k < 4; ++k) memcpy(x12 + 3 * k, x + 3 * C->verts[4 * e + k], 3 * sizeof(double));
+        or_contact_K(x12, C->w + 4 * e, C->n + 3 * e, C->eta, C->kc, Kc);
+        for (int k = 0; k < 4 && !status; ++k)
+            for (int l = 0; l < 4; ++l) {
+                int s = find_block(rowptr, colidx, C->verts[4 * e + k], C->verts[4 * e + l]);
+                if (s < 0) { status = -1; break; }
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) vals[9 * s + 3 * a + b] += Kc[(3 * k + a) * 12 + 3 * l + b];
+            }
+    }
     free(Kt);
     free(Kh);
     return status;
@@ -520,13 +596,16 @@ static void block_spmv(int nv, const int32_t *rowptr, const int32_t *colidx, con
  * diagonal diag(A) (nv x 3) and the pinned-neighbour remainder
  * D_i = -h(h+beta) sum_{j pinned, j != i} K_ij for unpinned i, 0 for pinned i
  * (nv x 9), from state (x, v).  Returns 0, or -1 on a pattern mismatch. */
-int or_assemble(int nv, int nt, const int32_t *tris, const double *Bt, const double *A0,
-                int H, const int32_t *hinges, const double *ch, const double *tbar,
-                const double *mass, const uint8_t *pinned, const or_params *P,
-                const double *x, const double *v, const int32_t *rowptr, const int32_t *colidx,
-                double *vals, double *b, double *diag, double *D) {
+int or_assemble2(int nv, int nt, const int32_t *tris, const double *Bt, const double *A0,
+                 int H, const int32_t *hinges, const double *ch, const double *tbar,
+                 int nc, const int32_t *cverts, const double *cw, const double *cn, double eta, double kc,
+                 const double *mass, const uint8_t *pinned, const or_params *P,
+                 const double *x, const double *v, const int32_t *rowptr, const int32_t *colidx,
+                 double *vals, double *b, double *diag, double *D) {
     int nnzb = rowptr[nv];
-    if (stiffness(nv, nt, tris, Bt, A0, H, hinges, ch, tbar, P, x, rowptr, colidx, vals)) return -1;
+    or_contacts C0 = {nc, cverts, cw, cn, eta, kc};
+    const or_contacts *C = &C0;
+    if (stiffness(nv, nt, tris, Bt, A0, H, hinges, ch, tbar, C, P, x, rowptr, colidx, vals)) return -1;
     /* right-hand side */
     double s = P->rhs_mode == 0 ? 1.0 : 0.0;
     double bk = P->rhs_mode == 0 ? P->beta : P->h + P->beta;
@@ -534,7 +613,7 @@ int or_assemble(int nv, int nt, const int32_t *tris, const double *Bt, const dou
     double *f = (double *)malloc(sizeof(double) * 3 * (size_t)nv);
     double *Kv = (double *)malloc(sizeof(double) * 3 * (size_t)nv);
     for (int i = 0; i < 3 * nv; ++i) y[i] = x[i] + s * P->h * v[i];
-    total_force(nv, nt, tris, Bt, A0, H, hinges, ch, tbar, mass, P, y, f);
+    total_force(nv, nt, tris, Bt, A0, H, hinges, ch, tbar, C, mass, P, y, f);
     block_spmv(nv, rowptr, colidx, vals, v, Kv);
     for (int i = 0; i < nv; ++i)
         for (int a = 0; a < 3; ++a)
@@ -573,6 +652,15 @@ int or_assemble(int nv, int nt, const int32_t *tris, const double *Bt, const dou
     free(f);
     free(Kv);
     return 0;
+}
+
+int or_assemble(int nv, int nt, const int32_t *tris, const double *Bt, const double *A0,
+                int H, const int32_t *hinges, const double *ch, const double *tbar,
+                const double *mass, const uint8_t *pinned, const or_params *P,
+                const double *x, const double *v, const int32_t *rowptr, const int32_t *colidx,
+                double *vals, double *b, double *diag, double *D) {
+    return or_assemble2(nv, nt, tris, Bt, A0, H, hinges, ch, tbar, 0, NULL, NULL, NULL, 0.0, 0.0, mass, pinned, P,
+                        x, v, rowptr, colidx, vals, b, diag, D);
 }
 
 /* y = A x on an assembled block-CSR matrix. */

@@ -248,8 +248,8 @@ pc_status pc_set_option(pc_ctx *h, int32_t option, int64_t value) {
             ctx->win_valid = false;
             return PC_OK;
         case PC_OPT_SPMV_SLICES_PER_BLOCK: {
-            if (value != 1 && value != 2 && value != 4 && value != 8) {
-                ctx->err = "slices per block must be 1, 2, 4 or 8";
+            if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16) {
+                ctx->err = "slices per block must be 1, 2, 4, 8 or 16";
                 return PC_ERR_ARG;
             }
             const bool was = ctx->assembled;

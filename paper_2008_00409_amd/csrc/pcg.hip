@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(256) k_item_windows(Sched S, const int *slice_
 // in win_cap rows, p[window] is first copied to LDS with coalesced loads and
 // the rows gather from there; otherwise they gather from global memory.
 template <typename TB>
-__global__ void __launch_bounds__(512) k_pcg_spmv(SpmvArgs M, Sched S, const float4 *p, double *q,
+__global__ void __launch_bounds__(1024) k_pcg_spmv(SpmvArgs M, Sched S, const float4 *p, double *q,
                                                   const PcgState *st, double *partials, const int2 *win,
                                                   int win_cap) {
     extern __shared__ float4 pwin[];
@@ -493,7 +493,7 @@ __global__ void __launch_bounds__(256) k_pcg_start_zero(Sched S, const uint8_t *
 // ||r||^2, ||b||^2.  MODE 1 (check, all instances): partials of ||t||^2,
 // ||b||^2.
 template <typename TB, int MODE>
-__global__ void __launch_bounds__(512) k_residual(SpmvArgs M, Sched S, const uint8_t *restart, const double *b,
+__global__ void __launch_bounds__(1024) k_residual(SpmvArgs M, Sched S, const uint8_t *restart, const double *b,
                                                   const double *x, double *r, float4 *p, PreArgs P,
                                                   double *partials) {
     const int it = item_of_block(S.n_sitems);
@@ -570,7 +570,7 @@ __global__ void __launch_bounds__(256) k_fin_check(Sched S, const double *partia
 
 // y = A x (FP64 in and out).
 template <typename TB>
-__global__ void __launch_bounds__(512) k_spmv_apply(SpmvArgs M, Sched S, const double *x, double *yout) {
+__global__ void __launch_bounds__(1024) k_spmv_apply(SpmvArgs M, Sched S, const double *x, double *yout) {
     const int it = item_of_block(S.n_sitems);
     if (it < 0) return;
     const int4 I = S.sitem[it];
@@ -1185,7 +1185,7 @@ pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, fl
         ctx->err = "pc_autotune: nothing assembled";
         return PC_ERR_ARG;
     }
-    const int spbs[4] = {1, 2, 4, 8};
+    const int spbs[4] = {2, 4, 8, 16};
     const int rpbs[3] = {512, 1024, 2048};
     const int chunks[2] = {0, 32};
     float best = 1e30f;

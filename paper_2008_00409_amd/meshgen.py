@@ -324,6 +324,98 @@ def config_batch(count: int = 64, seed: int = 5000, sizes=None) -> Cloth:
     return stack_sheets(parts, f"batch-{len(sides)}", 0.01, 1e-6, 100)
 
 
+@dataclasses.dataclass
+class ContactSet:
+    """Proximity pairs handed to the solver for one step: vertices (nc, 4),
+    weights (nc, 4) summing to zero per pair, unit normals (nc, 3), thickness
+    eta (m) and stiffness kc (N/m)."""
+    verts: np.ndarray
+    weights: np.ndarray
+    normals: np.ndarray
+    eta: float
+    kc: float
+
+    @property
+    def n(self) -> int:
+        return int(self.verts.shape[0])
+
+
+def vf_contacts(x: np.ndarray, tris: np.ndarray, verts, tri_ids, radius: float, eta: float, kc: float,
+                candidates: int = 6) -> ContactSet:
+    """Vertex-face proximity pairs, as a collision query would report them:
+    each vertex of `verts` is paired with the first of its `candidates`
+    nearest triangles of `tri_ids` (by centroid) onto whose plane it projects
+    inside the triangle within `radius`.  Weights (1, -w_a, -w_b, -w_c) are the
+    projection's barycentric coordinates, the normal is the triangle's unit
+    normal turned towards the vertex."""
+    from scipy.spatial import cKDTree
+    verts = np.asarray(verts, dtype=np.int64)
+    tri_ids = np.asarray(tri_ids, dtype=np.int64)
+    T = tris[tri_ids]
+    a, b, c = x[T[:, 0]], x[T[:, 1]], x[T[:, 2]]
+    cen = (a + b + c) / 3.0
+    tree = cKDTree(cen)
+    _, cand = tree.query(x[verts], k=min(candidates, len(tri_ids)))
+    cand = np.atleast_2d(cand)
+    P = x[verts][:, None, :]                                  # (n, 1, 3)
+    A, B, C = a[cand], b[cand], c[cand]                       # (n, k, 3)
+    nrm = np.cross(B - A, C - A)
+    ln = np.linalg.norm(nrm, axis=2, keepdims=True)
+    ok = ln[..., 0] > 0.0
+    nrm = nrm / np.where(ln > 0.0, ln, 1.0)
+    d = np.einsum("nka,nka->nk", P - A, nrm)
+    sgn = np.where(d < 0.0, -1.0, 1.0)
+    nrm = nrm * sgn[..., None]
+    d = d * sgn
+    q = P - d[..., None] * nrm
+    v0, v1, v2 = B - A, C - A, q - A
+    d00 = np.einsum("nka,nka->nk", v0, v0)
+    d01 = np.einsum("nka,nka->nk", v0, v1)
+    d11 = np.einsum("nka,nka->nk", v1, v1)
+    d20 = np.einsum("nka,nka->nk", v2, v0)
+    d21 = np.einsum("nka,nka->nk", v2, v1)
+    den = d00 * d11 - d01 * d01
+    ok &= den > 0.0
+    den = np.where(ok, den, 1.0)
+    wb = (d11 * d20 - d01 * d21) / den
+    wc = (d00 * d21 - d01 * d20) / den
+    wa = 1.0 - wb - wc
+    ok &= (d < radius) & (wa >= 0.0) & (wb >= 0.0) & (wc >= 0.0)
+    has = ok.any(axis=1)
+    first = np.argmax(ok, axis=1)                               # first valid candidate
+    rows = np.nonzero(has)[0]
+    k = first[rows]
+    t = T[cand[rows, k]]
+    cverts = np.column_stack([verts[rows], t]).astype(np.int32)
+    weights = np.column_stack([np.ones(rows.size), -wa[rows, k], -wb[rows, k], -wc[rows, k]])
+    return ContactSet(cverts, weights, nrm[rows, k], eta, kc)
+
+
+def config_contact(nx: int = 501, ny: int = 551, gap: float = 0.0015, seed_base: int = 6000) -> tuple:
+    """Two irregular sheets (2 mm edges, 10% flips, same bumps) with the upper
+    one `gap` above the lower, top rows pinned, h = 0.01 s; returns the cloth
+    and the vertex-face pairs of every upper vertex within the thickness
+    eta = 2 mm of the lower sheet (kc = 1000 N/m)."""
+    lower = irregular_sheet(nx, ny, 0.002, 0.0, seed_base, 0.10, strict=True)
+    upper = irregular_sheet(nx, ny, 0.002, gap, seed_base + 1, 0.10, strict=True)
+    # the same bumps on both sheets, so the gap is uniform
+    bump = lower[3][:, 2] - lower[0][:, 2]
+    rest_u, tris_u, pin_u, _ = upper
+    x_u = rest_u.copy()
+    x_u[:, 2] += _bump_at(lower[0], bump, rest_u)
+    c = stack_sheets([lower, (rest_u, tris_u, pin_u, x_u)], f"contact-2x{nx}x{ny}", 0.01, 1e-6, 100)
+    nl = lower[0].shape[0]
+    cs = vf_contacts(c.x0, c.tris, np.arange(nl, c.nv), np.arange(0, lower[1].shape[0]), 0.002, 0.002, 1000.0)
+    return c, cs
+
+
+def _bump_at(rest_lower: np.ndarray, bump_lower: np.ndarray, points: np.ndarray) -> np.ndarray:
+    """The lower sheet's bump height at the nearest lower rest vertex of each point."""
+    from scipy.spatial import cKDTree
+    _, idx = cKDTree(rest_lower[:, :2]).query(points[:, :2])
+    return bump_lower[idx]
+
+
 def mesh_counts(tris: np.ndarray, nv: int):
     """(interior edges, distinct off-diagonal block pairs) from topology alone:
     used to check the generators against the expected sizes."""
