@@ -187,6 +187,26 @@ pc_status cloth_spmv(pc_ctx *ctx, const double *x, double *y, int32_t solver_blo
 pc_status cloth_export_blocks(pc_ctx *ctx, double *vals_out, double *D_out, int32_t solver_blocks,
                               void *stream);
 
+/* Proximity (contact) forces inside the implicit solve (paper Sec. 3.2:
+ * the assembly elements include contact forces; Sec. 4: proximity forces
+ * are integrated in the implicit step).  Each of the ncontacts pairs that a
+ * proximity query reported is a repulsion element on 4 vertices: verts
+ * (device nc x 4 int32), weights c (device nc x 4 doubles, summing to zero:
+ * (1, -w_a, -w_b, -w_c) for a vertex-face pair with the closest point's
+ * barycentric weights, (1 - s, s, -(1 - t), -t) for an edge-edge pair) and a
+ * unit normal n (device nc x 3 doubles).  With the gap g = n . sum_k c_k x_k
+ * the element's energy is stiffness/2 (thickness - g)^2 while g < thickness:
+ * forces stiffness (thickness - g) c_k n and stiffness blocks
+ * stiffness c_k c_l n n^T (the exact Hessian, PSD).  The arrays are copied;
+ * the set applies to every following assembly until replaced, and
+ * ncontacts = 0 removes it.  The block pattern changes with the set.
+ * Synchronises the stream; PC_ERR_ARG for an index out of range, repeated
+ * vertices in a pair, weights not summing to zero, a normal that is not
+ * unit length, or a pair joining two instances (pc_set_instances); the set
+ * is then empty. */
+pc_status cloth_set_contacts(pc_ctx *ctx, int32_t ncontacts, const int32_t *verts, const double *weights,
+                             const double *normals, double thickness, double stiffness, void *stream);
+
 /* Preconditioners of the last assembly: inv_diag_out (device nv*3 floats)
  * receives 1 / diag(A); inv_blocks_out (device nv*6 floats) the inverses of
  * the 3x3 diagonal blocks A_ii as (xx, xy, xz, yy, yz, zz).  Either may be

@@ -28,7 +28,7 @@ ABI_SYMBOLS = ["pc_create", "pc_destroy", "pc_set_params", "pc_last_error", "pc_
                "cloth_export_pattern", "pc_check", "pc_profile", "pc_profile_read", "pc_set_option",
                "pc_ws_set_params", "pc_ws_get_params", "pc_ws_features", "pc_ws_predict", "pc_ws_gradient",
                "pc_ws_train_step", "pc_mfma_probe", "pc_get_option", "pc_set_instances", "pc_get_instance_info",
-               "pc_autotune", "cloth_export_precond", "pc_ws_start"]
+               "pc_autotune", "cloth_export_precond", "pc_ws_start", "cloth_set_contacts"]
 WS_PARAMS = 10307
 # Warm-start network layer shapes (inputs x outputs); the flat parameter
 # vector holds, per layer, W row-major then the bias.
@@ -106,6 +106,7 @@ def lib():
         L.cloth_spmv.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
         L.cloth_export_blocks.argtypes = [vp, vp, vp, ctypes.c_int32, vp]
         L.cloth_export_precond.argtypes = [vp, vp, vp, vp]
+        L.cloth_set_contacts.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp]
         L.pc_check.argtypes = [vp, vp]
         L.cloth_export_pattern.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
         L.pc_profile.argtypes = [vp, ctypes.c_int32]
@@ -268,6 +269,23 @@ class Context:
         self._check(lib().cloth_spmv(self.h, _dev3(x, self.nv, "x"), _dev3(y, self.nv, "y"), int(solver_blocks),
                                      _stream()))
         return y
+
+    def cloth_set_contacts(self, verts=None, weights=None, normals=None, thickness=0.0, stiffness=0.0):
+        """Proximity pairs for the following assemblies (None: remove them).
+        Arrays may be numpy or torch; they are copied to the device first."""
+        import torch
+        if verts is None or len(verts) == 0:
+            self._check(lib().cloth_set_contacts(self.h, 0, None, None, None, 0.0, 0.0, _stream()))
+            return
+        v = torch.as_tensor(np.ascontiguousarray(verts, dtype=np.int32) if isinstance(verts, np.ndarray) else verts,
+                            dtype=torch.int32, device="cuda").contiguous()
+        w = torch.as_tensor(weights, dtype=torch.float64, device="cuda").contiguous()
+        n = torch.as_tensor(normals, dtype=torch.float64, device="cuda").contiguous()
+        nc = v.shape[0]
+        if v.shape != (nc, 4) or w.shape != (nc, 4) or n.shape != (nc, 3):
+            raise ValueError("contacts: verts (nc, 4), weights (nc, 4), normals (nc, 3)")
+        self._check(lib().cloth_set_contacts(self.h, int(nc), _ptr(v), _ptr(w), _ptr(n), float(thickness),
+                                             float(stiffness), _stream()))
 
     def cloth_export_precond(self):
         """(1 / diag(A) as (nv, 3), inverse diagonal blocks as (nv, 3, 3)), float32 on the device."""

@@ -2,6 +2,7 @@
 // the assembly / solve / update launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -65,7 +66,7 @@ static void free_all(Ctx *c) {
     void *ptrs[] = {c->tri, c->Bm, c->A0, c->hinge, c->hcoef, c->htbar, c->mass, c->pinned, c->status,
                     c->inc_cnt, c->inc_ptr, c->inc, c->rowlen, c->rowptr, c->colidx, c->jcol, c->lane_row,
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
-                    c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win,
+                    c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn,
                     c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -158,10 +159,16 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
     }
     if ((st = topo_build(ctx, mesh, s))) return fail(st);
     const int nh = ctx->nh;
+    if (nt >= MAX_ELEMS || nh >= MAX_ELEMS) {
+        ctx->err = "more than 2^28 triangles or hinges";
+        return fail(PC_ERR_ARG);
+    }
     ctx->ninc = 3 * (int64_t)nt + 4 * (int64_t)nh;
+    ctx->ninc_cap = ctx->ninc;
     // block capacity: diagonal + both directions of every triangle edge (6
     // per triangle, duplicates included) + both wing pairs of every hinge
     ctx->cap = (int64_t)nv + 6 * (int64_t)nt + 2 * (int64_t)nh;
+    ctx->cap_base = ctx->cap;
     if (ctx->cap >= (int64_t)1 << 31) {
         ctx->err = "block capacity exceeds int32 indexing";
         return fail(PC_ERR_ARG);
@@ -297,6 +304,22 @@ pc_status pc_autotune(pc_ctx *h, const double *b, int32_t iters, int32_t precond
     return st;
 }
 
+// True when some contact pair has vertices in two instances (bounds: ninst + 1
+// first rows).  Reads the context's contact vertices back to the host.
+static pc_status contacts_cross(Ctx *ctx, const int32_t *bounds, int ninst, bool *cross) {
+    *cross = false;
+    if (ctx->nc == 0 || ninst <= 1) return PC_OK;
+    std::vector<int> cv((size_t)4 * ctx->nc);
+    PC_HIP(hipMemcpy(cv.data(), ctx->cverts, sizeof(int) * cv.size(), hipMemcpyDeviceToHost));
+    auto inst = [&](int v) { return (int)(std::upper_bound(bounds, bounds + ninst + 1, v) - bounds) - 1; };
+    for (int e = 0; e < ctx->nc && !*cross; ++e) {
+        const int i0 = inst(cv[4 * (size_t)e]);
+        for (int k = 1; k < 4; ++k)
+            if (inst(cv[4 * (size_t)e + k]) != i0) *cross = true;
+    }
+    return PC_OK;
+}
+
 pc_status pc_set_instances(pc_ctx *h, const int32_t *vertex_begin, int32_t ninst) {
     if (!h || !vertex_begin || ninst < 1) return PC_ERR_ARG;
     Ctx *ctx = &h->c;
@@ -321,6 +344,13 @@ pc_status pc_set_instances(pc_ctx *h, const int32_t *vertex_begin, int32_t ninst
             ctx->err = "triangle " + std::to_string(t) + " joins two instances";
             return PC_ERR_MESH;
         }
+    }
+    bool cross = false;
+    pc_status cst = contacts_cross(ctx, vertex_begin, ninst, &cross);
+    if (cst) return cst;
+    if (cross) {
+        ctx->err = "a contact pair joins two instances";
+        return PC_ERR_ARG;
     }
     ctx->inst_row0_h.assign(vertex_begin, vertex_begin + ninst + 1);
     return build_schedule(ctx);
@@ -569,6 +599,86 @@ pc_status cloth_export_pattern(pc_ctx *h, int32_t *rowptr_out, int32_t *colidx_o
 pc_status cloth_export_blocks(pc_ctx *h, double *vals_out, double *D_out, int32_t solver_blocks, void *stream) {
     if (!h || !vals_out) return PC_ERR_ARG;
     return export_blocks(&h->c, vals_out, D_out, solver_blocks != 0, (hipStream_t)stream);
+}
+
+pc_status cloth_set_contacts(pc_ctx *h, int32_t ncontacts, const int32_t *verts, const double *weights,
+                             const double *normals, double thickness, double stiffness, void *stream) {
+    if (!h) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    hipStream_t s = (hipStream_t)stream;
+    if (ncontacts < 0 || ncontacts >= MAX_ELEMS) { ctx->err = "bad contact count"; return PC_ERR_ARG; }
+    if (ncontacts > 0 && (!verts || !weights || !normals)) {
+        ctx->err = "cloth_set_contacts: null contact arrays";
+        return PC_ERR_ARG;
+    }
+    if (ncontacts > 0 && (!(thickness > 0.0) || !(stiffness >= 0.0) || !std::isfinite(thickness) ||
+                          !std::isfinite(stiffness))) {
+        ctx->err = "cloth_set_contacts: thickness must be > 0 and stiffness >= 0";
+        return PC_ERR_ARG;
+    }
+    pc_status st;
+    const int64_t nc = ncontacts;
+    if (nc > ctx->nc_cap) {
+        void **bufs[] = {(void **)&ctx->cverts, (void **)&ctx->cw, (void **)&ctx->cn};
+        const size_t sizes[] = {sizeof(int) * 4 * (size_t)nc, sizeof(double) * 4 * (size_t)nc,
+                                sizeof(double) * 3 * (size_t)nc};
+        for (int k = 0; k < 3; ++k) {
+            if (*bufs[k]) (void)hipFree(*bufs[k]);
+            *bufs[k] = nullptr;
+        }
+        ctx->nc_cap = 0;
+        for (int k = 0; k < 3; ++k)
+            if ((st = dev_alloc(ctx, bufs[k], sizes[k]))) return st;
+        ctx->nc_cap = nc;
+    }
+    if (nc > 0) {
+        PC_HIP(hipMemcpyAsync(ctx->cverts, verts, sizeof(int) * 4 * (size_t)nc, hipMemcpyDeviceToDevice, s));
+        PC_HIP(hipMemcpyAsync(ctx->cw, weights, sizeof(double) * 4 * (size_t)nc, hipMemcpyDeviceToDevice, s));
+        PC_HIP(hipMemcpyAsync(ctx->cn, normals, sizeof(double) * 3 * (size_t)nc, hipMemcpyDeviceToDevice, s));
+        int bad = 0;
+        if ((st = check_contacts(ctx, (int)nc, &bad, s))) return st;
+        if (bad) {
+            ctx->nc = 0;
+            ctx->assembled = false;
+            ctx->err = "cloth_set_contacts: a contact has an index out of range, repeated vertices, weights "
+                       "not summing to zero or a normal that is not unit length";
+            return PC_ERR_ARG;
+        }
+    }
+    // capacities: 4 incidences and at most 12 more blocks per contact
+    const int64_t ninc = 3 * (int64_t)ctx->nt + 4 * (int64_t)ctx->nh + 4 * nc;
+    if (ninc > ctx->ninc_cap) {
+        if (ctx->inc) (void)hipFree(ctx->inc);
+        ctx->inc = nullptr;
+        ctx->ninc_cap = 0;
+        if ((st = dev_alloc(ctx, (void **)&ctx->inc, sizeof(int) * (size_t)ninc))) return st;
+        ctx->ninc_cap = ninc;
+    }
+    ctx->ninc = ninc;
+    const int64_t cap = ctx->cap_base + 12 * nc;
+    if (cap >= (int64_t)1 << 31) {
+        ctx->err = "block capacity exceeds int32 indexing";
+        return PC_ERR_CAPACITY;
+    }
+    if (cap > ctx->cap) {
+        if (ctx->colidx) (void)hipFree(ctx->colidx);
+        ctx->colidx = nullptr;
+        if ((st = dev_alloc(ctx, (void **)&ctx->colidx, sizeof(int) * (size_t)cap))) return st;
+        ctx->cap = cap;
+        if ((st = build_schedule(ctx))) return st;   // stored-block capacity follows cap
+    }
+    ctx->nc = (int)nc;
+    ctx->ceta = thickness;
+    ctx->ckc = stiffness;
+    ctx->assembled = false;   // the pattern changes with the contacts
+    bool cross = false;
+    if ((st = contacts_cross(ctx, ctx->inst_row0_h.data(), ctx->ninst, &cross))) return st;
+    if (cross) {
+        ctx->nc = 0;
+        ctx->err = "cloth_set_contacts: a contact pair joins two instances";
+        return PC_ERR_ARG;
+    }
+    return PC_OK;
 }
 
 pc_status cloth_export_precond(pc_ctx *h, float *inv_diag_out, float *inv_blocks_out, void *stream) {

@@ -395,42 +395,74 @@ pc_status topo_build(Ctx *ctx, const pc_mesh *mesh, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- incidences
-// Incidence code: bit 31 = hinge, bits 2..30 = element index, bits 0..1 = corner.
-__global__ void k_inc_count(int nt, int nh, const int *tri, const int *hinge, int *cnt) {
+// Bucket every corner of every element (3 per triangle, 4 per hinge, 4 per
+// contact) at its vertex; codes as in pc_common.h.
+__global__ void k_inc_count(int nt, int nh, int nc, const int *tri, const int *hinge, const int *cverts,
+                            int *cnt) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ntc = 3 * (int64_t)nt;
+    const int64_t ntc = 3 * (int64_t)nt, nhc = 4 * (int64_t)nh;
     if (idx < ntc) {
         atomicAdd(&cnt[tri[idx]], 1);
-    } else if (idx < ntc + 4 * (int64_t)nh) {
+    } else if (idx < ntc + nhc) {
         atomicAdd(&cnt[hinge[idx - ntc]], 1);
+    } else if (idx < ntc + nhc + 4 * (int64_t)nc) {
+        atomicAdd(&cnt[cverts[idx - ntc - nhc]], 1);
     }
 }
 
-__global__ void k_inc_fill(int nt, int nh, const int *tri, const int *hinge, int *cnt, const int *ptr,
-                           int *inc) {
+__global__ void k_inc_fill(int nt, int nh, int nc, const int *tri, const int *hinge, const int *cverts, int *cnt,
+                           const int *ptr, int *inc) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t ntc = 3 * (int64_t)nt;
-    int v, code;
+    const int64_t ntc = 3 * (int64_t)nt, nhc = 4 * (int64_t)nh;
+    int v;
+    unsigned code;
     if (idx < ntc) {
         const int k = (int)(idx / nt), t = (int)(idx % nt);
         v = tri[idx];
-        code = (t << 2) | k;
-    } else if (idx < ntc + 4 * (int64_t)nh) {
+        code = inc_code(INC_TRI, (unsigned)t, (unsigned)k);
+    } else if (idx < ntc + nhc) {
         const int64_t j = idx - ntc;
         const int k = (int)(j / nh), h = (int)(j % nh);
         v = hinge[j];
-        code = (int)(0x80000000u | ((unsigned)h << 2) | (unsigned)k);
+        code = inc_code(INC_HINGE, (unsigned)h, (unsigned)k);
+    } else if (idx < ntc + nhc + 4 * (int64_t)nc) {
+        const int64_t j = idx - ntc - nhc;   // contacts are vertex-major: (contact, corner)
+        const int e = (int)(j >> 2), k = (int)(j & 3);
+        v = cverts[j];
+        code = inc_code(INC_CONTACT, (unsigned)e, (unsigned)k);
     } else {
         return;
     }
     const int slot = atomicSub(&cnt[v], 1) - 1;
-    inc[ptr[v] + slot] = code;
+    inc[ptr[v] + slot] = (int)code;
+}
+
+// Validation of a contact set: indices in range, four distinct vertices,
+// weights summing to zero, unit normals.
+__global__ void k_check_contacts(int nc, int nv, const int *cv, const double *w, const double *n, int *bad) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nc) return;
+    bool ok = true;
+    for (int k = 0; k < 4; ++k) {
+        const int a = cv[4 * e + k];
+        ok = ok && a >= 0 && a < nv;
+        for (int l = 0; l < k; ++l) ok = ok && cv[4 * e + l] != a;
+    }
+    double s = 0.0, sa = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        s += w[4 * e + k];
+        sa += fabs(w[4 * e + k]);
+    }
+    ok = ok && isfinite(s) && fabs(s) <= 1e-9 * sa && sa > 0.0;
+    const double nn = n[3 * e] * n[3 * e] + n[3 * e + 1] * n[3 * e + 1] + n[3 * e + 2] * n[3 * e + 2];
+    ok = ok && fabs(nn - 1.0) <= 1e-6;
+    if (!ok) atomicOr(bad, 1);
 }
 
 struct RowLDS {
     unsigned inc[64];
     int ev[64][4];
-    unsigned cand[128];
+    unsigned cand[256];
     int cols[64];
     double ed[64][14];   // element data of each incidence
     double fk[64][3];    // force on this row's corner of each incidence
@@ -439,6 +471,10 @@ struct RowLDS {
 struct AsmArgs {
     int nv, nt, nh;
     const int *tri, *hinge, *inc_ptr, *inc;
+    int nc;                      // contacts: vertices (nc x 4), weights (nc x 4), normals (nc x 3)
+    const int *cverts;
+    const double *cw, *cn;
+    double ceta, ckc;            // thickness, stiffness
     const double *Bm, *A0, *hcoef, *htbar, *mass;
     const uint8_t *pinned;
     const double *x, *v;
@@ -465,10 +501,14 @@ __device__ __forceinline__ int row_load(RowLDS &L, const AsmArgs &A, int i) {
     bitonic_lds<64>(L.inc);
     if (t < n) {
         const unsigned code = L.inc[t];
-        const int e = (int)((code & 0x7fffffffu) >> 2);
-        if (code >> 31) {
+        const int e = inc_elem(code);
+        const unsigned type = inc_type(code);
+        if (type == INC_HINGE) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) L.ev[t][q] = A.hinge[q * A.nh + e];
+        } else if (type == INC_CONTACT) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) L.ev[t][q] = A.cverts[4 * e + q];
         } else {
 #pragma unroll
             for (int q = 0; q < 3; ++q) L.ev[t][q] = A.tri[q * A.nt + e];
@@ -480,41 +520,58 @@ __device__ __forceinline__ int row_load(RowLDS &L, const AsmArgs &A, int i) {
 }
 
 // Distinct block columns of row i, ascending, diagonal included.  The column
-// set is {i} together with the other corners of every incident triangle and
-// the opposite wing of every hinge in which i is a wing (edge endpoints of a
-// hinge already share a triangle with its wings).  Returns the row length or
-// -1 when it exceeds MAX_COLS; L.cols holds the columns.
+// set is {i} together with the other corners of every incident triangle, the
+// opposite wing of every hinge in which i is a wing (edge endpoints of a
+// hinge already share a triangle with its wings) and the other three
+// vertices of every incident contact.  Each incidence offers up to 3
+// candidates (4 slots per lane, 256 in all), sorted and de-duplicated.
+// Returns the row length or -1 when it exceeds MAX_COLS; L.cols holds the
+// columns.
 __device__ __forceinline__ int row_columns(RowLDS &L, int i, int n) {
     const int t = threadIdx.x;
-    unsigned c0 = NONE, c1 = NONE;
+    unsigned c[4] = {NONE, NONE, NONE, NONE};
     if (t < n) {
         const unsigned code = L.inc[t];
-        const int k = code & 3;
-        if (!(code >> 31)) {
-            c0 = (unsigned)L.ev[t][(k + 1) % 3];
-            c1 = (unsigned)L.ev[t][(k + 2) % 3];
-        } else if (k == 2) {
-            c0 = (unsigned)L.ev[t][3];
-        } else if (k == 3) {
-            c0 = (unsigned)L.ev[t][2];
+        const int k = inc_corner(code);
+        const unsigned type = inc_type(code);
+        if (type == INC_TRI) {
+            c[0] = (unsigned)L.ev[t][(k + 1) % 3];
+            c[1] = (unsigned)L.ev[t][(k + 2) % 3];
+        } else if (type == INC_HINGE) {
+            if (k == 2) c[0] = (unsigned)L.ev[t][3];
+            if (k == 3) c[0] = (unsigned)L.ev[t][2];
+        } else {   // the three corners other than k, in order
+            c[0] = (unsigned)L.ev[t][k == 0 ? 1 : 0];
+            c[1] = (unsigned)L.ev[t][k <= 1 ? 2 : 1];
+            c[2] = (unsigned)L.ev[t][k <= 2 ? 3 : 2];
         }
     }
-    L.cand[2 * t] = c0;
-    L.cand[2 * t + 1] = c1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) L.cand[4 * t + q] = c[q];
     __syncthreads();
-    bitonic_lds<128>(L.cand);
-    const unsigned a = L.cand[2 * t], b = L.cand[2 * t + 1];
-    const unsigned prev = t > 0 ? L.cand[2 * t - 1] : NONE;
-    const int ua = (a != NONE) && (t == 0 || a != prev);
-    const int ub = (b != NONE) && (b != a);
-    const int cnt = ua + ub;
+    bitonic_lds<256>(L.cand);
+    int u[4], cnt = 0, below = 0;
+    const unsigned ui = (unsigned)i;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int idx = 4 * t + q;
+        c[q] = L.cand[idx];
+        const unsigned prev = idx > 0 ? L.cand[idx - 1] : NONE;
+        u[q] = (c[q] != NONE) && (idx == 0 || c[q] != prev);
+        cnt += u[q];
+        below += (u[q] && c[q] < ui);
+    }
     const int pre = wave_excl_scan(cnt);
     const int total = __shfl(pre + cnt, WAVE - 1, WAVE);
-    const unsigned ui = (unsigned)i;
-    const int dpos = wave_sum_int((ua && a < ui) + (ub && b < ui));
+    const int dpos = wave_sum_int(below);
     if (total + 1 > MAX_COLS) return -1;
-    if (ua) L.cols[pre + (a > ui ? 1 : 0)] = (int)a;
-    if (ub) L.cols[pre + ua + (b > ui ? 1 : 0)] = (int)b;
+    int o = pre;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (u[q]) {
+            L.cols[o + (c[q] > ui ? 1 : 0)] = (int)c[q];
+            ++o;
+        }
     if (t == 0) L.cols[dpos] = i;
     __syncthreads();
     return total + 1;
@@ -630,9 +687,33 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
     // ---- phase A: lane t evaluates incidence t's element
     if (t < n) {
         const unsigned code = L.inc[t];
-        const int e = (int)((code & 0x7fffffffu) >> 2);
-        const int k = code & 3;
-        if (!(code >> 31)) {
+        const int e = inc_elem(code);
+        const int k = inc_corner(code);
+        const unsigned type = inc_type(code);
+        if (type == INC_CONTACT) {
+            // repulsion element: gap g = n . sum_q c_q x_q, energy kc/2 (eta - g)^2
+            // while g < eta; K_kl = kc c_k c_l n n^T (active at x), force on
+            // corner k kc (eta - g) c_k n (active at the force state)
+            const d3 nrm = mk(A.cn[3 * e], A.cn[3 * e + 1], A.cn[3 * e + 2]);
+            double cw[4];
+            double gx = 0.0, gy = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                cw[q] = A.cw[4 * e + q];
+                const int vq = L.ev[t][q];
+                const d3 xq = ld3(A.x, vq);
+                const d3 yq = xq + (P.s_look * P.h) * ld3(A.v, vq);
+                gx += cw[q] * dot(nrm, xq);
+                gy += cw[q] * dot(nrm, yq);
+            }
+            double *ed = L.ed[t];
+            ed[0] = nrm.x; ed[1] = nrm.y; ed[2] = nrm.z;
+            ed[3] = cw[0]; ed[4] = cw[1]; ed[5] = cw[2]; ed[6] = cw[3];
+            ed[7] = gx < A.ceta ? A.ckc : 0.0;
+            const double ck = k == 0 ? cw[0] : (k == 1 ? cw[1] : (k == 2 ? cw[2] : cw[3]));
+            const double m = gy < A.ceta ? A.ckc * (A.ceta - gy) * ck : 0.0;
+            L.fk[t][0] = m * nrm.x; L.fk[t][1] = m * nrm.y; L.fk[t][2] = m * nrm.z;
+        } else if (type == INC_TRI) {
             TriShape sh;
             const double B0 = A.Bm[e], B1 = A.Bm[A.nt + e], B2 = A.Bm[2 * A.nt + e], B3 = A.Bm[3 * A.nt + e];
             sh.b[1][0] = B0; sh.b[1][1] = B1;
@@ -716,15 +797,22 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
     if (active && !isdiag) {
         for (int m = 0; m < n; ++m) {
             const unsigned code = L.inc[m];
-            const int k = code & 3;
-            const bool hinge = code >> 31;
+            const int k = inc_corner(code);
+            const unsigned type = inc_type(code);
             int l = -1;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (L.ev[m][q] == col) l = q;
             if (l < 0) continue;
             const double *ed = L.ed[m];
-            if (!hinge) {
+            if (type == INC_CONTACT) {
+                const double ck = ed[3 + k], cl = ed[3 + l];
+                const double sc = ed[7] * ck * cl;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) acc[3 * a + b] += sc * ed[a] * ed[b];
+            } else if (type == INC_TRI) {
                 // K_kl = A0 [mu (b_k.b_l) F F^T + mu u_l u_k^T + lam u_k u_l^T + (b_k^T S+ b_l) I]
                 double bk0, bk1, bl0, bl1;
                 const double B0 = ed[9], B1 = ed[10], B2 = ed[11], B3 = ed[12];
@@ -884,6 +972,21 @@ __global__ void __launch_bounds__(64) k_export(int nv, const int *rowptr, const 
 
 static size_t dtype_size(pc_dtype d) { return d == PC_F64 ? 8 : (d == PC_F32 ? 4 : 2); }
 
+__global__ void k_clear_bits(int *status, int mask) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) status[0] &= ~mask;
+}
+
+pc_status check_contacts(Ctx *ctx, int nc, int *bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, (int *)ctx->counter, 0, (int64_t)1);
+    hipLaunchKernelGGL(k_check_contacts, dim3((nc + 255) / 256), dim3(256), 0, s, nc, ctx->nv, ctx->cverts, ctx->cw,
+                       ctx->cn, (int *)ctx->counter);
+    PC_HIP(hipGetLastError());
+    PC_HIP(hipMemcpyAsync(ctx->status_host, ctx->counter, sizeof(int), hipMemcpyDeviceToHost, s));
+    PC_HIP(hipStreamSynchronize(s));
+    *bad = *ctx->status_host;
+    return PC_OK;
+}
+
 pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtype, double *b,
                        double *diag_out, hipStream_t s) {
     const int nv = ctx->nv, nt = ctx->nt, nh = ctx->nh;
@@ -909,18 +1012,21 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
         ctx->hi_blocks = ctx->vcap;
     }
     ctx->hi_valid = dtype != PC_F64;
-    // 1. incidence buckets
+    // 1. incidence buckets (the row-limit bits describe this assembly only)
     const int slot_all = ctx->prof.begin(PK_ASM_ALL, s);
-    const int64_t ni = 3 * (int64_t)nt + 4 * (int64_t)nh;
-    hipLaunchKernelGGL(k_inc_count, dim3((ni + TB - 1) / TB), dim3(TB), 0, s, nt, nh, ctx->tri, ctx->hinge,
-                       ctx->inc_cnt);
+    hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(64), 0, s, ctx->status, ST_INC_OVERFLOW | ST_COL_OVERFLOW);
+    const int nc = ctx->nc;
+    const int64_t ni = 3 * (int64_t)nt + 4 * (int64_t)nh + 4 * (int64_t)nc;
+    hipLaunchKernelGGL(k_inc_count, dim3((ni + TB - 1) / TB), dim3(TB), 0, s, nt, nh, nc, ctx->tri, ctx->hinge,
+                       ctx->cverts, ctx->inc_cnt);
     if ((st = scan_excl(ctx, ctx->inc_cnt, ctx->inc_ptr, nv, s))) return st;
-    hipLaunchKernelGGL(k_inc_fill, dim3((ni + TB - 1) / TB), dim3(TB), 0, s, nt, nh, ctx->tri, ctx->hinge,
-                       ctx->inc_cnt, ctx->inc_ptr, ctx->inc);
+    hipLaunchKernelGGL(k_inc_fill, dim3((ni + TB - 1) / TB), dim3(TB), 0, s, nt, nh, nc, ctx->tri, ctx->hinge,
+                       ctx->cverts, ctx->inc_cnt, ctx->inc_ptr, ctx->inc);
     // 2. row lengths and pointers
     AsmArgs a;
     a.nv = nv; a.nt = nt; a.nh = nh;
     a.tri = ctx->tri; a.hinge = ctx->hinge; a.inc_ptr = ctx->inc_ptr; a.inc = ctx->inc;
+    a.nc = nc; a.cverts = ctx->cverts; a.cw = ctx->cw; a.cn = ctx->cn; a.ceta = ctx->ceta; a.ckc = ctx->ckc;
     a.Bm = ctx->Bm; a.A0 = ctx->A0; a.hcoef = ctx->hcoef; a.htbar = ctx->htbar; a.mass = ctx->mass;
     a.pinned = ctx->pinned; a.x = x; a.v = v; a.prm = ctx->prm;
     a.rowlen = ctx->rowlen; a.rowptr = ctx->rowptr; a.colidx = ctx->colidx; a.jcol = ctx->jcol;

@@ -24,6 +24,19 @@ enum : int {
     ST_BUCKET_OVERFLOW = 128,
 };
 
+// Incidence codes of the per-vertex buckets: element type in bits 30..31
+// (triangle, hinge, contact), element index in bits 2..29, corner in 0..1.
+// Sorting the codes orders a row's incidences triangles first, then hinges,
+// then contacts, each by index.
+enum : unsigned { INC_TRI = 0u, INC_HINGE = 1u, INC_CONTACT = 2u };
+__host__ __device__ __forceinline__ unsigned inc_code(unsigned type, unsigned e, unsigned k) {
+    return (type << 30) | (e << 2) | k;
+}
+__host__ __device__ __forceinline__ unsigned inc_type(unsigned code) { return code >> 30; }
+__host__ __device__ __forceinline__ int inc_elem(unsigned code) { return (int)((code & 0x3fffffffu) >> 2); }
+__host__ __device__ __forceinline__ int inc_corner(unsigned code) { return (int)(code & 3u); }
+constexpr int MAX_ELEMS = 1 << 28;   // elements of one type the codes can index
+
 struct DevParams {
     double h, mu, lam, kb, beta;
     double g[3];

@@ -109,7 +109,17 @@ struct Ctx {
     int nv = 0, nt = 0, nh = 0;
     int nslices = 0;          // ceil(nv / 64)
     int64_t cap = 0;          // block capacity (upper bound of nnzb)
-    int64_t ninc = 0;         // 3 nt + 4 nh incidences
+    int64_t ninc = 0;         // 3 nt + 4 nh + 4 nc incidences
+    int64_t ninc_cap = 0;     // incidences inc can hold
+    int64_t cap_base = 0;     // block capacity without contacts
+
+    // proximity (contact) elements of the following assemblies
+    int nc = 0;
+    int64_t nc_cap = 0;
+    int *cverts = nullptr;    // nc x 4
+    double *cw = nullptr;     // nc x 4 weights (sum zero)
+    double *cn = nullptr;     // nc x 3 unit normals
+    double ceta = 0.0, ckc = 0.0;
     DevParams prm{};
     pc_params user_prm{};
 
@@ -229,6 +239,7 @@ pc_status scan_excl(Ctx *ctx, const int *in, int *out, int n, hipStream_t s);
 pc_status dev_alloc(Ctx *ctx, void **p, size_t bytes);
 pc_status read_status(Ctx *ctx, hipStream_t s, int *bits);
 pc_status build_schedule(Ctx *ctx);
+pc_status check_contacts(Ctx *ctx, int nc, int *bad, hipStream_t s);
 pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, float *best_ms, hipStream_t s);
 
 }  // namespace pc
