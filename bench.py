@@ -55,13 +55,16 @@ def assembly_bytes(nv, nt, nh, nnzb, blocks):
     return reads + writes
 
 
-def cpu_baseline(cloth, gpu_iters_per_step, seconds_budget=25.0):
+def cpu_baseline(cloth, gpu_iters_per_step, seconds_budget=25.0, contacts=None):
     """The FP64 oracle on the host: one assembly of the same step and a
     bounded number of Jacobi-PCG iterations; steps/s extrapolated with the
     iteration count the GPU needed for the same tolerance."""
     from oracle import oracle
     oracle.build()
     P = oracle.Problem.from_cloth(cloth)
+    if contacts is not None:
+        P.set_contacts(oracle.Contacts(contacts.verts, contacts.weights, contacts.normals, contacts.eta,
+                                       contacts.kc))
     t0 = time.perf_counter()
     A = P.assemble(cloth.x0, cloth.v0)
     t_asm = time.perf_counter() - t0
@@ -155,18 +158,23 @@ def read_traffic(kernel):
 
 
 def make_cloth(meshgen, workload):
+    """(cloth, proximity pairs or None)."""
     if workload == "large":
-        return meshgen.config_large()
+        return meshgen.config_large(), None
     if workload == "medium":
-        return meshgen.config_medium()
-    return meshgen.config_batch()
+        return meshgen.config_medium(), None
+    if workload == "contact":
+        return meshgen.config_contact()
+    return meshgen.config_batch(), None
 
 
-def new_context(binding, cloth):
+def new_context(binding, cloth, contacts=None):
     ctx = binding.Context.from_cloth(cloth)
     if len(cloth.sheet_ranges) > 1 and cloth.name.startswith("batch"):
         # independent cloths: per-instance CG scalars, convergence and sweeps
         ctx.set_instances([r[0] for r in cloth.sheet_ranges] + [cloth.nv])
+    if contacts is not None:
+        ctx.cloth_set_contacts(contacts.verts, contacts.weights, contacts.normals, contacts.eta, contacts.kc)
     return ctx
 
 
@@ -183,9 +191,10 @@ def main():
                     help="preconditioner of the project configuration")
     ap.add_argument("--inner-rho", type=float, default=0.0,
                     help="residual reduction per refinement sweep (0: library default)")
-    ap.add_argument("--workload", default="large", choices=["large", "medium", "batch"],
+    ap.add_argument("--workload", default="large", choices=["large", "medium", "batch", "contact"],
                     help="large: 3 stacked sheets, 1.65M triangles (the headline); batch: 64 uneven "
-                         "independent sheets, ~1.5M triangles in one launch")
+                         "independent sheets, ~1.5M triangles in one launch; contact: 2 sheets 1.5 mm "
+                         "apart with 274K vertex-face proximity pairs in the assembly")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 / Jacobi / zero-start run")
     ap.add_argument("--prof-every", type=int, default=8)
@@ -208,12 +217,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t0 = time.perf_counter()
-    cloth = make_cloth(meshgen, args.workload)
-    log(f"# workload {cloth.name}: nv={cloth.nv} nt={cloth.nt} ({time.perf_counter() - t0:.1f} s)")
+    cloth, contacts = make_cloth(meshgen, args.workload)
+    log(f"# workload {cloth.name}: nv={cloth.nv} nt={cloth.nt}"
+        f"{'' if contacts is None else f' contacts={contacts.n}'} ({time.perf_counter() - t0:.1f} s)")
     tol = cloth.tol
     rec_plain = None
     if not args.no_plain:
-        ctx = new_context(binding, cloth)
+        ctx = new_context(binding, cloth, contacts)
         x = torch.from_numpy(cloth.x0.copy()).cuda()
         v = torch.from_numpy(cloth.v0.copy()).cuda()
         tune_plain = None
@@ -236,7 +246,7 @@ def main():
     params = None
     if args.warm == "learned":
         params, train_info = train_warm_start(binding, meshgen, args.train_steps, 3, 1e-3, log)
-    ctx = new_context(binding, cloth)
+    ctx = new_context(binding, cloth, contacts)
     if params is not None:
         ctx.ws_set_params(params)
     x = torch.from_numpy(cloth.x0.copy()).cuda()
@@ -296,7 +306,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{cloth.name}: {nt} triangles, {nv} vertices, {nh} hinges, nnzb {nnzb}",
+            "workload": f"{cloth.name}: {nt} triangles, {nv} vertices, {nh} hinges, nnzb {nnzb}"
+                        + ("" if contacts is None else f", {contacts.n} proximity pairs"),
             "h": cloth.h, "tol": tol, "block_storage": args.blocks, "warm_start": args.warm,
             "refinement_sweeps": [i["sweeps"] for i in infos], "starts_used": [i["warm_used"] for i in infos],
             "preconditioner": args.precond, "inner_rho": args.inner_rho,
@@ -328,7 +339,7 @@ def main():
     ctx.close()
     if not args.no_cpu_baseline:
         log("# cpu baseline (oracle)...")
-        rec["cpu_baseline"] = cpu_baseline(cloth, float(np.mean(iters)))
+        rec["cpu_baseline"] = cpu_baseline(cloth, float(np.mean(iters)), contacts=contacts)
     print(json.dumps(rec), flush=True)
 
 

@@ -35,20 +35,25 @@ def spmv_source_hash() -> str:
 
 def kernel_rows(db):
     con = sqlite3.connect(db)
-    return con.execute("select name, start, end from kernels").fetchall()
+    return con.execute("select name, start, end, grid_x from kernels").fetchall()
 
 
-def trace_table(db, top=15):
+def trace_table(db, top=15, by_grid=False):
+    """Per-kernel table; with by_grid, launches of one kernel with different
+    grid sizes (different workloads or schedules) are listed separately."""
     rows = kernel_rows(db)
     per = {}
-    for name, s, e in rows:
-        per.setdefault(name, []).append((e - s) / 1e3)
+    for name, s, e, gx in rows:
+        key = (name, gx if by_grid else 0)
+        per.setdefault(key, []).append((e - s) / 1e3)
     total = sum(sum(v) for v in per.values())
-    out = ["| kernel | calls | mean us | mean us, full launches | min us | max us | share |",
-           "|---|---|---|---|---|---|---|"]
-    for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:top]:
+    head = "| kernel | grid threads | calls" if by_grid else "| kernel | calls"
+    out = [head + " | mean us | mean us, full launches | min us | max us | share |",
+           "|---|---|---|---|---|---|---|" + ("---|" if by_grid else "")]
+    for (name, gx), v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:top]:
         short = name.split("(")[0].replace("void ", "")
-        out.append(f"| `{short}` | {len(v)} | {statistics.mean(v):.2f} | {full_mean(v):.2f} | {min(v):.2f} | "
+        lead = f"| `{short}` | {gx} | {len(v)}" if by_grid else f"| `{short}` | {len(v)}"
+        out.append(f"{lead} | {statistics.mean(v):.2f} | {full_mean(v):.2f} | {min(v):.2f} | "
                    f"{max(v):.2f} | {100 * sum(v) / total:.1f}% |")
     return "\n".join(out)
 
@@ -112,6 +117,7 @@ def main(argv=None):
     t = sub.add_parser("trace")
     t.add_argument("db")
     t.add_argument("--top", type=int, default=15)
+    t.add_argument("--by-grid", action="store_true")
     p = sub.add_parser("pmc")
     p.add_argument("fetch_db")
     p.add_argument("write_db")
@@ -120,7 +126,7 @@ def main(argv=None):
     p.add_argument("--copy-bytes", type=float, required=True)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
-        print(trace_table(a.db, a.top))
+        print(trace_table(a.db, a.top, a.by_grid))
     else:
         print(pmc_table(a.fetch_db, a.write_db, a.kernel, a.copy_kernel, a.copy_bytes))
 
