@@ -287,9 +287,13 @@ pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
  *   larger work items cost less per iteration on large instances.
  * PC_OPT_LDS_WINDOW: 1 (default): each SpMV work item whose block columns
  *   span at most 4096 rows first copies that window of the search direction
- *   to LDS and gathers from there; 0: all gathers from global memory. */
+ *   to LDS and gathers from there; 0: all gathers from global memory.
+ * PC_OPT_NARROW_COLUMNS: 1 (default): when every block column lies within
+ *   +-32767 rows of its 64-row slice (true for meshes numbered in grid
+ *   order), the CG SpMV reads 16-bit column offsets instead of 32-bit
+ *   columns; 0: always 32-bit.  Results do not change. */
 typedef enum { PC_OPT_GRAPH_CHUNK = 0, PC_OPT_SPMV_SLICES_PER_BLOCK = 1, PC_OPT_VECTOR_ROWS_PER_BLOCK = 2,
-               PC_OPT_LDS_WINDOW = 3 } pc_option;
+               PC_OPT_LDS_WINDOW = 3, PC_OPT_NARROW_COLUMNS = 4 } pc_option;
 pc_status pc_set_option(pc_ctx *ctx, int32_t option, int64_t value);
 pc_status pc_get_option(pc_ctx *ctx, int32_t option, int64_t *value);
 

@@ -34,7 +34,8 @@ WS_PARAMS = 10307
 # vector holds, per layer, W row-major then the bias.
 WS_SHAPES = [(27, 64), (64, 64), (64, 64), (64, 3)]
 WARM = {"zero": 0, "prev": 1, "given": 1, "learned": 2}
-PC_OPT_GRAPH_CHUNK, PC_OPT_SPMV_SLICES_PER_BLOCK, PC_OPT_VECTOR_ROWS_PER_BLOCK, PC_OPT_LDS_WINDOW = 0, 1, 2, 3
+PC_OPT_GRAPH_CHUNK, PC_OPT_SPMV_SLICES_PER_BLOCK, PC_OPT_VECTOR_ROWS_PER_BLOCK, PC_OPT_LDS_WINDOW, \
+    PC_OPT_NARROW_COLUMNS = 0, 1, 2, 3, 4
 PROFILE_KINDS = ["spmv", "cg_update", "cg_dir", "row_assemble", "row_pattern", "assemble_all", "k6", "k7"]
 
 

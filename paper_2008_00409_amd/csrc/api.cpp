@@ -66,7 +66,7 @@ static void free_all(Ctx *c) {
     void *ptrs[] = {c->tri, c->Bm, c->A0, c->hinge, c->hcoef, c->htbar, c->mass, c->pinned, c->status,
                     c->inc_cnt, c->inc_ptr, c->inc, c->rowlen, c->rowptr, c->colidx, c->jcol, c->lane_row,
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
-                    c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn,
+                    c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn, c->jdel,
                     c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -254,6 +254,13 @@ pc_status pc_set_option(pc_ctx *h, int32_t option, int64_t value) {
             ctx->use_win = value != 0;
             ctx->win_valid = false;
             return PC_OK;
+        case PC_OPT_NARROW_COLUMNS:
+            if (value != 0 && value != 1) {
+                ctx->err = "narrow column option must be 0 or 1";
+                return PC_ERR_ARG;
+            }
+            ctx->use_narrow = value != 0;
+            return PC_OK;
         case PC_OPT_SPMV_SLICES_PER_BLOCK: {
             if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16) {
                 ctx->err = "slices per block must be 1, 2, 4, 8 or 16";
@@ -290,6 +297,7 @@ pc_status pc_get_option(pc_ctx *h, int32_t option, int64_t *value) {
         case PC_OPT_SPMV_SLICES_PER_BLOCK: *value = ctx->spb; return PC_OK;
         case PC_OPT_VECTOR_ROWS_PER_BLOCK: *value = ctx->rpb; return PC_OK;
         case PC_OPT_LDS_WINDOW: *value = ctx->use_win ? 1 : 0; return PC_OK;
+        case PC_OPT_NARROW_COLUMNS: *value = ctx->use_narrow ? 1 : 0; return PC_OK;
         default: ctx->err = "unknown option"; return PC_ERR_ARG;
     }
 }

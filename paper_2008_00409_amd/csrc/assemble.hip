@@ -480,6 +480,7 @@ struct AsmArgs {
     const double *x, *v;
     DevParams prm;
     int *rowlen, *rowptr, *colidx, *jcol;
+    int16_t *jdel;
     const int *row_lane, *row_slice, *slice_row0, *slice_vbase;
     const uint8_t *slot_cnt;
     void *jval;
@@ -638,6 +639,7 @@ __device__ void write_overflow_row(const AsmArgs &A, int i) {
     const int lane = A.row_lane[i];
     A.colidx[A.rowptr[i]] = i;
     A.jcol[seg + lane] = i;
+    A.jdel[seg + lane] = (int16_t)(i - A.slice_row0[s]);
     const double zero[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     BlockIO<TB>::store((TB *)A.jval + 9 * seg, w, lane, zero);
     if (A.jval_hi) BlockIO<double>::store(A.jval_hi + 9 * seg, w, lane, zero);
@@ -915,6 +917,9 @@ __global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
         const int64_t seg = (int64_t)A.slice_vbase[s] + off;
         const int lane = A.row_lane[i];
         A.jcol[seg + lane] = col;
+        // offset from the slice's first row; meaningful only when it fits
+        // (the solver checks every slice before using it)
+        A.jdel[seg + lane] = (int16_t)(col - A.slice_row0[s]);
         BlockIO<TB>::store((TB *)A.jval + 9 * seg, w, lane, blk);
         if (A.jval_hi) BlockIO<double>::store(A.jval_hi + 9 * seg, w, lane, blk);
     }
@@ -1029,7 +1034,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     a.nc = nc; a.cverts = ctx->cverts; a.cw = ctx->cw; a.cn = ctx->cn; a.ceta = ctx->ceta; a.ckc = ctx->ckc;
     a.Bm = ctx->Bm; a.A0 = ctx->A0; a.hcoef = ctx->hcoef; a.htbar = ctx->htbar; a.mass = ctx->mass;
     a.pinned = ctx->pinned; a.x = x; a.v = v; a.prm = ctx->prm;
-    a.rowlen = ctx->rowlen; a.rowptr = ctx->rowptr; a.colidx = ctx->colidx; a.jcol = ctx->jcol;
+    a.rowlen = ctx->rowlen; a.rowptr = ctx->rowptr; a.colidx = ctx->colidx; a.jcol = ctx->jcol; a.jdel = ctx->jdel;
     a.row_lane = ctx->row_lane; a.slot_cnt = ctx->slot_cnt; a.jval = ctx->jval;
     a.row_slice = ctx->row_slice; a.slice_row0 = ctx->slice_row0; a.slice_vbase = ctx->slice_vbase;
     a.jval_hi = dtype != PC_F64 ? ctx->jval_hi : nullptr;

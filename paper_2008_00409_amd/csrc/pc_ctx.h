@@ -142,6 +142,9 @@ struct Ctx {
     int *rowptr = nullptr;    // nv + 1
     int *colidx = nullptr;    // cap (block-CSR order)
     int *jcol = nullptr;      // cap (solver layout)
+    int16_t *jdel = nullptr;  // the same columns as offsets from each slice's first row
+    bool narrow = false;      // every offset fits in 16 bits (decided with the windows)
+    bool use_narrow = true;   // PC_OPT_NARROW_COLUMNS
     int *lane_row = nullptr;  // nslices * 64 (row of each lane, -1 padding)
     int *row_lane = nullptr;  // nv
     uint8_t *slot_cnt = nullptr;  // nslices * 64
@@ -207,6 +210,7 @@ struct Ctx {
     int gkey_sched[2] = {-1, -1};
     int gkey_pre[2] = {-1, -1};
     int gkey_win[2] = {-1, -1};
+    int gkey_narrow[2] = {-1, -1};
 
     // column windows of the SpMV work items (p staged in LDS)
     int2 *sitem_win = nullptr;

@@ -32,9 +32,11 @@ struct SpmvArgs {
     int nv, nslices;
     const int *rowptr;
     const int *slice_vbase;
+    const int *slice_row0;
     const uint8_t *slot_cnt;
     const int *lane_row;
     const int *jcol;
+    const int16_t *jdel;   // block columns as offsets from the slice's first row
     const void *jval;
     const double *mass;
 };
@@ -84,14 +86,17 @@ struct VecD3 {
 // row's last) load a valid neighbouring element and their contribution is
 // masked afterwards; the diagonal slot gathers x_i itself.  Each block is
 // read with 16-byte loads (BlockIO).
-template <typename TB, int UNROLL>
+// NARROW: columns come from the 16-bit offsets jdel (added to the slice's
+// first row r0) instead of the 32-bit jcol.
+template <typename TB, int UNROLL, bool NARROW>
 struct SlotGroup {
     typedef typename BlockIO<TB>::R R;
     int jc[UNROLL];
     R v[UNROLL][9];
     bool act[UNROLL];
 
-    __device__ __forceinline__ void load(const SpmvArgs &M, int k, int nslots, int lane, int my_cnt, int my_off) {
+    __device__ __forceinline__ void load(const SpmvArgs &M, int k, int nslots, int lane, int my_cnt, int my_off,
+                                         int r0) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const int kk = min(k + u, nslots - 1);
@@ -99,7 +104,10 @@ struct SlotGroup {
             const int off = __builtin_amdgcn_readlane(my_off, kk);
             act[u] = (k + u < nslots) && lane < c;
             const int l = min(lane, c - 1);
-            jc[u] = M.jcol[off + l];
+            if (NARROW)
+                jc[u] = r0 + (int)M.jdel[off + l];
+            else
+                jc[u] = M.jcol[off + l];
             BlockIO<TB>::load((const TB *)M.jval + 9 * (int64_t)off, slot_width(c), l, v[u]);
         }
     }
@@ -124,29 +132,30 @@ struct SlotGroup {
     }
 };
 
-template <typename TB, typename V, int UNROLL = PC_SPMV_UNROLL>
+template <typename TB, typename V, bool NARROW = false, int UNROLL = PC_SPMV_UNROLL>
 __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, const V &x, double y[3],
                                         double xi[3]) {
     const int row = M.lane_row[slice * WAVE + lane];
     const int my_cnt = (int)M.slot_cnt[slice * WAVE + lane];
     const int my_off = M.slice_vbase[slice] + wave_excl_scan(slot_width(my_cnt));
+    const int r0 = NARROW ? M.slice_row0[slice] : 0;
     const int nslots = __popcll(__ballot(my_cnt > 0));  // counts are non-increasing in the slot
     double x0 = 0.0, x1 = 0.0, x2 = 0.0;
     if (row >= 0) x.load(row, x0, x1, x2);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #if PC_SPMV_PIPE
-    SlotGroup<TB, UNROLL> cur;
-    cur.load(M, 0, nslots, lane, my_cnt, my_off);
+    SlotGroup<TB, UNROLL, NARROW> cur;
+    cur.load(M, 0, nslots, lane, my_cnt, my_off, r0);
     for (int k = 0; k < nslots; k += UNROLL) {
-        SlotGroup<TB, UNROLL> nxt;
-        nxt.load(M, k + UNROLL, nslots, lane, my_cnt, my_off);
+        SlotGroup<TB, UNROLL, NARROW> nxt;
+        nxt.load(M, k + UNROLL, nslots, lane, my_cnt, my_off, r0);
         cur.apply(x, row, x0, x1, x2, a0, a1, a2);
         cur = nxt;
     }
 #else
     for (int k = 0; k < nslots; k += UNROLL) {
-        SlotGroup<TB, UNROLL> g;
-        g.load(M, k, nslots, lane, my_cnt, my_off);
+        SlotGroup<TB, UNROLL, NARROW> g;
+        g.load(M, k, nslots, lane, my_cnt, my_off, r0);
         g.apply(x, row, x0, x1, x2, a0, a1, a2);
     }
 #endif
@@ -309,7 +318,7 @@ __global__ void __launch_bounds__(256) k_item_windows(Sched S, const int *slice_
 // q = A p and per-item partials of p.q.  When the item's column window fits
 // in win_cap rows, p[window] is first copied to LDS with coalesced loads and
 // the rows gather from there; otherwise they gather from global memory.
-template <typename TB>
+template <typename TB, bool NARROW>
 __global__ void __launch_bounds__(1024) k_pcg_spmv(SpmvArgs M, Sched S, const float4 *p, double *q,
                                                   const PcgState *st, double *partials, const int2 *win,
                                                   int win_cap) {
@@ -331,8 +340,8 @@ __global__ void __launch_bounds__(1024) k_pcg_spmv(SpmvArgs M, Sched S, const fl
     double pq = 0.0;
     if (w < I.z) {
         double y[3], xi[3];
-        const int row = use_lds ? spmv_row<TB>(M, I.y + w, lane, VecLds{pwin, W.x}, y, xi)
-                                : spmv_row<TB>(M, I.y + w, lane, VecF4{p}, y, xi);
+        const int row = use_lds ? spmv_row<TB, VecLds, NARROW>(M, I.y + w, lane, VecLds{pwin, W.x}, y, xi)
+                                : spmv_row<TB, VecF4, NARROW>(M, I.y + w, lane, VecF4{p}, y, xi);
         if (row >= 0) {
             q[3 * row] = y[0];
             q[3 * row + 1] = y[1];
@@ -623,9 +632,11 @@ static SpmvArgs spmv_args(Ctx *ctx, bool hi) {
     M.nslices = ctx->nslices;
     M.rowptr = ctx->rowptr;
     M.slice_vbase = ctx->slice_vbase;
+    M.slice_row0 = ctx->slice_row0;
     M.slot_cnt = ctx->slot_cnt;
     M.lane_row = ctx->lane_row;
     M.jcol = ctx->jcol;
+    M.jdel = ctx->use_narrow ? ctx->jdel : nullptr;
     M.jval = (hi && ctx->hi_valid) ? (const void *)ctx->jval_hi : ctx->jval;
     M.mass = ctx->mass;
     return M;
@@ -702,6 +713,7 @@ pc_status build_schedule(Ctx *ctx) {
     ctx->vcap = vcap;
     if (vcap > ctx->jcol_blocks) {
         if ((st = realloc((void **)&ctx->jcol, sizeof(int) * (size_t)vcap))) return st;
+        if ((st = realloc((void **)&ctx->jdel, sizeof(int16_t) * (size_t)vcap))) return st;
         ctx->jcol_blocks = vcap;
     }
     if ((st = realloc((void **)&ctx->sitem, sizeof(int4) * sitems.size()))) return st;
@@ -783,6 +795,18 @@ static pc_status ensure_windows(Ctx *ctx, hipStream_t s) {
         if (n <= PC_WIN_MAX) cap = std::max(cap, n);
     }
     ctx->win_cap = ctx->use_win ? cap : 0;
+    // 16-bit column offsets: every column of an item's slices lies in
+    // [lo, hi], and the slices' first rows in [first row, first row + 64 spb)
+    bool narrow = true;
+    std::vector<int4> items(ctx->n_sitems);
+    std::vector<int> row0(ctx->nslices + 1);
+    PC_HIP(hipMemcpy(items.data(), ctx->sitem, sizeof(int4) * items.size(), hipMemcpyDeviceToHost));
+    PC_HIP(hipMemcpy(row0.data(), ctx->slice_row0, sizeof(int) * row0.size(), hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < items.size() && narrow; ++k) {
+        const int r_first = row0[items[k].y], r_last = row0[items[k].y + items[k].z - 1];
+        narrow = (long long)w[k].y - r_first <= 32767 && (long long)w[k].x - r_last >= -32768;
+    }
+    ctx->narrow = narrow;
     ctx->win_valid = true;
     return PC_OK;
 }
@@ -793,8 +817,14 @@ static pc_status ensure_windows(Ctx *ctx, hipStream_t s) {
 template <typename TB>
 static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s, int par) {
     int slot = ctx->prof.begin(PK_SPMV, s);
-    hipLaunchKernelGGL(k_pcg_spmv<TB>, dim3(g.sblocks), dim3(g.sthreads), sizeof(float4) * (size_t)ctx->win_cap, s, M,
-                       S, ctx->p, ctx->q, ctx->st, ctx->partials, ctx->sitem_win, ctx->win_cap);
+    if (ctx->narrow && M.jdel)
+        hipLaunchKernelGGL((k_pcg_spmv<TB, true>), dim3(g.sblocks), dim3(g.sthreads),
+                           sizeof(float4) * (size_t)ctx->win_cap, s, M, S, ctx->p, ctx->q, ctx->st, ctx->partials,
+                           ctx->sitem_win, ctx->win_cap);
+    else
+        hipLaunchKernelGGL((k_pcg_spmv<TB, false>), dim3(g.sblocks), dim3(g.sthreads),
+                           sizeof(float4) * (size_t)ctx->win_cap, s, M, S, ctx->p, ctx->q, ctx->st, ctx->partials,
+                           ctx->sitem_win, ctx->win_cap);
     ctx->prof.end(slot, s);
     hipLaunchKernelGGL(k_fin_alpha, dim3(ctx->ninst), dim3(256), 0, s, S, par, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
@@ -845,7 +875,8 @@ static void launch_start_zero(Ctx *ctx, const Sched &S, const Grids &g, const ui
 static bool graph_stale(const Ctx *ctx, int variant, const SpmvArgs &M, int elem_size) {
     return !ctx->gexec[variant] || ctx->gkey[variant] != M.jval || ctx->gkey_dtype[variant] != elem_size ||
            ctx->gkey_chunk[variant] != ctx->graph_chunk || ctx->gkey_sched[variant] != ctx->sched_version ||
-           ctx->gkey_pre[variant] != ctx->precond || ctx->gkey_win[variant] != ctx->win_cap;
+           ctx->gkey_pre[variant] != ctx->precond || ctx->gkey_win[variant] != ctx->win_cap ||
+           ctx->gkey_narrow[variant] != (int)ctx->narrow;
 }
 
 // Capture `chunk` (even) iterations on the context's capture stream; the
@@ -884,6 +915,7 @@ static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Sched &S, cons
     ctx->gkey_sched[variant] = ctx->sched_version;
     ctx->gkey_pre[variant] = ctx->precond;
     ctx->gkey_win[variant] = ctx->win_cap;
+    ctx->gkey_narrow[variant] = (int)ctx->narrow;
     return PC_OK;
 }
 

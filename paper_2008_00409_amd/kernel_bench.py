@@ -25,6 +25,7 @@ def main(argv=None):
     ap.add_argument("--spb", type=int, default=0, help="slices per SpMV block (0: library default)")
     ap.add_argument("--rpb", type=int, default=0, help="rows per vector block (0: library default)")
     ap.add_argument("--lds-window", type=int, default=1, help="1: stage the SpMV's p window in LDS")
+    ap.add_argument("--narrow", type=int, default=1, help="1: 16-bit column offsets when they fit")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy")
     ap.add_argument("--copies", type=int, default=5)
     a = ap.parse_args(argv)
@@ -44,6 +45,7 @@ def main(argv=None):
     if a.rpb:
         ctx.set_option(binding.PC_OPT_VECTOR_ROWS_PER_BLOCK, a.rpb)
     ctx.set_option(binding.PC_OPT_LDS_WINDOW, a.lds_window)
+    ctx.set_option(binding.PC_OPT_NARROW_COLUMNS, a.narrow)
     x = torch.from_numpy(c.x0.copy()).cuda()
     v = torch.from_numpy(c.v0.copy()).cuda()
     print(f"# kernel_bench {c.name}: nv={c.nv} nt={c.nt} blocks={a.blocks} precond={a.precond} iters={a.iters}",
