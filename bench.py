@@ -34,15 +34,16 @@ HBM_PEAK_GBS = 8000.0
 BLOCK_BYTES = {"f64": 72, "f32": 36, "bf16": 18}
 KERNEL_TB = {"f64": "double", "f32": "float", "bf16": "pc::bf16_t"}
 # committed counter summaries (profiles/) giving HBM bytes per launch
-TRAFFIC_FILES = {"k_pcg_spmv<pc::bf16_t>": "k_pcg_spmv_bf16_stacked-3x501x551_traffic.md",
-                 "k_pcg_spmv<float>": "k_pcg_spmv_f32_stacked-3x501x551_traffic.md"}
+TRAFFIC_FILES = {"k_pcg_spmv<pc::bf16_t, true>": "k_pcg_spmv_bf16_stacked-3x501x551_traffic.md",
+                 "k_pcg_spmv<float, true>": "k_pcg_spmv_f32_stacked-3x501x551_traffic.md"}
 
 
-def spmv_bytes(nv, nnzb, blocks):
+def spmv_bytes(nv, nnzb, blocks, col_bytes=4):
     """Algorithmic bytes of one difference-form SpMV in the CG loop: every
-    stored block and its column index once, the input vector once per row
+    stored block and its column index once (16-bit offsets when the SpMV
+    runs with them, else 32-bit columns), the input vector once per row
     (float4), the FP64 output, the FP64 mass, and the row pointers."""
-    return nnzb * (BLOCK_BYTES[blocks] + 4) + nv * (16 + 24 + 8) + 4 * (nv + 1)
+    return nnzb * (BLOCK_BYTES[blocks] + col_bytes) + nv * (16 + 24 + 8) + 4 * (nv + 1)
 
 
 def assembly_bytes(nv, nt, nh, nnzb, blocks):
@@ -234,11 +235,12 @@ def main():
         rowptr, colidx = ctx.pattern()
         nnzb = int(colidx.numel())
         sp = prof.get("spmv", {}).get("median_ms", float("nan"))
+        cb = 2 if ctx.get_option(binding.PC_OPT_SPMV_NARROW_ACTIVE) else 4
         rec_plain = {"steps_per_s": args.steps / el, "block_storage": "f32", "warm_start": "zero",
                      "preconditioner": "jacobi", "schedule": tune_plain,
                      "cg_iters_per_step": [i["iters"] for i in infos],
                      "rel_res_true_max": max(i["rel_res_true"] for i in infos),
-                     "spmv_median_ms": sp, "spmv_GBs": spmv_bytes(ctx.nv, nnzb, "f32") / (sp * 1e-3) / 1e9}
+                     "spmv_median_ms": sp, "spmv_GBs": spmv_bytes(ctx.nv, nnzb, "f32", cb) / (sp * 1e-3) / 1e9}
         log(f"# plain: {rec_plain['steps_per_s']:.3f} steps/s, iters {rec_plain['cg_iters_per_step']}")
         ctx.close()
         del x, v
@@ -287,8 +289,9 @@ def main():
     log(f"# paired starts on one system: {paired}")
     spmv = prof.get("spmv", {})
     spmv_ms = spmv.get("median_ms", float("nan"))
-    kname = f"k_pcg_spmv<{KERNEL_TB[args.blocks]}>"
-    alg = spmv_bytes(nv, nnzb, args.blocks)
+    narrow = bool(ctx.get_option(binding.PC_OPT_SPMV_NARROW_ACTIVE))
+    kname = f"k_pcg_spmv<{KERNEL_TB[args.blocks]}, {'true' if narrow else 'false'}>"
+    alg = spmv_bytes(nv, nnzb, args.blocks, 2 if narrow else 4)
     ach = alg / (spmv_ms * 1e-3) / 1e9 if spmv_ms == spmv_ms and spmv_ms > 0 else None
     asm = prof.get("assemble_all", {})
     asm_ms = asm.get("median_ms", float("nan"))

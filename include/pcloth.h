@@ -207,6 +207,34 @@ pc_status cloth_export_blocks(pc_ctx *ctx, double *vals_out, double *D_out, int3
 pc_status cloth_set_contacts(pc_ctx *ctx, int32_t ncontacts, const int32_t *verts, const double *weights,
                              const double *normals, double thickness, double stiffness, void *stream);
 
+/* ---- The paper's own matrix filling and layout (Sec. 3.2.2), for comparison ----
+ * cloth_assemble_bell assembles the same system as cloth_assemble (A = M +
+ * h (h + beta) K with pinned rows and columns eliminated, and b) in the five
+ * steps of the paper's GPU filling: per-row index-table sizes (every element
+ * corner adds one slot per vertex of its element, plus one diagonal slot per
+ * row), index filling with integer atomics, per-row sort and de-duplication
+ * (compacting), a BELL value table as wide as the longest compacted row,
+ * and value filling with one thread per element adding its 3x3 blocks with
+ * floating-point atomics.  Values: dtype PC_F32 or PC_F64 (else PC_ERR_ARG).
+ * Layout: slot k of row i at k*nv + i; columns ascending within a row, the
+ * padding repeats the row's own index with zero blocks; plane q (row-major
+ * 3x3 entry q) of slot k of row i at (q*width + k)*nv + i.  The atomics add
+ * in an order that varies between runs, so the last bits of A and b do.
+ * x, v: device nv*3 doubles; b: device nv*3 doubles (output); width_out
+ * (host, optional): the table width.  Synchronises the stream (the table
+ * sizes are read back to allocate, as in the paper).  The table lives in
+ * the context, independent of cloth_assemble's matrix. */
+pc_status cloth_assemble_bell(pc_ctx *ctx, const double *x, const double *v, pc_dtype dtype, double *b,
+                              int32_t *width_out, void *stream);
+/* y = A x over the BELL table, one thread per row: x (device nv*3 doubles)
+ * is rounded to FP32, as the solver's search direction is; FP64 accumulation
+ * into y (device nv*3 doubles).  PC_ERR_ARG before cloth_assemble_bell. */
+pc_status cloth_spmv_bell(pc_ctx *ctx, const double *x, double *y, void *stream);
+/* Copy the BELL table out: width_out (host, optional), cols_out (device
+ * nv*width int32, optional), vals_out (device 9*nv*width doubles, optional),
+ * in the layout above.  Enqueued on the stream. */
+pc_status cloth_export_bell(pc_ctx *ctx, int32_t *width_out, int32_t *cols_out, double *vals_out, void *stream);
+
 /* Preconditioners of the last assembly: inv_diag_out (device nv*3 floats)
  * receives 1 / diag(A); inv_blocks_out (device nv*6 floats) the inverses of
  * the 3x3 diagonal blocks A_ii as (xx, xy, xz, yy, yz, zz).  Either may be
@@ -291,9 +319,11 @@ pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
  * PC_OPT_NARROW_COLUMNS: 1 (default): when every block column lies within
  *   +-32767 rows of its 64-row slice (true for meshes numbered in grid
  *   order), the CG SpMV reads 16-bit column offsets instead of 32-bit
- *   columns; 0: always 32-bit.  Results do not change. */
+ *   columns; 0: always 32-bit.  Results do not change.
+ * PC_OPT_SPMV_NARROW_ACTIVE (read only, pc_get_option): 1 when the CG SpMV
+ *   of the last solve read 16-bit column offsets, else 0. */
 typedef enum { PC_OPT_GRAPH_CHUNK = 0, PC_OPT_SPMV_SLICES_PER_BLOCK = 1, PC_OPT_VECTOR_ROWS_PER_BLOCK = 2,
-               PC_OPT_LDS_WINDOW = 3, PC_OPT_NARROW_COLUMNS = 4 } pc_option;
+               PC_OPT_LDS_WINDOW = 3, PC_OPT_NARROW_COLUMNS = 4, PC_OPT_SPMV_NARROW_ACTIVE = 5 } pc_option;
 pc_status pc_set_option(pc_ctx *ctx, int32_t option, int64_t value);
 pc_status pc_get_option(pc_ctx *ctx, int32_t option, int64_t *value);
 

@@ -28,14 +28,15 @@ ABI_SYMBOLS = ["pc_create", "pc_destroy", "pc_set_params", "pc_last_error", "pc_
                "cloth_export_pattern", "pc_check", "pc_profile", "pc_profile_read", "pc_set_option",
                "pc_ws_set_params", "pc_ws_get_params", "pc_ws_features", "pc_ws_predict", "pc_ws_gradient",
                "pc_ws_train_step", "pc_mfma_probe", "pc_get_option", "pc_set_instances", "pc_get_instance_info",
-               "pc_autotune", "cloth_export_precond", "pc_ws_start", "cloth_set_contacts"]
+               "pc_autotune", "cloth_export_precond", "pc_ws_start", "cloth_set_contacts",
+               "cloth_assemble_bell", "cloth_spmv_bell", "cloth_export_bell"]
 WS_PARAMS = 10307
 # Warm-start network layer shapes (inputs x outputs); the flat parameter
 # vector holds, per layer, W row-major then the bias.
 WS_SHAPES = [(27, 64), (64, 64), (64, 64), (64, 3)]
 WARM = {"zero": 0, "prev": 1, "given": 1, "learned": 2}
 PC_OPT_GRAPH_CHUNK, PC_OPT_SPMV_SLICES_PER_BLOCK, PC_OPT_VECTOR_ROWS_PER_BLOCK, PC_OPT_LDS_WINDOW, \
-    PC_OPT_NARROW_COLUMNS = 0, 1, 2, 3, 4
+    PC_OPT_NARROW_COLUMNS, PC_OPT_SPMV_NARROW_ACTIVE = 0, 1, 2, 3, 4, 5
 PROFILE_KINDS = ["spmv", "cg_update", "cg_dir", "row_assemble", "row_pattern", "assemble_all", "k6", "k7"]
 
 
@@ -109,6 +110,9 @@ def lib():
         L.cloth_export_precond.argtypes = [vp, vp, vp, vp]
         L.cloth_set_contacts.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_double, ctypes.c_double, vp]
         L.pc_check.argtypes = [vp, vp]
+        L.cloth_assemble_bell.argtypes = [vp, vp, vp, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_int32), vp]
+        L.cloth_spmv_bell.argtypes = [vp, vp, vp, vp]
+        L.cloth_export_bell.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), vp, vp, vp]
         L.cloth_export_pattern.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
         L.pc_profile.argtypes = [vp, ctypes.c_int32]
         L.pc_set_option.argtypes = [vp, ctypes.c_int32, ctypes.c_int64]
@@ -296,6 +300,35 @@ class Context:
         self._check(lib().cloth_export_precond(self.h, _ptr(dinv), _ptr(b6), _stream()))
         idx = [0, 1, 2, 1, 3, 4, 2, 4, 5]
         return dinv, b6[:, idx].reshape(self.nv, 3, 3)
+
+    def cloth_assemble_bell(self, x, v, dtype="f32", b=None):
+        """The paper's five-step filling into a BELL table: returns (b, width)."""
+        import torch
+        dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        if b is None:
+            b = torch.empty((self.nv, 3), dtype=torch.float64, device="cuda")
+        w = ctypes.c_int32(0)
+        self._check(lib().cloth_assemble_bell(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"), dt,
+                                              _dev3(b, self.nv, "b"), ctypes.byref(w), _stream()))
+        return b, int(w.value)
+
+    def cloth_spmv_bell(self, x, y=None):
+        import torch
+        if y is None:
+            y = torch.empty_like(x)
+        self._check(lib().cloth_spmv_bell(self.h, _dev3(x, self.nv, "x"), _dev3(y, self.nv, "y"), _stream()))
+        return y
+
+    def cloth_export_bell(self):
+        """(cols (width, nv) int32, vals (9, width, nv) float64) on the device."""
+        import torch
+        w = ctypes.c_int32(0)
+        self._check(lib().cloth_export_bell(self.h, ctypes.byref(w), None, None, _stream()))
+        width = int(w.value)
+        cols = torch.empty((width, self.nv), dtype=torch.int32, device="cuda")
+        vals = torch.empty((9, width, self.nv), dtype=torch.float64, device="cuda")
+        self._check(lib().cloth_export_bell(self.h, None, _ptr(cols), _ptr(vals), _stream()))
+        return cols, vals
 
     def cloth_export_blocks(self, with_D=True, solver_blocks=False):
         import torch

@@ -73,6 +73,7 @@ static void free_all(Ctx *c) {
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->restart_h) (void)hipHostFree(c->restart_h);
     if (c->status_host) (void)hipHostFree(c->status_host);
+    bell_free(c->bell);
 }
 
 extern "C" {
@@ -298,6 +299,9 @@ pc_status pc_get_option(pc_ctx *h, int32_t option, int64_t *value) {
         case PC_OPT_VECTOR_ROWS_PER_BLOCK: *value = ctx->rpb; return PC_OK;
         case PC_OPT_LDS_WINDOW: *value = ctx->use_win ? 1 : 0; return PC_OK;
         case PC_OPT_NARROW_COLUMNS: *value = ctx->use_narrow ? 1 : 0; return PC_OK;
+        case PC_OPT_SPMV_NARROW_ACTIVE:
+            *value = (ctx->use_narrow && ctx->narrow && ctx->win_valid) ? 1 : 0;
+            return PC_OK;
         default: ctx->err = "unknown option"; return PC_ERR_ARG;
     }
 }
@@ -607,6 +611,29 @@ pc_status cloth_export_pattern(pc_ctx *h, int32_t *rowptr_out, int32_t *colidx_o
 pc_status cloth_export_blocks(pc_ctx *h, double *vals_out, double *D_out, int32_t solver_blocks, void *stream) {
     if (!h || !vals_out) return PC_ERR_ARG;
     return export_blocks(&h->c, vals_out, D_out, solver_blocks != 0, (hipStream_t)stream);
+}
+
+pc_status cloth_assemble_bell(pc_ctx *h, const double *x, const double *v, pc_dtype dtype, double *b,
+                              int32_t *width_out, void *stream) {
+    if (!h) return PC_ERR_ARG;
+    Ctx *ctx = &h->c;
+    if (!x || !v || !b) { ctx->err = "cloth_assemble_bell: x, v and b must be device pointers"; return PC_ERR_ARG; }
+    pc_status st = bell_assemble(ctx, x, v, dtype, b, (hipStream_t)stream);
+    if (st) return st;
+    if ((st = pc_check(h, stream))) return st;
+    if (width_out) *width_out = ctx->bell.Wv;
+    return PC_OK;
+}
+
+pc_status cloth_spmv_bell(pc_ctx *h, const double *x, double *y, void *stream) {
+    if (!h) return PC_ERR_ARG;
+    if (!x || !y) { h->c.err = "cloth_spmv_bell: x and y must be device pointers"; return PC_ERR_ARG; }
+    return bell_spmv(&h->c, x, y, (hipStream_t)stream);
+}
+
+pc_status cloth_export_bell(pc_ctx *h, int32_t *width_out, int32_t *cols_out, double *vals_out, void *stream) {
+    if (!h) return PC_ERR_ARG;
+    return bell_export(&h->c, width_out, cols_out, vals_out, (hipStream_t)stream);
 }
 
 pc_status cloth_set_contacts(pc_ctx *h, int32_t ncontacts, const int32_t *verts, const double *weights,

@@ -100,6 +100,23 @@ struct Prof {
 
 struct MlpState;
 
+// The paper's sparse-matrix filling and BELL layout (built beside the
+// solver's assembly for comparison): index table (nv x Wi), compacted
+// column table and value planes (slot k of row i at k nv + i).
+struct BellState {
+    int *cnt = nullptr;     // nv + 4: slot counts / fill pointers, then the two widths
+    int *len = nullptr;     // nv: compacted row lengths
+    double *f = nullptr;    // 6 nv: element forces, then c K v
+    int *idx = nullptr;     // nv x Wi index table
+    int *col = nullptr;     // Wv x nv columns
+    void *val = nullptr;    // 9 x Wv x nv values (FP32 or FP64)
+    float4 *x4 = nullptr;   // nv: SpMV input as float4
+    size_t cnt_bytes = 0, len_bytes = 0, f_bytes = 0, idx_bytes = 0, col_bytes = 0, val_bytes = 0;
+    int Wi = 0, Wv = 0;
+    pc_dtype dtype = PC_F32;
+    bool valid = false;
+};
+
 struct Ctx {
     std::string err;
     Prof prof;
@@ -218,6 +235,8 @@ struct Ctx {
     bool win_valid = false;
     bool use_win = true;          // PC_OPT_LDS_WINDOW
     int win_cap = 0;              // LDS window rows of the SpMV launches (0: global gathers)
+
+    BellState bell;
 };
 
 // Error helpers (host)
@@ -244,6 +263,10 @@ pc_status dev_alloc(Ctx *ctx, void **p, size_t bytes);
 pc_status read_status(Ctx *ctx, hipStream_t s, int *bits);
 pc_status build_schedule(Ctx *ctx);
 pc_status check_contacts(Ctx *ctx, int nc, int *bad, hipStream_t s);
+pc_status bell_assemble(Ctx *ctx, const double *x, const double *v, pc_dtype dtype, double *b, hipStream_t s);
+pc_status bell_spmv(Ctx *ctx, const double *x, double *y, hipStream_t s);
+pc_status bell_export(Ctx *ctx, int32_t *width, int32_t *cols, double *vals, hipStream_t s);
+void bell_free(BellState &Bs);
 pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, float *best_ms, hipStream_t s);
 
 }  // namespace pc
