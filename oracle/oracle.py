@@ -336,18 +336,20 @@ class Problem:
                       _p(x, _f64p), _p(y, _f64p))
         return y
 
-    def pcg(self, A: Assembled, x0=None, tol=1e-8, maxit=20000, precond="jacobi"):
+    def pcg(self, A: Assembled, x0=None, tol=1e-8, maxit=20000, precond="jacobi", method="cg"):
         """Preconditioned CG: precond "jacobi" (diag(A)) or "block" (the 3x3
-        diagonal blocks of A)."""
+        diagonal blocks of A); method "cg" (the textbook recurrences) or
+        "chronopoulos-gear" (one fused reduction per iteration)."""
         x = np.zeros((self.nv, 3)) if x0 is None else _f64(x0).copy()
-        out = np.zeros(3)
+        out = np.zeros(4)
         vals = _f64(A.vals)
         pre = {"jacobi": 0, "block": 1}[precond]
-        st = lib().or_pcg2(self.nv, _p(A.rowptr, _i32p), _p(A.colidx, _i32p), _p(vals, _f64p),
-                           _p(A.b, _f64p), _p(A.diag, _f64p), _p(x, _f64p), ctypes.c_double(tol),
-                           int(maxit), int(pre), _p(out, _f64p))
+        fn = {"cg": lib().or_pcg2, "chronopoulos-gear": lib().or_pcg_cg}[method]
+        st = fn(self.nv, _p(A.rowptr, _i32p), _p(A.colidx, _i32p), _p(vals, _f64p),
+                _p(A.b, _f64p), _p(A.diag, _f64p), _p(x, _f64p), ctypes.c_double(tol),
+                int(maxit), int(pre), _p(out, _f64p))
         return x, {"converged": st == 0, "iters": int(out[0]), "rel_res_recursive": out[1],
-                   "rel_res_true": out[2]}
+                   "rel_res_true": out[2], "breakdown": bool(out[3])}
 
     def pcg_fixed(self, A: Assembled, iters: int):
         x = np.zeros((self.nv, 3))

@@ -764,6 +764,70 @@ int or_pcg2(int nv, const int32_t *rowptr, const int32_t *colidx, const double *
     return sqrt(rr) <= tol * bnorm ? 0 : 1;
 }
 
+/* Preconditioned CG in the single-reduction form of Chronopoulos and Gear
+ * ("s-step iterative methods for symmetric linear systems", 1989, the s = 1
+ * case).  Each iteration takes one product w = A u of the preconditioned
+ * residual u = P^-1 r and the two dots gamma = r.u and delta = w.u together;
+ * the direction p and s = A p follow from recurrences:
+ *   beta_k  = gamma_k / gamma_{k-1}                 (beta_0 = 0)
+ *   alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1})
+ *   p_k = u_k + beta_k p_{k-1},   s_k = w_k + beta_k s_{k-1}
+ *   x_{k+1} = x_k + alpha_k p_k,  r_{k+1} = r_k - alpha_k s_k.
+ * In exact arithmetic the iterates are those of or_pcg2 (alpha_k, beta_k
+ * are the same numbers: delta_k - beta_k gamma_k / alpha_{k-1} = p_k.A p_k).
+ * Same preconditioners, stopping rule, outputs and return value as or_pcg2;
+ * out[3] = 1 if a denominator was not positive (breakdown), else 0. */
+int or_pcg_cg(int nv, const int32_t *rowptr, const int32_t *colidx, const double *vals,
+              const double *b, const double *diag, double *x, double tol, int maxit, int precond, double *out) {
+    int n = 3 * nv;
+    double bnorm = sqrt(dotn(n, b, b));
+    out[3] = 0.0;
+    if (bnorm == 0.0) {
+        memset(x, 0, sizeof(double) * n);
+        out[0] = 0; out[1] = 0.0; out[2] = 0.0;
+        return 0;
+    }
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *u = (double *)malloc(sizeof(double) * n);
+    double *w = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)calloc(n, sizeof(double));
+    double *s = (double *)calloc(n, sizeof(double));
+    block_spmv(nv, rowptr, colidx, vals, x, w);
+    for (int i = 0; i < n; ++i) r[i] = b[i] - w[i];
+    apply_precond(nv, rowptr, colidx, vals, diag, precond, r, u);
+    double rr = dotn(n, r, r);
+    double gamma_prev = 0.0, alpha_prev = 0.0;
+    int it = 0;
+    while (sqrt(rr) > tol * bnorm && it < maxit) {
+        block_spmv(nv, rowptr, colidx, vals, u, w);
+        double gamma = dotn(n, r, u);
+        double delta = dotn(n, w, u);
+        double beta = it == 0 ? 0.0 : gamma / gamma_prev;
+        double den = it == 0 ? delta : delta - beta * gamma / alpha_prev;
+        if (!(den > 0.0)) { out[3] = 1.0; break; }
+        double alpha = gamma / den;
+        for (int i = 0; i < n; ++i) {
+            p[i] = u[i] + beta * p[i];
+            s[i] = w[i] + beta * s[i];
+            x[i] += alpha * p[i];
+            r[i] -= alpha * s[i];
+        }
+        apply_precond(nv, rowptr, colidx, vals, diag, precond, r, u);
+        rr = dotn(n, r, r);
+        gamma_prev = gamma;
+        alpha_prev = alpha;
+        ++it;
+    }
+    block_spmv(nv, rowptr, colidx, vals, x, w);
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i) tr += (b[i] - w[i]) * (b[i] - w[i]);
+    out[0] = it;
+    out[1] = sqrt(rr) / bnorm;
+    out[2] = sqrt(tr) / bnorm;
+    free(r); free(u); free(w); free(p); free(s);
+    return sqrt(rr) <= tol * bnorm ? 0 : 1;
+}
+
 /* Jacobi-preconditioned CG (or_pcg2 with precond 0). */
 int or_pcg(int nv, const int32_t *rowptr, const int32_t *colidx, const double *vals,
            const double *b, const double *diag, double *x, double tol, int maxit, double *out) {
