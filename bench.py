@@ -85,10 +85,11 @@ def cpu_baseline(cloth, gpu_iters_per_step, seconds_budget=25.0, contacts=None):
                        f"same tolerance")}
 
 
-def time_steps(ctx, x, v, steps, warmup, blocks, tol, warm, prof_every, precond="jacobi", inner_rho=0.0):
+def time_steps(ctx, x, v, steps, warmup, blocks, tol, warm, prof_every, precond="jacobi", inner_rho=0.0,
+               method="cg"):
     """Run warmup then timed steps; returns (elapsed s, infos, profile)."""
     import torch
-    kw = dict(dtype=blocks, tol=tol, warm=warm, precond=precond, inner_rho=inner_rho)
+    kw = dict(dtype=blocks, tol=tol, warm=warm, precond=precond, inner_rho=inner_rho, method=method)
     if warmup:
         ctx.cloth_step(x, v, nsteps=warmup, **kw)
     ctx.profile(prof_every)
@@ -196,6 +197,8 @@ def main():
                     help="large: 3 stacked sheets, 1.65M triangles (the headline); batch: 64 uneven "
                          "independent sheets, ~1.5M triangles in one launch; contact: 2 sheets 1.5 mm "
                          "apart with 274K vertex-face proximity pairs in the assembly")
+    ap.add_argument("--method", default="cg", choices=["cg", "chronopoulos-gear"],
+                    help="CG form of the project configuration: textbook recurrences or single reduction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 / Jacobi / zero-start run")
     ap.add_argument("--prof-every", type=int, default=8)
@@ -259,7 +262,7 @@ def main():
         tune = ctx.autotune(b, iters=64, precond=args.precond)
         log(f"# autotune: {tune}")
     el, infos, prof = time_steps(ctx, x, v, args.steps, args.warmup, args.blocks, tol, args.warm, args.prof_every,
-                                 args.precond, args.inner_rho)
+                                 args.precond, args.inner_rho, args.method)
     rowptr, colidx = ctx.pattern()
     nnzb = int(colidx.numel())
     nv, nt, nh = ctx.nv, ctx.nt, ctx.nh
@@ -276,14 +279,14 @@ def main():
     # system is solved from each start to the same tolerance
     v_before = v.clone()
     ctx.cloth_step(x, v, nsteps=1, dtype=args.blocks, tol=tol, warm=args.warm, precond=args.precond,
-                   inner_rho=args.inner_rho)
+                   inner_rho=args.inner_rho, method=args.method)
     dv_prev = v - v_before
     b = ctx.cloth_assemble(x, v, args.blocks)
     paired = {}
     for mode in (["zero", "prev"] + (["learned"] if params is not None else [])):
         dv0 = torch.zeros_like(x) if mode == "zero" else dv_prev.clone()
         _, pinfo = ctx.cloth_pcg_solve(b, dv=dv0, tol=tol, warm=mode, precond=args.precond,
-                                       inner_rho=args.inner_rho)
+                                       inner_rho=args.inner_rho, method=args.method)
         paired[mode] = {"iters": pinfo["iters"], "start_used": pinfo["warm_used"],
                         "rel_res_true": pinfo["rel_res_true"]}
     log(f"# paired starts on one system: {paired}")
@@ -313,7 +316,7 @@ def main():
                         + ("" if contacts is None else f", {contacts.n} proximity pairs"),
             "h": cloth.h, "tol": tol, "block_storage": args.blocks, "warm_start": args.warm,
             "refinement_sweeps": [i["sweeps"] for i in infos], "starts_used": [i["warm_used"] for i in infos],
-            "preconditioner": args.precond, "inner_rho": args.inner_rho,
+            "preconditioner": args.precond, "inner_rho": args.inner_rho, "cg_form": args.method,
             "cg_iters_per_step": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
             "rel_res_true_max": max(i["rel_res_true"] for i in infos),
             "schedule": tune,

@@ -105,7 +105,11 @@ typedef struct {
     int32_t precond;       /* 0: Jacobi, P = diag(A) (the paper's preconditioner, Sec. 2.5);
                               1: block Jacobi, P = the 3x3 diagonal blocks A_ii, inverted in
                               FP64 at assembly and applied in FP32 x FP64 */
-    int32_t reserved;      /* set to 0 */
+    int32_t method;        /* 0: the textbook PCG recurrences (two reductions per iteration);
+                              1: the single-reduction form of Chronopoulos and Gear (1989):
+                              gamma = r.u and delta = u.Au from one product per iteration,
+                              the direction and its product by recurrences (project solver
+                              variant; same iterates in exact arithmetic) */
 } pc_solve_opts;
 
 typedef struct {

@@ -35,6 +35,7 @@ WS_PARAMS = 10307
 # vector holds, per layer, W row-major then the bias.
 WS_SHAPES = [(27, 64), (64, 64), (64, 64), (64, 3)]
 WARM = {"zero": 0, "prev": 1, "given": 1, "learned": 2}
+METHOD = {"cg": 0, "chronopoulos-gear": 1}
 PC_OPT_GRAPH_CHUNK, PC_OPT_SPMV_SLICES_PER_BLOCK, PC_OPT_VECTOR_ROWS_PER_BLOCK, PC_OPT_LDS_WINDOW, \
     PC_OPT_NARROW_COLUMNS, PC_OPT_SPMV_NARROW_ACTIVE = 0, 1, 2, 3, 4, 5
 PROFILE_KINDS = ["spmv", "cg_update", "cg_dir", "row_assemble", "row_pattern", "assemble_all", "k6", "k7"]
@@ -60,16 +61,18 @@ class PcBsr3(ctypes.Structure):
 class PcSolveOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("inner_rho", ctypes.c_double), ("maxit", ctypes.c_int32),
                 ("warm", ctypes.c_int32), ("check_every", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 PRECOND = {"jacobi": 0, "block": 1}
 
 
-def solve_opts(tol=1e-6, maxit=20000, warm=False, check_every=0, inner_rho=0.0, max_sweeps=0, precond="jacobi"):
+def solve_opts(tol=1e-6, maxit=20000, warm=False, check_every=0, inner_rho=0.0, max_sweeps=0, precond="jacobi",
+               method="cg"):
     w = WARM[warm] if isinstance(warm, str) else int(warm)
     pre = PRECOND[precond] if isinstance(precond, str) else int(precond)
-    return PcSolveOpts(float(tol), float(inner_rho), int(maxit), w, int(check_every), int(max_sweeps), pre, 0)
+    m = METHOD[method] if isinstance(method, str) else int(method)
+    return PcSolveOpts(float(tol), float(inner_rho), int(maxit), w, int(check_every), int(max_sweeps), pre, m)
 
 
 class PcSolveInfo(ctypes.Structure):
@@ -253,11 +256,11 @@ class Context:
         return rowptr, colidx[:n.value]
 
     def cloth_pcg_solve(self, b, dv=None, tol=1e-6, maxit=20000, warm=False, check_every=0, raise_on_error=True,
-                        inner_rho=0.0, max_sweeps=0, precond="jacobi"):
+                        inner_rho=0.0, max_sweeps=0, precond="jacobi", method="cg"):
         import torch
         if dv is None:
             dv = torch.zeros((self.nv, 3), dtype=torch.float64, device=b.device)
-        o = solve_opts(tol, maxit, warm, check_every, inner_rho, max_sweeps, precond)
+        o = solve_opts(tol, maxit, warm, check_every, inner_rho, max_sweeps, precond, method)
         info = PcSolveInfo()
         st = lib().cloth_pcg_solve(self.h, _dev3(b, self.nv, "b"), _dev3(dv, self.nv, "dv"), ctypes.byref(o),
                                    ctypes.byref(info), _stream())
@@ -340,9 +343,9 @@ class Context:
         return rowptr, colidx, vals, D
 
     def cloth_step(self, x, v, nsteps=1, dtype="f32", tol=1e-6, maxit=20000, warm=False, check_every=0,
-                   inner_rho=0.0, max_sweeps=0, precond="jacobi"):
+                   inner_rho=0.0, max_sweeps=0, precond="jacobi", method="cg"):
         dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
-        o = solve_opts(tol, maxit, warm, check_every, inner_rho, max_sweeps, precond)
+        o = solve_opts(tol, maxit, warm, check_every, inner_rho, max_sweeps, precond, method)
         infos = (PcSolveInfo * max(1, nsteps))()
         st = lib().cloth_step(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"), int(nsteps), dt,
                               ctypes.byref(o), infos, _stream())

@@ -66,7 +66,7 @@ static void free_all(Ctx *c) {
     void *ptrs[] = {c->tri, c->Bm, c->A0, c->hinge, c->hcoef, c->htbar, c->mass, c->pinned, c->status,
                     c->inc_cnt, c->inc_ptr, c->inc, c->rowlen, c->rowptr, c->colidx, c->jcol, c->lane_row,
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
-                    c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn, c->jdel,
+                    c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn, c->jdel, c->cg_pd, c->cg_s,
                     c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -310,6 +310,7 @@ pc_status pc_autotune(pc_ctx *h, const double *b, int32_t iters, int32_t precond
                       double *ms_per_iter, void *stream) {
     if (!h || !b || iters < 1 || precond < 0 || precond > 1) return PC_ERR_ARG;
     h->c.precond = precond;
+    h->c.method = 0;   // the schedule is timed on the textbook iteration
     float ms = 0.0f;
     pc_status st = autotune_run(&h->c, b, iters, chosen, &ms, (hipStream_t)stream);
     if (ms_per_iter) *ms_per_iter = ms;
@@ -565,7 +566,7 @@ pc_status pc_check(pc_ctx *h, void *stream) {
 
 static bool opts_ok(Ctx *ctx, const pc_solve_opts *o) {
     if (o && (!(o->tol >= 0.0) || o->warm < 0 || o->warm > 2 || !(o->inner_rho >= 0.0) || o->inner_rho >= 1.0 ||
-              o->precond < 0 || o->precond > 1)) {
+              o->precond < 0 || o->precond > 1 || o->method < 0 || o->method > 1)) {
         ctx->err = "bad solve options";
         return false;
     }

@@ -21,7 +21,11 @@ struct PcgState {
     double rho2;     // inner reduction factor squared (refinement sweeps)
     double thresh;   // stop when ||r||^2 <= thresh = max(tol^2 ||b||^2, rho^2 ||r_0||^2)
     double rr0;      // ||r_0||^2 of this sweep
+    // single-reduction (Chronopoulos-Gear) form: beta of the iteration being
+    // applied, gamma and alpha of the previous one
+    double beta, gprev, aprev;
     int iters, maxit, done, flags;   // flags: 1 breakdown (p.Ap <= 0), 2 non-finite
+    int kc, pad_;                    // iterations of the current sweep (single-reduction form)
 };
 
 // Sampled kernel timing with HIP events on the launch stream: every
@@ -203,6 +207,9 @@ struct Ctx {
     float4 *p = nullptr;
     float4 *zb = nullptr;         // preconditioned residual (block Jacobi)
     int precond = 0;              // preconditioner of the current / last solve
+    int method = 0;               // 0 textbook PCG, 1 single-reduction (Chronopoulos-Gear) form
+    double *cg_pd = nullptr;      // nv * 3: direction of the single-reduction form (FP64)
+    double *cg_s = nullptr;       // nv * 3: its product s = A p, by recurrence
     double *partials = nullptr;   // per-block partial sums (4 doubles per block): SpMV, starts, checks
     double *partials_u = nullptr; // per-block partial sums of the CG update (2 doubles per block)
     int cg_par = 0;               // parity of the next CG iteration launched
@@ -228,6 +235,7 @@ struct Ctx {
     int gkey_pre[2] = {-1, -1};
     int gkey_win[2] = {-1, -1};
     int gkey_narrow[2] = {-1, -1};
+    int gkey_method[2] = {-1, -1};
 
     // column windows of the SpMV work items (p staged in LDS)
     int2 *sitem_win = nullptr;

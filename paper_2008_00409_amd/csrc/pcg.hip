@@ -237,7 +237,7 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *partials
 }
 
 // Sum of partials[q][i0..i1) in a fixed order, valid in every thread of the
-// (256-thread) block.
+// block (up to 1024 threads).
 template <int NV>
 __device__ __forceinline__ void instance_sum(const double *partials, int nitems, int i0, int i1, double (&tot)[NV]) {
     __shared__ double sh[NV][16];
@@ -275,6 +275,8 @@ __global__ void k_state_init(int ninst, PcgState *st, const uint8_t *restart, do
     S.thresh = 0.0;
     S.rr0 = 0.0;
     S.rz0 = 0.0;
+    S.beta = S.gprev = S.aprev = 0.0;
+    S.kc = 0;
     S.iters = 0;
     S.maxit = maxit[i];
     S.done = 0;
@@ -472,6 +474,113 @@ __global__ void __launch_bounds__(256) k_pcg_dir(Sched S, int par, const double 
         o.w = 0.0f;
         p[i] = o;
     }
+}
+
+// ---- single-reduction form (Chronopoulos and Gear, 1989; s = 1) ----
+// Iteration k: w = A u_k (the SpMV above, with u_k in the float4 buffer
+// and partials of delta_k = u_k.w), then one block per instance sums
+// delta_k and the vector kernel's partials of gamma_k = r_k.z_k and
+// ||r_k||^2 (z = P^-1 r before rounding; at k = 0 the sweep start's values),
+// tests convergence, and forms
+//   beta_k = gamma_k / gamma_{k-1} (0 at k = 0),
+//   alpha_k = gamma_k / (delta_k - beta_k gamma_k / alpha_{k-1}),
+// which equals gamma_k / p_k.A p_k in exact arithmetic; a non-positive
+// denominator ends the sweep as a breakdown.
+__global__ void __launch_bounds__(1024) k_fin_cgcg(Sched S, const double *partials, const double *part_u,
+                                                  PcgState *st) {
+    const int inst = blockIdx.x;
+    if (inst >= S.ninst || st[inst].done) return;
+    double d[1], gu[2];
+    instance_sum<1>(partials, S.n_sitems, S.inst_sitem0[inst], S.inst_sitem0[inst + 1], d);
+    instance_sum<2>(part_u, S.n_vitems, S.inst_vitem0[inst], S.inst_vitem0[inst + 1], gu);
+    if (threadIdx.x != 0) return;
+    PcgState &T = st[inst];
+    double gamma;
+    if (T.kc == 0) {
+        gamma = T.rz0;
+    } else {
+        gamma = gu[0];
+        T.rr = gu[1];
+        if (!isfinite(gu[0]) || !isfinite(gu[1])) {
+            T.flags |= 2;
+            T.done = 1;
+            return;
+        }
+        if (gu[1] <= T.thresh) {
+            T.done = 1;
+            return;
+        }
+    }
+    if (T.iters >= T.maxit) {
+        T.done = 1;
+        return;
+    }
+    const double beta = T.kc == 0 ? 0.0 : gamma / T.gprev;
+    const double den = T.kc == 0 ? d[0] : d[0] - beta * gamma / T.aprev;
+    const double a = gamma / den;
+    if (!(den > 0.0) || !isfinite(a)) {
+        T.flags |= isfinite(den) ? 1 : 2;
+        T.done = 1;
+        return;
+    }
+    T.alpha = a;
+    T.beta = beta;
+    T.gprev = gamma;
+    T.aprev = a;
+    T.kc += 1;
+    T.iters += 1;
+}
+
+// p = u + beta p, s = w + beta s (p = u, s = w in the first iteration of a
+// sweep), x += alpha p, r -= alpha s over the item's rows with flat
+// component indexing (consecutive threads touch consecutive 8-byte
+// elements), each 256-row chunk of the new r staged in LDS; then one thread
+// per row forms u = P^-1 r, stores it as float4 for the next product and
+// adds to the partials of r.u (with the stored, rounded u, the vector the
+// product and the direction use) and ||r||^2.
+__global__ void __launch_bounds__(256) k_cgcg_vec(Sched S, double *x, double *r, float4 *u, const double *w,
+                                                  double *pd, double *sv, PreArgs P, const PcgState *st,
+                                                  double *part_u) {
+    __shared__ double rs[3 * 256];
+    const int it = item_of_block(S.n_vitems);
+    if (it < 0) return;
+    const int4 I = S.vitem[it];
+    const PcgState &T = st[I.x];
+    if (T.done) return;
+    const double alpha = T.alpha, beta = T.beta;
+    const bool first = T.kc == 1;
+    const float *uf = (const float *)u;
+    double gz = 0.0, rr = 0.0;
+    for (int r0 = I.y; r0 < I.z; r0 += 256) {
+        const int nr = min(256, I.z - r0);
+        for (int k = threadIdx.x; k < 3 * nr; k += blockDim.x) {
+            const int64_t kk = 3 * (int64_t)r0 + k;
+            const int i = (int)(kk / 3);
+            const double uk = uf[4 * (int64_t)i + (kk - 3 * (int64_t)i)];
+            const double pk = first ? uk : uk + beta * pd[kk];
+            const double sk = first ? w[kk] : w[kk] + beta * sv[kk];
+            pd[kk] = pk;
+            sv[kk] = sk;
+            x[kk] += alpha * pk;
+            const double rk = r[kk] - alpha * sk;
+            r[kk] = rk;
+            rs[k] = rk;
+            rr += rk * rk;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nr) {
+            const int t = threadIdx.x, i = r0 + t;
+            const double a0 = rs[3 * t], a1 = rs[3 * t + 1], a2 = rs[3 * t + 2];
+            double z[3];
+            precond3(P, i, a0, a1, a2, z);
+            const float4 zf = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
+            gz += a0 * (double)zf.x + a1 * (double)zf.y + a2 * (double)zf.z;
+            u[i] = zf;
+        }
+        __syncthreads();
+    }
+    double v[2] = {gz, rr};
+    block_partials<2>(v, part_u, it, S.n_vitems);
 }
 
 // Zero start of the flagged instances (all when restart == nullptr):
@@ -837,11 +946,40 @@ static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids
     ctx->prof.end(slot, s);
 }
 
+// One iteration of the single-reduction form: SpMV of u with partials of
+// u.w, the per-instance scalars, the fused vector update.
+template <typename TB>
+static void launch_iter_cgcg(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s) {
+    int slot = ctx->prof.begin(PK_SPMV, s);
+    if (ctx->narrow && M.jdel)
+        hipLaunchKernelGGL((k_pcg_spmv<TB, true>), dim3(g.sblocks), dim3(g.sthreads),
+                           sizeof(float4) * (size_t)ctx->win_cap, s, M, S, ctx->p, ctx->q, ctx->st, ctx->partials,
+                           ctx->sitem_win, ctx->win_cap);
+    else
+        hipLaunchKernelGGL((k_pcg_spmv<TB, false>), dim3(g.sblocks), dim3(g.sthreads),
+                           sizeof(float4) * (size_t)ctx->win_cap, s, M, S, ctx->p, ctx->q, ctx->st, ctx->partials,
+                           ctx->sitem_win, ctx->win_cap);
+    ctx->prof.end(slot, s);
+    hipLaunchKernelGGL(k_fin_cgcg, dim3(ctx->ninst), dim3(1024), 0, s, S, ctx->partials, ctx->partials_u, ctx->st);
+    slot = ctx->prof.begin(PK_UPDATE, s);
+    hipLaunchKernelGGL(k_cgcg_vec, dim3(g.vblocks), dim3(256), 0, s, S, ctx->x, ctx->r, ctx->p, ctx->q, ctx->cg_pd,
+                       ctx->cg_s, pre_args(ctx), ctx->st, ctx->partials_u);
+    ctx->prof.end(slot, s);
+}
+
+template <typename TB>
+static void launch_one(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s, int par) {
+    if (ctx->method == 1)
+        launch_iter_cgcg<TB>(ctx, M, S, g, s);
+    else
+        launch_iter<TB>(ctx, M, S, g, s, par);
+}
+
 // Plain launches of n iterations continuing the context's parity.
 template <typename TB>
 static void launch_iters(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s, int n) {
     for (int c = 0; c < n; ++c) {
-        launch_iter<TB>(ctx, M, S, g, s, ctx->cg_par);
+        launch_one<TB>(ctx, M, S, g, s, ctx->cg_par);
         ctx->cg_par ^= 1;
     }
 }
@@ -876,7 +1014,7 @@ static bool graph_stale(const Ctx *ctx, int variant, const SpmvArgs &M, int elem
     return !ctx->gexec[variant] || ctx->gkey[variant] != M.jval || ctx->gkey_dtype[variant] != elem_size ||
            ctx->gkey_chunk[variant] != ctx->graph_chunk || ctx->gkey_sched[variant] != ctx->sched_version ||
            ctx->gkey_pre[variant] != ctx->precond || ctx->gkey_win[variant] != ctx->win_cap ||
-           ctx->gkey_narrow[variant] != (int)ctx->narrow;
+           ctx->gkey_narrow[variant] != (int)ctx->narrow || ctx->gkey_method[variant] != ctx->method;
 }
 
 // Capture `chunk` (even) iterations on the context's capture stream; the
@@ -894,7 +1032,7 @@ static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Sched &S, cons
     ctx->prof.every = 0;  // no profiler events inside the graph
     hipStream_t cs = ctx->cap_stream;
     PC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    for (int c = 0; c < chunk; ++c) launch_iter<TB>(ctx, M, S, g, cs, c & 1);
+    for (int c = 0; c < chunk; ++c) launch_one<TB>(ctx, M, S, g, cs, c & 1);
     hipGraph_t graph = nullptr;
     hipError_t ec = hipStreamEndCapture(cs, &graph);
     ctx->prof.every = saved;
@@ -916,6 +1054,7 @@ static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Sched &S, cons
     ctx->gkey_pre[variant] = ctx->precond;
     ctx->gkey_win[variant] = ctx->win_cap;
     ctx->gkey_narrow[variant] = (int)ctx->narrow;
+    ctx->gkey_method[variant] = ctx->method;
     return PC_OK;
 }
 
@@ -1268,6 +1407,12 @@ pc_status pcg_run(Ctx *ctx, const double *b, double *dv, const pc_solve_opts *o,
         return PC_ERR_ARG;
     }
     ctx->precond = o ? o->precond : 0;
+    ctx->method = o ? o->method : 0;
+    if (ctx->method == 1 && !ctx->cg_pd) {
+        pc_status st = dev_alloc(ctx, (void **)&ctx->cg_pd, sizeof(double) * 3 * (size_t)ctx->nv);
+        if (st) return st;
+        if ((st = dev_alloc(ctx, (void **)&ctx->cg_s, sizeof(double) * 3 * (size_t)ctx->nv))) return st;
+    }
     switch (ctx->dtype) {
         case PC_F64: return pcg_typed<double>(ctx, b, dv, o, info, s);
         case PC_F32: return pcg_typed<float>(ctx, b, dv, o, info, s);
