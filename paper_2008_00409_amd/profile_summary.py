@@ -22,7 +22,7 @@ import statistics
 HERE = os.path.dirname(os.path.abspath(__file__))
 # Sources the SpMV kernel is built from: a traffic figure stays valid only
 # while they are unchanged.
-SPMV_SOURCES = ["csrc/pcg.hip", "csrc/pc_common.h"]
+SPMV_SOURCES = ["csrc/pc_spmv.h", "csrc/pc_common.h"]
 
 
 def spmv_source_hash() -> str:
