@@ -325,9 +325,16 @@ pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
  *   order), the CG SpMV reads 16-bit column offsets instead of 32-bit
  *   columns; 0: always 32-bit.  Results do not change.
  * PC_OPT_SPMV_NARROW_ACTIVE (read only, pc_get_option): 1 when the CG SpMV
- *   of the last solve read 16-bit column offsets, else 0. */
+ *   of the last solve read 16-bit column offsets, else 0.
+ * PC_OPT_INNER_FP32: 1 (default): with BF16 blocks and the textbook
+ *   recurrences, each refinement sweep solves for a correction e (x += e at
+ *   the sweep's end) with the correction, residual and product vectors in
+ *   FP32 (dots still accumulate in FP64; the sweep's start residual and the
+ *   convergence test use FP64 x and the FP64 blocks); 0: FP64 vectors.
+ *   Results change at the inner solves' rounding level only. */
 typedef enum { PC_OPT_GRAPH_CHUNK = 0, PC_OPT_SPMV_SLICES_PER_BLOCK = 1, PC_OPT_VECTOR_ROWS_PER_BLOCK = 2,
-               PC_OPT_LDS_WINDOW = 3, PC_OPT_NARROW_COLUMNS = 4, PC_OPT_SPMV_NARROW_ACTIVE = 5 } pc_option;
+               PC_OPT_LDS_WINDOW = 3, PC_OPT_NARROW_COLUMNS = 4, PC_OPT_SPMV_NARROW_ACTIVE = 5,
+               PC_OPT_INNER_FP32 = 6 } pc_option;
 pc_status pc_set_option(pc_ctx *ctx, int32_t option, int64_t value);
 pc_status pc_get_option(pc_ctx *ctx, int32_t option, int64_t *value);
 

@@ -66,7 +66,7 @@ static void free_all(Ctx *c) {
     void *ptrs[] = {c->tri, c->Bm, c->A0, c->hinge, c->hcoef, c->htbar, c->mass, c->pinned, c->status,
                     c->inc_cnt, c->inc_ptr, c->inc, c->rowlen, c->rowptr, c->colidx, c->jcol, c->lane_row,
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
-                    c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn, c->jdel, c->cg_pd, c->cg_s,
+                    c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn, c->jdel, c->cg_pd, c->cg_s, c->e32, c->r32, c->q32,
                     c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -262,6 +262,13 @@ pc_status pc_set_option(pc_ctx *h, int32_t option, int64_t value) {
             }
             ctx->use_narrow = value != 0;
             return PC_OK;
+        case PC_OPT_INNER_FP32:
+            if (value != 0 && value != 1) {
+                ctx->err = "inner FP32 option must be 0 or 1";
+                return PC_ERR_ARG;
+            }
+            ctx->use_inner32 = value != 0;
+            return PC_OK;
         case PC_OPT_SPMV_SLICES_PER_BLOCK: {
             if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16) {
                 ctx->err = "slices per block must be 1, 2, 4, 8 or 16";
@@ -302,6 +309,7 @@ pc_status pc_get_option(pc_ctx *h, int32_t option, int64_t *value) {
         case PC_OPT_SPMV_NARROW_ACTIVE:
             *value = (ctx->use_narrow && ctx->narrow && ctx->win_valid) ? 1 : 0;
             return PC_OK;
+        case PC_OPT_INNER_FP32: *value = ctx->use_inner32 ? 1 : 0; return PC_OK;
         default: ctx->err = "unknown option"; return PC_ERR_ARG;
     }
 }
@@ -311,6 +319,8 @@ pc_status pc_autotune(pc_ctx *h, const double *b, int32_t iters, int32_t precond
     if (!h || !b || iters < 1 || precond < 0 || precond > 1) return PC_ERR_ARG;
     h->c.precond = precond;
     h->c.method = 0;   // the schedule is timed on the textbook iteration
+    pc_status ist = set_inner_vectors(&h->c);
+    if (ist) return ist;
     float ms = 0.0f;
     pc_status st = autotune_run(&h->c, b, iters, chosen, &ms, (hipStream_t)stream);
     if (ms_per_iter) *ms_per_iter = ms;

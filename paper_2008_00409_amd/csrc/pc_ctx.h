@@ -210,6 +210,9 @@ struct Ctx {
     int method = 0;               // 0 textbook PCG, 1 single-reduction (Chronopoulos-Gear) form
     double *cg_pd = nullptr;      // nv * 3: direction of the single-reduction form (FP64)
     double *cg_s = nullptr;       // nv * 3: its product s = A p, by recurrence
+    bool inner32 = false;         // inner CG vectors (correction, residual, product) in FP32
+    bool use_inner32 = true;      // PC_OPT_INNER_FP32
+    float *e32 = nullptr, *r32 = nullptr, *q32 = nullptr;   // nv * 3 each
     double *partials = nullptr;   // per-block partial sums (4 doubles per block): SpMV, starts, checks
     double *partials_u = nullptr; // per-block partial sums of the CG update (2 doubles per block)
     int cg_par = 0;               // parity of the next CG iteration launched
@@ -236,6 +239,7 @@ struct Ctx {
     int gkey_win[2] = {-1, -1};
     int gkey_narrow[2] = {-1, -1};
     int gkey_method[2] = {-1, -1};
+    int gkey_inner32[2] = {-1, -1};
 
     // column windows of the SpMV work items (p staged in LDS)
     int2 *sitem_win = nullptr;
@@ -275,6 +279,7 @@ pc_status bell_assemble(Ctx *ctx, const double *x, const double *v, pc_dtype dty
 pc_status bell_spmv(Ctx *ctx, const double *x, double *y, hipStream_t s);
 pc_status bell_export(Ctx *ctx, int32_t *width, int32_t *cols, double *vals, hipStream_t s);
 void bell_free(BellState &Bs);
+pc_status set_inner_vectors(Ctx *ctx);
 pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, float *best_ms, hipStream_t s);
 
 }  // namespace pc

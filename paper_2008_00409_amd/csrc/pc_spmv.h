@@ -193,11 +193,11 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *partials
     }
 }
 
-// q = A p and per-item partials of p.q.  When the item's column window fits
+// q = A p (stored as TQ) and per-item partials of p.q.  When the item's column window fits
 // in win_cap rows, p[window] is first copied to LDS with coalesced loads and
 // the rows gather from there; otherwise they gather from global memory.
-template <typename TB, bool NARROW>
-__global__ void __launch_bounds__(1024) k_pcg_spmv(SpmvArgs M, Sched S, const float4 *p, double *q,
+template <typename TB, bool NARROW, typename TQ>
+__global__ void __launch_bounds__(1024) k_pcg_spmv(SpmvArgs M, Sched S, const float4 *p, TQ *q,
                                                   const PcgState *st, double *partials, const int2 *win,
                                                   int win_cap) {
     extern __shared__ float4 pwin[];
@@ -221,10 +221,13 @@ __global__ void __launch_bounds__(1024) k_pcg_spmv(SpmvArgs M, Sched S, const fl
         const int row = use_lds ? spmv_row<TB, VecLds, NARROW>(M, I.y + w, lane, VecLds{pwin, W.x}, y, xi)
                                 : spmv_row<TB, VecF4, NARROW>(M, I.y + w, lane, VecF4{p}, y, xi);
         if (row >= 0) {
-            q[3 * row] = y[0];
-            q[3 * row + 1] = y[1];
-            q[3 * row + 2] = y[2];
-            pq = xi[0] * y[0] + xi[1] * y[1] + xi[2] * y[2];
+            // q as stored (FP64, or FP32 for the inner vectors of a refinement
+            // sweep); p.q with the stored values, which the update uses
+            const TQ q0 = (TQ)y[0], q1 = (TQ)y[1], q2 = (TQ)y[2];
+            q[3 * row] = q0;
+            q[3 * row + 1] = q1;
+            q[3 * row + 2] = q2;
+            pq = xi[0] * (double)q0 + xi[1] * (double)q1 + xi[2] * (double)q2;
         }
     }
     double v[1] = {pq};

@@ -155,10 +155,12 @@ __global__ void __launch_bounds__(256) k_fin_alpha(Sched S, int par, const doubl
 }
 
 // x += alpha p, r -= alpha q over the item's rows (flat component indexing:
-// consecutive threads touch consecutive 8-byte elements); partials of r.z
-// (z = P^-1 r) and r.r.  Block Jacobi stages each 256-row chunk of r in LDS,
+// consecutive threads touch consecutive elements); partials of r.z
+// (z = P^-1 r) and r.r with r as stored.  TV: FP64 vectors, or FP32 for the
+// correction, residual and product inside a refinement sweep.  Block Jacobi stages each 256-row chunk of r in LDS,
 // then one thread per row applies the inverse block and stores z.
-__global__ void __launch_bounds__(256) k_pcg_update(Sched S, double *x, double *r, const float *pf, const double *q,
+template <typename TV>
+__global__ void __launch_bounds__(256) k_pcg_update(Sched S, TV *x, TV *r, const float *pf, const TV *q,
                                                     PreArgs P, const PcgState *st, double *part_u) {
     __shared__ double rs[3 * 256];
     const int it = item_of_block(S.n_vitems);
@@ -171,9 +173,10 @@ __global__ void __launch_bounds__(256) k_pcg_update(Sched S, double *x, double *
         for (int k = 3 * I.y + threadIdx.x; k < 3 * I.z; k += blockDim.x) {
             const int i = k / 3;
             const double pk = pf[4 * i + (k - 3 * i)];
-            x[k] += alpha * pk;
-            const double rk = r[k] - alpha * q[k];
-            r[k] = rk;
+            x[k] = (TV)((double)x[k] + alpha * pk);
+            const TV rv = (TV)((double)r[k] - alpha * (double)q[k]);
+            r[k] = rv;
+            const double rk = rv;
             rz += rk * rk * (double)P.dinv[k];
             rr += rk * rk;
         }
@@ -184,9 +187,10 @@ __global__ void __launch_bounds__(256) k_pcg_update(Sched S, double *x, double *
                 const int kk = 3 * r0 + k;
                 const int i = kk / 3;
                 const double pk = pf[4 * i + (kk - 3 * i)];
-                x[kk] += alpha * pk;
-                const double rk = r[kk] - alpha * q[kk];
-                r[kk] = rk;
+                x[kk] = (TV)((double)x[kk] + alpha * pk);
+                const TV rv = (TV)((double)r[kk] - alpha * (double)q[kk]);
+                r[kk] = rv;
+                const double rk = rv;
                 rs[k] = rk;
                 rr += rk * rk;
             }
@@ -212,7 +216,8 @@ __global__ void __launch_bounds__(256) k_pcg_update(Sched S, double *x, double *
 // instance advances the instance state: rzp[1 - par] = rz_new, ||r||^2, the
 // iteration count and the convergence test ||r||^2 <= thresh.  Blocks that
 // see the instance converged skip the direction (it is not used again).
-__global__ void __launch_bounds__(256) k_pcg_dir(Sched S, int par, const double *r, float4 *p, PreArgs P,
+template <typename TV>
+__global__ void __launch_bounds__(256) k_pcg_dir(Sched S, int par, const TV *r, float4 *p, PreArgs P,
                                                  PcgState *st, const double *part_u) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
@@ -240,9 +245,9 @@ __global__ void __launch_bounds__(256) k_pcg_dir(Sched S, int par, const double 
         const float4 pv = p[i];
         double z0, z1, z2;
         if (P.kind == 0) {
-            z0 = r[3 * i] * (double)P.dinv[3 * i];
-            z1 = r[3 * i + 1] * (double)P.dinv[3 * i + 1];
-            z2 = r[3 * i + 2] * (double)P.dinv[3 * i + 2];
+            z0 = (double)r[3 * i] * (double)P.dinv[3 * i];
+            z1 = (double)r[3 * i + 1] * (double)P.dinv[3 * i + 1];
+            z2 = (double)r[3 * i + 2] * (double)P.dinv[3 * i + 2];
         } else {
             const float4 zv = P.z[i];
             z0 = zv.x; z1 = zv.y; z2 = zv.z;
@@ -364,9 +369,11 @@ __global__ void __launch_bounds__(256) k_cgcg_vec(Sched S, double *x, double *r,
 }
 
 // Zero start of the flagged instances (all when restart == nullptr):
-// x = 0, r = b, p = P^-1 r; partials of r.z, ||r||^2 and ||b||^2.
+// x = 0, r = b, p = P^-1 r (and the sweep's correction e = 0 when the inner
+// vectors are FP32); partials of r.z, ||r||^2 and ||b||^2.
+template <typename TV>
 __global__ void __launch_bounds__(256) k_pcg_start_zero(Sched S, const uint8_t *restart, const double *b, double *x,
-                                                        double *r, float4 *p, PreArgs P, double *partials) {
+                                                        TV *r, float4 *p, PreArgs P, double *partials, TV *e) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
@@ -377,7 +384,10 @@ __global__ void __launch_bounds__(256) k_pcg_start_zero(Sched S, const uint8_t *
         double z[3];
         precond3(P, i, r0, r1, r2, z);
         x[3 * i] = 0.0; x[3 * i + 1] = 0.0; x[3 * i + 2] = 0.0;
-        r[3 * i] = r0; r[3 * i + 1] = r1; r[3 * i + 2] = r2;
+        r[3 * i] = (TV)r0; r[3 * i + 1] = (TV)r1; r[3 * i + 2] = (TV)r2;
+        if (e) {
+            e[3 * i] = TV(0); e[3 * i + 1] = TV(0); e[3 * i + 2] = TV(0);
+        }
         rz += r0 * z[0] + r1 * z[1] + r2 * z[2];
         rr += r0 * r0 + r1 * r1 + r2 * r2;
         p[i] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
@@ -387,13 +397,14 @@ __global__ void __launch_bounds__(256) k_pcg_start_zero(Sched S, const uint8_t *
 }
 
 // Residual t = b - A x for FP64 x over the item's slices.  MODE 0 (sweep
-// start of the flagged instances): r = t, p = D^-1 r; partials of r.z,
+// start of the flagged instances): r = t, p = P^-1 r, e = 0 (FP32 inner
+// vectors); partials of r.z,
 // ||r||^2, ||b||^2.  MODE 1 (check, all instances): partials of ||t||^2,
 // ||b||^2.
-template <typename TB, int MODE>
+template <typename TB, int MODE, typename TV>
 __global__ void __launch_bounds__(1024) k_residual(SpmvArgs M, Sched S, const uint8_t *restart, const double *b,
-                                                  const double *x, double *r, float4 *p, PreArgs P,
-                                                  double *partials) {
+                                                  const double *x, TV *r, float4 *p, PreArgs P,
+                                                  double *partials, TV *e) {
     const int it = item_of_block(S.n_sitems);
     if (it < 0) return;
     const int4 I = S.sitem[it];
@@ -416,7 +427,10 @@ __global__ void __launch_bounds__(1024) k_residual(SpmvArgs M, Sched S, const ui
             if (MODE == 0) {
                 double z[3];
                 precond3(P, row, t[0], t[1], t[2], z);
-                r[3 * row] = t[0]; r[3 * row + 1] = t[1]; r[3 * row + 2] = t[2];
+                r[3 * row] = (TV)t[0]; r[3 * row + 1] = (TV)t[1]; r[3 * row + 2] = (TV)t[2];
+                if (e) {
+                    e[3 * row] = TV(0); e[3 * row + 1] = TV(0); e[3 * row + 2] = TV(0);
+                }
                 rz += t[0] * z[0] + t[1] * z[1] + t[2] * z[2];
                 p[row] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
             }
@@ -480,6 +494,15 @@ __global__ void __launch_bounds__(1024) k_spmv_apply(SpmvArgs M, Sched S, const 
         yout[3 * row] = y[0];
         yout[3 * row + 1] = y[1];
         yout[3 * row + 2] = y[2];
+    }
+}
+
+// End of a refinement sweep with FP32 inner vectors: x += e, e = 0.
+__global__ void k_fold(int64_t n, double *x, float *e) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) {
+        x[k] += (double)e[k];
+        e[k] = 0.0f;
     }
 }
 
@@ -700,30 +723,47 @@ static pc_status ensure_windows(Ctx *ctx, hipStream_t s) {
     return PC_OK;
 }
 
-// One CG iteration of parity par (the parity selects the rz slot, see
-// PcgState): SpMV with its partials, alpha, update, direction (beta from
-// the update partials, state advance).
-template <typename TB>
-static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s, int par) {
-    int slot = ctx->prof.begin(PK_SPMV, s);
+// SpMV of p into q (stored as TQ) with partials of p.q.
+template <typename TB, typename TQ>
+static void launch_spmv(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s, TQ *q) {
     if (ctx->narrow && M.jdel)
-        hipLaunchKernelGGL((k_pcg_spmv<TB, true>), dim3(g.sblocks), dim3(g.sthreads),
-                           sizeof(float4) * (size_t)ctx->win_cap, s, M, S, ctx->p, ctx->q, ctx->st, ctx->partials,
+        hipLaunchKernelGGL((k_pcg_spmv<TB, true, TQ>), dim3(g.sblocks), dim3(g.sthreads),
+                           sizeof(float4) * (size_t)ctx->win_cap, s, M, S, ctx->p, q, ctx->st, ctx->partials,
                            ctx->sitem_win, ctx->win_cap);
     else
-        hipLaunchKernelGGL((k_pcg_spmv<TB, false>), dim3(g.sblocks), dim3(g.sthreads),
-                           sizeof(float4) * (size_t)ctx->win_cap, s, M, S, ctx->p, ctx->q, ctx->st, ctx->partials,
+        hipLaunchKernelGGL((k_pcg_spmv<TB, false, TQ>), dim3(g.sblocks), dim3(g.sthreads),
+                           sizeof(float4) * (size_t)ctx->win_cap, s, M, S, ctx->p, q, ctx->st, ctx->partials,
                            ctx->sitem_win, ctx->win_cap);
+}
+
+// One CG iteration of parity par (the parity selects the rz slot, see
+// PcgState): SpMV with its partials, alpha, update, direction (beta from
+// the update partials, state advance).  TV: type of the iterate, residual
+// and product (FP64, or FP32 inside a refinement sweep, where the iterate
+// is the sweep's correction e).
+template <typename TB, typename TV>
+static void launch_iter_v(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s, int par,
+                          TV *x, TV *r, TV *q) {
+    int slot = ctx->prof.begin(PK_SPMV, s);
+    launch_spmv<TB, TV>(ctx, M, S, g, s, q);
     ctx->prof.end(slot, s);
     hipLaunchKernelGGL(k_fin_alpha, dim3(ctx->ninst), dim3(256), 0, s, S, par, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
-    hipLaunchKernelGGL(k_pcg_update, dim3(g.vblocks), dim3(256), 0, s, S, ctx->x, ctx->r, (const float *)ctx->p,
-                       ctx->q, pre_args(ctx), ctx->st, ctx->partials_u);
+    hipLaunchKernelGGL(k_pcg_update<TV>, dim3(g.vblocks), dim3(256), 0, s, S, x, r, (const float *)ctx->p,
+                       (const TV *)q, pre_args(ctx), ctx->st, ctx->partials_u);
     ctx->prof.end(slot, s);
     slot = ctx->prof.begin(PK_DIR, s);
-    hipLaunchKernelGGL(k_pcg_dir, dim3(g.vblocks), dim3(256), 0, s, S, par, ctx->r, ctx->p, pre_args(ctx), ctx->st,
-                       ctx->partials_u);
+    hipLaunchKernelGGL(k_pcg_dir<TV>, dim3(g.vblocks), dim3(256), 0, s, S, par, (const TV *)r, ctx->p,
+                       pre_args(ctx), ctx->st, ctx->partials_u);
     ctx->prof.end(slot, s);
+}
+
+template <typename TB>
+static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s, int par) {
+    if (ctx->inner32)
+        launch_iter_v<TB, float>(ctx, M, S, g, s, par, ctx->e32, ctx->r32, ctx->q32);
+    else
+        launch_iter_v<TB, double>(ctx, M, S, g, s, par, ctx->x, ctx->r, ctx->q);
 }
 
 // One iteration of the single-reduction form: SpMV of u with partials of
@@ -731,14 +771,7 @@ static void launch_iter(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids
 template <typename TB>
 static void launch_iter_cgcg(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, hipStream_t s) {
     int slot = ctx->prof.begin(PK_SPMV, s);
-    if (ctx->narrow && M.jdel)
-        hipLaunchKernelGGL((k_pcg_spmv<TB, true>), dim3(g.sblocks), dim3(g.sthreads),
-                           sizeof(float4) * (size_t)ctx->win_cap, s, M, S, ctx->p, ctx->q, ctx->st, ctx->partials,
-                           ctx->sitem_win, ctx->win_cap);
-    else
-        hipLaunchKernelGGL((k_pcg_spmv<TB, false>), dim3(g.sblocks), dim3(g.sthreads),
-                           sizeof(float4) * (size_t)ctx->win_cap, s, M, S, ctx->p, ctx->q, ctx->st, ctx->partials,
-                           ctx->sitem_win, ctx->win_cap);
+    launch_spmv<TB, double>(ctx, M, S, g, s, ctx->q);
     ctx->prof.end(slot, s);
     hipLaunchKernelGGL(k_fin_cgcg, dim3(ctx->ninst), dim3(1024), 0, s, S, ctx->partials, ctx->partials_u, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
@@ -771,30 +804,61 @@ static void launch_residual(Ctx *ctx, const SpmvArgs &M, const Sched &S, const G
                             const double *b, const double *x, int mode, double *out2, hipStream_t s) {
     using TB = double;
     if (mode == 0) {
-        hipLaunchKernelGGL((k_residual<TB, 0>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b, x, ctx->r,
-                           ctx->p, pre_args(ctx), ctx->partials);
+        if (ctx->inner32)
+            hipLaunchKernelGGL((k_residual<TB, 0, float>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b,
+                               x, ctx->r32, ctx->p, pre_args(ctx), ctx->partials, ctx->e32);
+        else
+            hipLaunchKernelGGL((k_residual<TB, 0, double>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart,
+                               b, x, ctx->r, ctx->p, pre_args(ctx), ctx->partials, (double *)nullptr);
         hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 1, ctx->cg_par, restart, ctx->partials,
                            ctx->st);
     } else {
-        hipLaunchKernelGGL((k_residual<TB, 1>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b, x, ctx->r,
-                           ctx->p, pre_args(ctx), ctx->partials);
+        hipLaunchKernelGGL((k_residual<TB, 1, double>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b, x,
+                           ctx->r, ctx->p, pre_args(ctx), ctx->partials, (double *)nullptr);
         hipLaunchKernelGGL(k_fin_check, dim3(ctx->ninst), dim3(256), 0, s, S, ctx->partials, out2);
     }
 }
 
 static void launch_start_zero(Ctx *ctx, const Sched &S, const Grids &g, const uint8_t *restart, const double *b,
                               hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_start_zero, dim3(g.vblocks), dim3(256), 0, s, S, restart, b, ctx->x, ctx->r, ctx->p,
-                       pre_args(ctx), ctx->partials);
+    if (ctx->inner32)
+        hipLaunchKernelGGL(k_pcg_start_zero<float>, dim3(g.vblocks), dim3(256), 0, s, S, restart, b, ctx->x,
+                           ctx->r32, ctx->p, pre_args(ctx), ctx->partials, ctx->e32);
+    else
+        hipLaunchKernelGGL(k_pcg_start_zero<double>, dim3(g.vblocks), dim3(256), 0, s, S, restart, b, ctx->x,
+                           ctx->r, ctx->p, pre_args(ctx), ctx->partials, (double *)nullptr);
     hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 0, ctx->cg_par, restart, ctx->partials,
                        ctx->st);
+}
+
+// With FP32 inner vectors the sweep's correction is added to x at its end.
+static void launch_fold(Ctx *ctx, hipStream_t s) {
+    if (!ctx->inner32) return;
+    const int64_t n3 = 3 * (int64_t)ctx->nv;
+    hipLaunchKernelGGL(k_fold, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, ctx->x, ctx->e32);
+}
+
+// FP32 inner vectors apply to BF16 blocks with the textbook recurrences
+// (the refinement sweeps only ask 1e-2 of each inner solve there).
+pc_status set_inner_vectors(Ctx *ctx) {
+    ctx->inner32 = ctx->use_inner32 && ctx->dtype == PC_BF16 && ctx->method == 0;
+    if (ctx->inner32 && !ctx->e32) {
+        const size_t bytes = sizeof(float) * 3 * (size_t)ctx->nv;
+        pc_status st;
+        if ((st = dev_alloc(ctx, (void **)&ctx->e32, bytes))) return st;
+        if ((st = dev_alloc(ctx, (void **)&ctx->r32, bytes))) return st;
+        if ((st = dev_alloc(ctx, (void **)&ctx->q32, bytes))) return st;
+        PC_HIP(hipMemset(ctx->e32, 0, bytes));
+    }
+    return PC_OK;
 }
 
 static bool graph_stale(const Ctx *ctx, int variant, const SpmvArgs &M, int elem_size) {
     return !ctx->gexec[variant] || ctx->gkey[variant] != M.jval || ctx->gkey_dtype[variant] != elem_size ||
            ctx->gkey_chunk[variant] != ctx->graph_chunk || ctx->gkey_sched[variant] != ctx->sched_version ||
            ctx->gkey_pre[variant] != ctx->precond || ctx->gkey_win[variant] != ctx->win_cap ||
-           ctx->gkey_narrow[variant] != (int)ctx->narrow || ctx->gkey_method[variant] != ctx->method;
+           ctx->gkey_narrow[variant] != (int)ctx->narrow || ctx->gkey_method[variant] != ctx->method ||
+           ctx->gkey_inner32[variant] != (int)ctx->inner32;
 }
 
 // Capture `chunk` (even) iterations on the context's capture stream; the
@@ -835,6 +899,7 @@ static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Sched &S, cons
     ctx->gkey_win[variant] = ctx->win_cap;
     ctx->gkey_narrow[variant] = (int)ctx->narrow;
     ctx->gkey_method[variant] = ctx->method;
+    ctx->gkey_inner32[variant] = (int)ctx->inner32;
     return PC_OK;
 }
 
@@ -990,6 +1055,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
         }
         for (int i = 0; i < ninst; ++i)
             if (active[i]) iters[i] += ctx->st_host[i].iters;
+        launch_fold(ctx, s);
         // true residual of every instance
         launch_residual(ctx, Mhi, S, g, nullptr, b, ctx->x, 1, ctx->res2, s);
         PC_HIP(hipGetLastError());
@@ -1193,6 +1259,8 @@ pc_status pcg_run(Ctx *ctx, const double *b, double *dv, const pc_solve_opts *o,
         if (st) return st;
         if ((st = dev_alloc(ctx, (void **)&ctx->cg_s, sizeof(double) * 3 * (size_t)ctx->nv))) return st;
     }
+    pc_status ist = set_inner_vectors(ctx);
+    if (ist) return ist;
     switch (ctx->dtype) {
         case PC_F64: return pcg_typed<double>(ctx, b, dv, o, info, s);
         case PC_F32: return pcg_typed<float>(ctx, b, dv, o, info, s);

@@ -1,0 +1,89 @@
+"""FP32 inner vectors of the refinement sweeps (BF16 blocks): each sweep
+solves for a correction e with e, r and q = A p stored in FP32 and adds it
+to the FP64 x at its end.  Against the oracle's matrix, with the option on
+and off: both meet the tolerance (the FP64 true residual decides), the
+sweep and iteration counts stay within 10% of each other, and batched
+instances, a warm start, a sweep count above one and graph replay all go
+through the correction path; the option does not touch FP32/FP64 blocks."""
+import numpy as np
+import pytest
+
+from gpu_helpers import random_velocity, require_gpu, sheet, to_dev
+from paper_2008_00409_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2008_00409_amd import binding
+    return binding
+
+
+def solve(torch, B, c, v, dtype, inner, precond="block", chunk=0, dv0=None, instances=None, tol=1e-6):
+    ctx = B.Context.from_cloth(c)
+    try:
+        if instances is not None:
+            ctx.set_instances(instances)
+        ctx.set_option(B.PC_OPT_INNER_FP32, inner)
+        ctx.set_option(B.PC_OPT_GRAPH_CHUNK, chunk)
+        assert ctx.get_option(B.PC_OPT_INNER_FP32) == inner
+        b = ctx.cloth_assemble(to_dev(torch, c.x0), to_dev(torch, v), dtype)
+        start = None if dv0 is None else to_dev(torch, dv0)
+        dv, info = ctx.cloth_pcg_solve(b, dv=start, tol=tol, precond=precond, warm=dv0 is not None)
+        per = ctx.instance_info() if instances is not None else None
+        return dv.cpu().numpy(), info, per
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("precond", ["block", "jacobi"])
+def test_bf16_inner32_meets_tolerance(torch, B, oracle_mod, precond):
+    c = sheet(71, 53, seed=21, flips=0.1)
+    v = random_velocity(c, 0.05, seed=2)
+    P = oracle_mod.Problem.from_cloth(c)
+    A = P.assemble(c.x0, v)
+    d1, i1, _ = solve(torch, B, c, v, "bf16", 1, precond)
+    d0, i0, _ = solve(torch, B, c, v, "bf16", 0, precond)
+    assert i1["sweeps"] > 1
+    for d, i in ((d1, i1), (d0, i0)):
+        assert i["rel_res_true"] <= 1e-6
+        assert P.residual(A, d) <= 1e-6 * (1 + 1e-6)
+    assert abs(i1["iters"] - i0["iters"]) <= 0.1 * i0["iters"] + 5, (i1["iters"], i0["iters"])
+    assert np.linalg.norm(d1 - d0) <= 1e-4 * np.linalg.norm(d0)
+
+
+def test_inner32_warm_start_graph_and_instances(torch, B, oracle_mod):
+    c = mg.config_batch(seed=93, sizes=[12, 33, 9, 21])
+    begins = [r[0] for r in c.sheet_ranges] + [c.nv]
+    v = random_velocity(c, 0.05, seed=8)
+    P = oracle_mod.Problem.from_cloth(c)
+    A = P.assemble(c.x0, v)
+    dv_ref, _ = P.pcg(A, tol=1e-10)
+    start = dv_ref + 1e-3 * np.random.default_rng(4).normal(size=dv_ref.shape) * np.abs(dv_ref).max()
+    start[c.pinned == 1] = 0
+    outs = []
+    for chunk in (0, 32):
+        d, info, per = solve(torch, B, c, v, "bf16", 1, chunk=chunk, dv0=start, instances=begins)
+        r = A.b - P.spmv(A, d)
+        for k in range(len(begins) - 1):
+            sl = slice(begins[k], begins[k + 1])
+            assert np.linalg.norm(r[sl]) <= 1e-6 * (1 + 1e-6) * np.linalg.norm(A.b[sl])
+        outs.append((d, info["iters"]))
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0].view(np.uint64), outs[1][0].view(np.uint64))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_option_leaves_higher_precision_blocks_alone(torch, B, dtype):
+    c = sheet(40, 30, seed=35, flips=0.1)
+    v = random_velocity(c, 0.05, seed=9)
+    d1, i1, _ = solve(torch, B, c, v, dtype, 1)
+    d0, i0, _ = solve(torch, B, c, v, dtype, 0)
+    assert i1["iters"] == i0["iters"]
+    assert np.array_equal(d1.view(np.uint64), d0.view(np.uint64))
