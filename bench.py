@@ -34,16 +34,17 @@ HBM_PEAK_GBS = 8000.0
 BLOCK_BYTES = {"f64": 72, "f32": 36, "bf16": 18}
 KERNEL_TB = {"f64": "double", "f32": "float", "bf16": "pc::bf16_t"}
 # committed counter summaries (profiles/) giving HBM bytes per launch
-TRAFFIC_FILES = {"k_pcg_spmv<pc::bf16_t, true>": "k_pcg_spmv_bf16_stacked-3x501x551_traffic.md",
-                 "k_pcg_spmv<float, true>": "k_pcg_spmv_f32_stacked-3x501x551_traffic.md"}
+TRAFFIC_FILES = {"k_pcg_spmv<pc::bf16_t, true, float>": "k_pcg_spmv_bf16_stacked-3x501x551_traffic.md",
+                 "k_pcg_spmv<float, true, double>": "k_pcg_spmv_f32_stacked-3x501x551_traffic.md"}
 
 
-def spmv_bytes(nv, nnzb, blocks, col_bytes=4):
+def spmv_bytes(nv, nnzb, blocks, col_bytes=4, q_bytes=24):
     """Algorithmic bytes of one difference-form SpMV in the CG loop: every
     stored block and its column index once (16-bit offsets when the SpMV
     runs with them, else 32-bit columns), the input vector once per row
-    (float4), the FP64 output, the FP64 mass, and the row pointers."""
-    return nnzb * (BLOCK_BYTES[blocks] + col_bytes) + nv * (16 + 24 + 8) + 4 * (nv + 1)
+    (float4), the output (FP64, or FP32 inside the BF16 refinement sweeps),
+    the FP64 mass, and the row pointers."""
+    return nnzb * (BLOCK_BYTES[blocks] + col_bytes) + nv * (16 + q_bytes + 8) + 4 * (nv + 1)
 
 
 def assembly_bytes(nv, nt, nh, nnzb, blocks):
@@ -293,8 +294,9 @@ def main():
     spmv = prof.get("spmv", {})
     spmv_ms = spmv.get("median_ms", float("nan"))
     narrow = bool(ctx.get_option(binding.PC_OPT_SPMV_NARROW_ACTIVE))
-    kname = f"k_pcg_spmv<{KERNEL_TB[args.blocks]}, {'true' if narrow else 'false'}>"
-    alg = spmv_bytes(nv, nnzb, args.blocks, 2 if narrow else 4)
+    inner32 = args.blocks == "bf16" and args.method == "cg" and bool(ctx.get_option(binding.PC_OPT_INNER_FP32))
+    kname = f"k_pcg_spmv<{KERNEL_TB[args.blocks]}, {'true' if narrow else 'false'}, {'float' if inner32 else 'double'}>"
+    alg = spmv_bytes(nv, nnzb, args.blocks, 2 if narrow else 4, 12 if inner32 else 24)
     ach = alg / (spmv_ms * 1e-3) / 1e9 if spmv_ms == spmv_ms and spmv_ms > 0 else None
     asm = prof.get("assemble_all", {})
     asm_ms = asm.get("median_ms", float("nan"))
