@@ -163,8 +163,10 @@ pc_status cloth_assemble(pc_ctx *ctx, const double *x, const double *v, pc_dtype
  * of the stored blocks does not disturb the mass term.  CG runs on the
  * solver copy of the blocks (the assembled dtype); each sweep starts from the
  * residual b - A dv computed with the FP64 copy, and sweeps repeat (iterative
- * refinement) until that FP64 residual meets tol.  Dots, vectors and all
- * accumulation are FP64 (the search direction is stored as FP32).
+ * refinement) until that FP64 residual meets tol.  Dots and all
+ * accumulation are FP64; vectors are FP64 except the search direction
+ * (FP32) and, with BF16 blocks and PC_OPT_INNER_FP32, the sweep's
+ * correction, residual and product (FP32; x stays FP64).
  * dv: device nv*3 doubles, the start when opts->warm = 1, the solution on
  * return (also when PC_ERR_NOT_CONVERGED).  info: host, optional.
  * Synchronises the stream. */
