@@ -6,6 +6,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pc_ctx.h"
 
 namespace pc {
@@ -36,7 +38,8 @@ struct SpmvArgs {
 
 struct VecF4 {
     const float4 *p;
-    __device__ __forceinline__ void load(int i, double &a, double &b, double &c) const {
+    template <typename T>
+    __device__ __forceinline__ void load(int i, T &a, T &b, T &c) const {
         const float4 v = p[i];
         a = v.x; b = v.y; c = v.z;
     }
@@ -46,17 +49,28 @@ struct VecF4 {
 struct VecLds {
     const float4 *w;
     int lo;
-    __device__ __forceinline__ void load(int i, double &a, double &b, double &c) const {
+    template <typename T>
+    __device__ __forceinline__ void load(int i, T &a, T &b, T &c) const {
         const float4 v = w[i - lo];
         a = v.x; b = v.y; c = v.z;
     }
 };
 struct VecD3 {
     const double *p;
-    __device__ __forceinline__ void load(int i, double &a, double &b, double &c) const {
+    template <typename T>
+    __device__ __forceinline__ void load(int i, T &a, T &b, T &c) const {
         a = p[3 * i]; b = p[3 * i + 1]; c = p[3 * i + 2];
     }
 };
+
+// Arithmetic type of the row sums: FP64, except for BF16 blocks applied to
+// the FP32 search direction, whose products and differences are taken in
+// FP32 (the stored values carry 8 significant bits; FP32 rounding adds about
+// 6e-8 of the row's terms, the blocks' own rounding 4e-3; differences of two
+// FP32 values within a factor 2 of each other are exact).  The mass term is
+// always FP64.
+template <typename TB> struct SpmvAcc { typedef double T; };
+template <> struct SpmvAcc<bf16_t> { typedef float T; };
 
 // One row of the difference-form product for the lane's row of `slice`.
 // Lane k of the wavefront holds slot k's row count and start offset, so the
@@ -93,23 +107,22 @@ struct SlotGroup {
             BlockIO<TB>::load((const TB *)M.jval + 9 * (int64_t)off, slot_width(c), l, v[u]);
         }
     }
-    template <typename V>
-    __device__ __forceinline__ void apply(const V &x, int row, double x0, double x1, double x2, double &a0,
-                                          double &a1, double &a2) const {
+    template <typename V, typename A>
+    __device__ __forceinline__ void apply(const V &x, int row, A x0, A x1, A x2, A &a0, A &a1, A &a2) const {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            double d0, d1, d2;
+            A d0, d1, d2;
             x.load(jc[u], d0, d1, d2);
             const bool off_diag = jc[u] != row;
-            d0 -= off_diag ? x0 : 0.0;
-            d1 -= off_diag ? x1 : 0.0;
-            d2 -= off_diag ? x2 : 0.0;
-            d0 = act[u] ? d0 : 0.0;
-            d1 = act[u] ? d1 : 0.0;
-            d2 = act[u] ? d2 : 0.0;
-            a0 += to_f64(v[u][0]) * d0 + to_f64(v[u][1]) * d1 + to_f64(v[u][2]) * d2;
-            a1 += to_f64(v[u][3]) * d0 + to_f64(v[u][4]) * d1 + to_f64(v[u][5]) * d2;
-            a2 += to_f64(v[u][6]) * d0 + to_f64(v[u][7]) * d1 + to_f64(v[u][8]) * d2;
+            d0 -= off_diag ? x0 : A(0);
+            d1 -= off_diag ? x1 : A(0);
+            d2 -= off_diag ? x2 : A(0);
+            d0 = act[u] ? d0 : A(0);
+            d1 = act[u] ? d1 : A(0);
+            d2 = act[u] ? d2 : A(0);
+            a0 += (A)v[u][0] * d0 + (A)v[u][1] * d1 + (A)v[u][2] * d2;
+            a1 += (A)v[u][3] * d0 + (A)v[u][4] * d1 + (A)v[u][5] * d2;
+            a2 += (A)v[u][6] * d0 + (A)v[u][7] * d1 + (A)v[u][8] * d2;
         }
     }
 };
@@ -122,9 +135,11 @@ __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, 
     const int my_off = M.slice_vbase[slice] + wave_excl_scan(slot_width(my_cnt));
     const int r0 = NARROW ? M.slice_row0[slice] : 0;
     const int nslots = __popcll(__ballot(my_cnt > 0));  // counts are non-increasing in the slot
-    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    // FP64 input vectors (residuals, the API's product) keep FP64 sums
+    typedef typename std::conditional<std::is_same<V, VecD3>::value, double, typename SpmvAcc<TB>::T>::type A;
+    A x0 = 0, x1 = 0, x2 = 0;
     if (row >= 0) x.load(row, x0, x1, x2);
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    A a0 = 0, a1 = 0, a2 = 0;
 #if PC_SPMV_PIPE
     SlotGroup<TB, UNROLL, NARROW> cur;
     cur.load(M, 0, nslots, lane, my_cnt, my_off, r0);
@@ -143,9 +158,9 @@ __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, 
 #endif
     if (row >= 0) {
         const double m = M.mass[row];
-        y[0] = a0 + m * x0;
-        y[1] = a1 + m * x1;
-        y[2] = a2 + m * x2;
+        y[0] = (double)a0 + m * (double)x0;
+        y[1] = (double)a1 + m * (double)x1;
+        y[2] = (double)a2 + m * (double)x2;
     } else {
         y[0] = y[1] = y[2] = 0.0;
     }
