@@ -119,7 +119,8 @@ typedef struct {
     double rel_res_true;       /* ||b - A dv|| / ||b|| recomputed at exit with the FP64 blocks */
     double bnorm;              /* ||b||_2 */
     int32_t fallback;          /* 1 if the inner CG switched to the FP64 blocks after a
-                                  breakdown on the low-precision copy */
+                                  breakdown on the low-precision copy, or after a sweep on
+                                  it that did not halve the FP64 residual it started from */
     int32_t warm_used;         /* start actually used: 0 zero, 1 given / previous increment,
                                   2 learned (previous increment plus a nonzero step along the
                                   network's correction) */

@@ -1065,6 +1065,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
         bool any = false, any_breakdown = false;
         for (int i = 0; i < ninst; ++i) {
             const PcgState &h = ctx->st_host[i];
+            const bool was_active = active[i] != 0;
             active[i] = 0;
             const bool ok = res2[2 * i] <= tol * tol * res2[2 * i + 1];
             if (ok || res2[2 * i + 1] == 0.0 || (h.flags & 2) || iters[i] >= maxit) continue;
@@ -1075,6 +1076,13 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
                 } else {
                     continue;
                 }
+            } else if (!inner_hi && ctx->hi_valid && was_active && !(res2[2 * i] <= 0.25 * h.rr0)) {
+                // the sweep on the low-precision copy did not halve the FP64
+                // residual it started from: refinement with that operator is not
+                // contracting for this system (its rounding is too coarse for the
+                // conditioning); FP64 blocks from here on
+                any_breakdown = true;
+                fallback[i] = 1;
             } else if (sweeps[i] >= max_sweeps) {
                 continue;
             }
@@ -1083,7 +1091,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
             any = true;
         }
         if (!any || ++guard > 64) break;
-        if (any_breakdown) inner_hi = true;  // low-precision operator lost definiteness: FP64 blocks from here on
+        if (any_breakdown) inner_hi = true;  // low-precision operator lost definiteness or stopped contracting: FP64 blocks from here on
         for (int i = 0; i < ninst; ++i) {
             if (again[i]) {
                 sweeps[i] += 1;
