@@ -317,7 +317,7 @@ pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
  * PC_OPT_SPMV_SLICES_PER_BLOCK: 64-row slices per SpMV work item / block
  *   (1, 2, 4, 8 (default) or 16).
  * PC_OPT_VECTOR_ROWS_PER_BLOCK: rows per work item of the CG vector kernels
- *   (multiple of 64 in [64, 4096], default 512).  Every block of the direction
+ *   (multiple of 64 in [64, 4096], default 2048; 1024 threads per block).  Every block of the direction
  *   kernel sums its instance's partials of the update kernel, so fewer,
  *   larger work items cost less per iteration on large instances.
  * PC_OPT_LDS_WINDOW: 1 (default): each SpMV work item whose block columns
@@ -343,7 +343,7 @@ pc_status pc_get_option(pc_ctx *ctx, int32_t option, int64_t *value);
 
 /* Autotuner: on the assembled system and right-hand side b (device nv*3),
  * time `iters` CG iterations for every candidate schedule (slices per SpMV
- * block 2/4/8/16 x rows per vector block 512/1024/2048 x graph chunk 0/32)
+ * block 2/4/8/16 x rows per vector block 1024/2048/4096 x graph chunk 0/32)
  * with HIP events on the stream, and keep the fastest.  precond: the
  * preconditioner the iterations use (as pc_solve_opts.precond).  chosen
  * (host, optional) receives {slices per block, rows per block, graph chunk};

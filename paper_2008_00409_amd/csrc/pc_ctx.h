@@ -182,7 +182,7 @@ struct Ctx {
     int ninst = 1;
     std::vector<int> inst_row0_h;     // ninst + 1 instance row ranges
     int spb = 8;                      // slices per SpMV work item (wavefronts per block)
-    int rpb = 512;                    // rows per vector work item
+    int rpb = 2048;                   // rows per vector work item
     int n_sitems = 0, n_vitems = 0;
     int4 *sitem = nullptr, *vitem = nullptr;
     int *inst_sitem0 = nullptr, *inst_vitem0 = nullptr;

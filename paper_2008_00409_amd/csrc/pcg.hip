@@ -29,6 +29,10 @@
 
 namespace pc {
 
+// Threads per block of the vector kernels (one block per vector work item;
+// block Jacobi stages VT rows of r at a time in LDS).
+constexpr int VT = 1024;
+
 // Preconditioner z = P^-1 r: kind 0 Jacobi (dinv, 3 per row), kind 1 block
 // Jacobi (binv, the inverse diagonal block, 6 per row: xx, xy, xz, yy, yz,
 // zz).  z holds the block-Jacobi z of the current residual (FP32).
@@ -160,9 +164,9 @@ __global__ void __launch_bounds__(256) k_fin_alpha(Sched S, int par, const doubl
 // correction, residual and product inside a refinement sweep.  Block Jacobi stages each 256-row chunk of r in LDS,
 // then one thread per row applies the inverse block and stores z.
 template <typename TV>
-__global__ void __launch_bounds__(256) k_pcg_update(Sched S, TV *x, TV *r, const float *pf, const TV *q,
+__global__ void __launch_bounds__(VT) k_pcg_update(Sched S, TV *x, TV *r, const float *pf, const TV *q,
                                                     PreArgs P, const PcgState *st, double *part_u) {
-    __shared__ double rs[3 * 256];
+    __shared__ double rs[3 * VT];
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
@@ -181,8 +185,8 @@ __global__ void __launch_bounds__(256) k_pcg_update(Sched S, TV *x, TV *r, const
             rr += rk * rk;
         }
     } else {
-        for (int r0 = I.y; r0 < I.z; r0 += 256) {
-            const int nr = min(256, I.z - r0);
+        for (int r0 = I.y; r0 < I.z; r0 += VT) {
+            const int nr = min(VT, I.z - r0);
             for (int k = threadIdx.x; k < 3 * nr; k += blockDim.x) {
                 const int kk = 3 * r0 + k;
                 const int i = kk / 3;
@@ -217,7 +221,7 @@ __global__ void __launch_bounds__(256) k_pcg_update(Sched S, TV *x, TV *r, const
 // iteration count and the convergence test ||r||^2 <= thresh.  Blocks that
 // see the instance converged skip the direction (it is not used again).
 template <typename TV>
-__global__ void __launch_bounds__(256) k_pcg_dir(Sched S, int par, const TV *r, float4 *p, PreArgs P,
+__global__ void __launch_bounds__(VT) k_pcg_dir(Sched S, int par, const TV *r, float4 *p, PreArgs P,
                                                  PcgState *st, const double *part_u) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
@@ -323,10 +327,10 @@ __global__ void __launch_bounds__(1024) k_fin_cgcg(Sched S, const double *partia
 // per row forms u = P^-1 r, stores it as float4 for the next product and
 // adds to the partials of r.u (with the stored, rounded u, the vector the
 // product and the direction use) and ||r||^2.
-__global__ void __launch_bounds__(256) k_cgcg_vec(Sched S, double *x, double *r, float4 *u, const double *w,
+__global__ void __launch_bounds__(VT) k_cgcg_vec(Sched S, double *x, double *r, float4 *u, const double *w,
                                                   double *pd, double *sv, PreArgs P, const PcgState *st,
                                                   double *part_u) {
-    __shared__ double rs[3 * 256];
+    __shared__ double rs[3 * VT];
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
@@ -336,8 +340,8 @@ __global__ void __launch_bounds__(256) k_cgcg_vec(Sched S, double *x, double *r,
     const bool first = T.kc == 1;
     const float *uf = (const float *)u;
     double gz = 0.0, rr = 0.0;
-    for (int r0 = I.y; r0 < I.z; r0 += 256) {
-        const int nr = min(256, I.z - r0);
+    for (int r0 = I.y; r0 < I.z; r0 += VT) {
+        const int nr = min(VT, I.z - r0);
         for (int k = threadIdx.x; k < 3 * nr; k += blockDim.x) {
             const int64_t kk = 3 * (int64_t)r0 + k;
             const int i = (int)(kk / 3);
@@ -372,7 +376,7 @@ __global__ void __launch_bounds__(256) k_cgcg_vec(Sched S, double *x, double *r,
 // x = 0, r = b, p = P^-1 r (and the sweep's correction e = 0 when the inner
 // vectors are FP32); partials of r.z, ||r||^2 and ||b||^2.
 template <typename TV>
-__global__ void __launch_bounds__(256) k_pcg_start_zero(Sched S, const uint8_t *restart, const double *b, double *x,
+__global__ void __launch_bounds__(VT) k_pcg_start_zero(Sched S, const uint8_t *restart, const double *b, double *x,
                                                         TV *r, float4 *p, PreArgs P, double *partials, TV *e) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
@@ -749,11 +753,11 @@ static void launch_iter_v(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Gri
     ctx->prof.end(slot, s);
     hipLaunchKernelGGL(k_fin_alpha, dim3(ctx->ninst), dim3(256), 0, s, S, par, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
-    hipLaunchKernelGGL(k_pcg_update<TV>, dim3(g.vblocks), dim3(256), 0, s, S, x, r, (const float *)ctx->p,
+    hipLaunchKernelGGL(k_pcg_update<TV>, dim3(g.vblocks), dim3(VT), 0, s, S, x, r, (const float *)ctx->p,
                        (const TV *)q, pre_args(ctx), ctx->st, ctx->partials_u);
     ctx->prof.end(slot, s);
     slot = ctx->prof.begin(PK_DIR, s);
-    hipLaunchKernelGGL(k_pcg_dir<TV>, dim3(g.vblocks), dim3(256), 0, s, S, par, (const TV *)r, ctx->p,
+    hipLaunchKernelGGL(k_pcg_dir<TV>, dim3(g.vblocks), dim3(VT), 0, s, S, par, (const TV *)r, ctx->p,
                        pre_args(ctx), ctx->st, ctx->partials_u);
     ctx->prof.end(slot, s);
 }
@@ -775,7 +779,7 @@ static void launch_iter_cgcg(Ctx *ctx, const SpmvArgs &M, const Sched &S, const 
     ctx->prof.end(slot, s);
     hipLaunchKernelGGL(k_fin_cgcg, dim3(ctx->ninst), dim3(1024), 0, s, S, ctx->partials, ctx->partials_u, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
-    hipLaunchKernelGGL(k_cgcg_vec, dim3(g.vblocks), dim3(256), 0, s, S, ctx->x, ctx->r, ctx->p, ctx->q, ctx->cg_pd,
+    hipLaunchKernelGGL(k_cgcg_vec, dim3(g.vblocks), dim3(VT), 0, s, S, ctx->x, ctx->r, ctx->p, ctx->q, ctx->cg_pd,
                        ctx->cg_s, pre_args(ctx), ctx->st, ctx->partials_u);
     ctx->prof.end(slot, s);
 }
@@ -822,10 +826,10 @@ static void launch_residual(Ctx *ctx, const SpmvArgs &M, const Sched &S, const G
 static void launch_start_zero(Ctx *ctx, const Sched &S, const Grids &g, const uint8_t *restart, const double *b,
                               hipStream_t s) {
     if (ctx->inner32)
-        hipLaunchKernelGGL(k_pcg_start_zero<float>, dim3(g.vblocks), dim3(256), 0, s, S, restart, b, ctx->x,
+        hipLaunchKernelGGL(k_pcg_start_zero<float>, dim3(g.vblocks), dim3(VT), 0, s, S, restart, b, ctx->x,
                            ctx->r32, ctx->p, pre_args(ctx), ctx->partials, ctx->e32);
     else
-        hipLaunchKernelGGL(k_pcg_start_zero<double>, dim3(g.vblocks), dim3(256), 0, s, S, restart, b, ctx->x,
+        hipLaunchKernelGGL(k_pcg_start_zero<double>, dim3(g.vblocks), dim3(VT), 0, s, S, restart, b, ctx->x,
                            ctx->r, ctx->p, pre_args(ctx), ctx->partials, (double *)nullptr);
     hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 0, ctx->cg_par, restart, ctx->partials,
                        ctx->st);
@@ -1116,7 +1120,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
         }
     if (anyzero) {
         if ((st = upload_flags(ctx, zero, s))) return st;
-        hipLaunchKernelGGL(k_zero_rows, dim3(g.vblocks), dim3(256), 0, s, S, ctx->restart, ctx->x);
+        hipLaunchKernelGGL(k_zero_rows, dim3(g.vblocks), dim3(VT), 0, s, S, ctx->restart, ctx->x);
     }
     hipLaunchKernelGGL(k_copy_d, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, ctx->x, dv);
     PC_HIP(hipGetLastError());
@@ -1211,7 +1215,7 @@ pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, fl
         return PC_ERR_ARG;
     }
     const int spbs[4] = {2, 4, 8, 16};
-    const int rpbs[3] = {512, 1024, 2048};
+    const int rpbs[3] = {1024, 2048, 4096};
     const int chunks[2] = {0, 32};
     float best = 1e30f;
     int bs = ctx->spb, br = ctx->rpb, bc = ctx->graph_chunk;
