@@ -1,6 +1,9 @@
-// Block SpMV and Jacobi-preconditioned CG (paper Sec. 2.5: the linear system
-// of Eq. 3 is solved by PCG each step; Sec. 3.1: SpMV is the dominant
-// operator, vector operations are element-wise).
+// Preconditioned CG on the block SpMV (paper Sec. 2.5: the linear system of
+// Eq. 3 is solved by PCG each step; Sec. 3.1: SpMV is the dominant operator,
+// vector operations are element-wise): Jacobi or block-Jacobi
+// preconditioning, the textbook recurrences or the single-reduction form,
+// FP64 refinement sweeps around a low-precision inner solve.  The SpMV kernel
+// itself is in pc_spmv.h.
 //
 // Solver layout: rows are grouped in slices of up to 64 (one wavefront),
 // never across instances; inside a slice rows are ordered by decreasing
@@ -18,7 +21,8 @@
 //   y_i = m_i x_i + D_i x_i + sum_{j != i} A_ij (x_j - x_i),
 // where the diagonal slot stores the remainder D_i, so that rounding of the
 // stored (FP32/BF16) blocks leaves the mass term and the exact null space of
-// the stiffness intact.  All arithmetic is FP64.
+// the stiffness intact.  Arithmetic is FP64, except the BF16 SpMV's row sums
+// (FP32, see pc_spmv.h) and the FP32 inner vectors of BF16 sweeps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -161,8 +165,9 @@ __global__ void __launch_bounds__(256) k_fin_alpha(Sched S, int par, const doubl
 // x += alpha p, r -= alpha q over the item's rows (flat component indexing:
 // consecutive threads touch consecutive elements); partials of r.z
 // (z = P^-1 r) and r.r with r as stored.  TV: FP64 vectors, or FP32 for the
-// correction, residual and product inside a refinement sweep.  Block Jacobi stages each 256-row chunk of r in LDS,
-// then one thread per row applies the inverse block and stores z.
+// correction, residual and product inside a refinement sweep.  Block Jacobi
+// stages each VT-row chunk of r in LDS, then one thread per row applies the
+// inverse block and stores z.
 template <typename TV>
 __global__ void __launch_bounds__(VT) k_pcg_update(Sched S, TV *x, TV *r, const float *pf, const TV *q,
                                                     PreArgs P, const PcgState *st, double *part_u) {
@@ -323,7 +328,7 @@ __global__ void __launch_bounds__(1024) k_fin_cgcg(Sched S, const double *partia
 // p = u + beta p, s = w + beta s (p = u, s = w in the first iteration of a
 // sweep), x += alpha p, r -= alpha s over the item's rows with flat
 // component indexing (consecutive threads touch consecutive 8-byte
-// elements), each 256-row chunk of the new r staged in LDS; then one thread
+// elements), each VT-row chunk of the new r staged in LDS; then one thread
 // per row forms u = P^-1 r, stores it as float4 for the next product and
 // adds to the partials of r.u (with the stored, rounded u, the vector the
 // product and the direction use) and ||r||^2.
@@ -671,7 +676,7 @@ pc_status build_schedule(Ctx *ctx) {
 
 struct Grids {
     int sblocks, sthreads;  // SpMV items: spb wavefronts each
-    int vblocks;            // vector items: 256 threads each
+    int vblocks;            // vector items: VT threads each
 };
 
 static Grids grids(Ctx *ctx) {
