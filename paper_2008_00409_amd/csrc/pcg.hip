@@ -143,40 +143,34 @@ __global__ void __launch_bounds__(256) k_item_windows(Sched S, const int *slice_
     }
 }
 
-// alpha = rz / p.q per instance; a non-positive or non-finite p.q ends the
-// sweep.  (A single block: summing the SpMV partials in every block of the
-// update measured slower than this extra launch.)
-__global__ void __launch_bounds__(256) k_fin_alpha(Sched S, int par, const double *partials, PcgState *st) {
-    const int inst = blockIdx.x;
-    if (inst >= S.ninst || st[inst].done) return;
-    double tot[1];
-    instance_sum<1>(partials, S.n_sitems, S.inst_sitem0[inst], S.inst_sitem0[inst + 1], tot);
-    if (threadIdx.x == 0) {
-        PcgState &T = st[inst];
-        const double a = T.rzp[par] / tot[0];
-        T.alpha = a;
-        if (!(tot[0] > 0.0) || !isfinite(a)) {
-            T.flags |= isfinite(tot[0]) ? 1 : 2;
-            T.done = 1;
-        }
-    }
-}
-
-// x += alpha p, r -= alpha q over the item's rows (flat component indexing:
-// consecutive threads touch consecutive elements); partials of r.z
-// (z = P^-1 r) and r.r with r as stored.  TV: FP64 vectors, or FP32 for the
+// alpha, then x += alpha p, r -= alpha q over the item's rows (flat
+// component indexing: consecutive threads touch consecutive elements);
+// partials of r.z (z = P^-1 r) and r.r with r as stored.  TV: FP64 vectors, or FP32 for the
 // correction, residual and product inside a refinement sweep.  Block Jacobi
 // stages each VT-row chunk of r in LDS, then one thread per row applies the
 // inverse block and stores z.
 template <typename TV>
-__global__ void __launch_bounds__(VT) k_pcg_update(Sched S, TV *x, TV *r, const float *pf, const TV *q,
-                                                    PreArgs P, const PcgState *st, double *part_u) {
+__global__ void __launch_bounds__(VT) k_pcg_update(Sched S, int par, TV *x, TV *r, const float *pf, const TV *q,
+                                                    PreArgs P, PcgState *st, const double *part_s,
+                                                    double *part_u) {
     __shared__ double rs[3 * VT];
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
     if (st[I.x].done) return;
-    const double alpha = st[I.x].alpha;
+    // alpha = rz / p.q from the SpMV's partials (every block sums its
+    // instance's in the same order, so all blocks agree bit for bit); a
+    // non-positive or non-finite p.q ends the sweep (the first block records it)
+    double pq[1];
+    instance_sum<1>(part_s, S.n_sitems, S.inst_sitem0[I.x], S.inst_sitem0[I.x + 1], pq);
+    const double alpha = st[I.x].rzp[par] / pq[0];
+    if (!(pq[0] > 0.0) || !isfinite(alpha)) {
+        if (it == S.inst_vitem0[I.x] && threadIdx.x == 0) {
+            st[I.x].flags |= isfinite(pq[0]) ? 1 : 2;
+            st[I.x].done = 1;
+        }
+        return;
+    }
     double rz = 0.0, rr = 0.0;
     if (P.kind == 0) {
         for (int k = 3 * I.y + threadIdx.x; k < 3 * I.z; k += blockDim.x) {
@@ -756,10 +750,9 @@ static void launch_iter_v(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Gri
     int slot = ctx->prof.begin(PK_SPMV, s);
     launch_spmv<TB, TV>(ctx, M, S, g, s, q);
     ctx->prof.end(slot, s);
-    hipLaunchKernelGGL(k_fin_alpha, dim3(ctx->ninst), dim3(256), 0, s, S, par, ctx->partials, ctx->st);
     slot = ctx->prof.begin(PK_UPDATE, s);
-    hipLaunchKernelGGL(k_pcg_update<TV>, dim3(g.vblocks), dim3(VT), 0, s, S, x, r, (const float *)ctx->p,
-                       (const TV *)q, pre_args(ctx), ctx->st, ctx->partials_u);
+    hipLaunchKernelGGL(k_pcg_update<TV>, dim3(g.vblocks), dim3(VT), 0, s, S, par, x, r, (const float *)ctx->p,
+                       (const TV *)q, pre_args(ctx), ctx->st, (const double *)ctx->partials, ctx->partials_u);
     ctx->prof.end(slot, s);
     slot = ctx->prof.begin(PK_DIR, s);
     hipLaunchKernelGGL(k_pcg_dir<TV>, dim3(g.vblocks), dim3(VT), 0, s, S, par, (const TV *)r, ctx->p,
