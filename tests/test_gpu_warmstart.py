@@ -170,3 +170,49 @@ def test_learned_start_matches_oracle_line_search(torch, B, oracle_mod, M):
         assert E(start) <= E(dvp) + 1e-12 * abs(E(dvp))
     finally:
         ctx.close()
+
+
+def test_trained_network_gain_on_held_out_step(torch, B, oracle_mod):
+    """What the trained network adds over the method without it: the network
+    is trained online on the first 20 steps of a 96 x 96 bumped sheet (3 Adam
+    steps per step, the solver advancing with the learned start), then the
+    next step's system is solved from the zero start, the previous increment
+    and the learned start.  The learned start lowers the A-norm energy of the
+    previous increment (through the oracle's matrix), and needs no more CG
+    iterations than the zero start; the three counts are printed."""
+    from paper_2008_00409_amd import meshgen as mg
+    c = mg.config_grid(96, seed=2096, h=1.0 / 200)
+    ctx = B.Context.from_cloth(c)
+    try:
+        ctx.ws_set_params(B.Context.ws_init_params(0))
+        x = to_dev(torch, c.x0)
+        v = torch.zeros_like(x)
+        dvp = torch.zeros_like(x)
+        pin = torch.from_numpy(c.pinned.astype(bool)).cuda()
+        for _ in range(20):
+            b = ctx.cloth_assemble(x, v, "f32")
+            for _ in range(3):
+                ctx.ws_train_step(x, v, b, dvp, lr=1e-3)
+            dv, _ = ctx.cloth_pcg_solve(b, dv=dvp.clone(), tol=1e-6, warm="learned")
+            v += dv
+            v[pin] = 0
+            x += c.h * v
+            dvp = dv
+        b = ctx.cloth_assemble(x, v, "f32")
+        start, _g = ctx.ws_start(x, v, b, dvp)
+        iters = {}
+        for mode in ("zero", "prev", "learned"):
+            dv0 = torch.zeros_like(x) if mode == "zero" else dvp.clone()
+            _, info = ctx.cloth_pcg_solve(b, dv=dv0, tol=1e-6, warm=mode)
+            assert info["rel_res_true"] <= 1e-6
+            iters[mode] = info["iters"]
+        P = oracle_mod.Problem.from_cloth(c)
+        A = P.assemble(x.cpu().numpy(), v.cpu().numpy())
+    finally:
+        ctx.close()
+    E = lambda z: 0.5 * float((z * P.spmv(A, z)).sum()) - float((A.b * z).sum())
+    e_prev, e_learned = E(dvp.cpu().numpy()), E(start.cpu().numpy())
+    print(f"held-out step: CG iterations zero {iters['zero']}, previous {iters['prev']}, "
+          f"learned {iters['learned']}; energy previous {e_prev:.6e}, learned {e_learned:.6e}")
+    assert e_learned < e_prev
+    assert iters["learned"] <= iters["zero"]
