@@ -311,7 +311,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        # arithmetic of the CG inner loop: FP32 row sums and inner vectors with
+        # BF16 blocks (textbook form), FP64 otherwise; dots, the refinement
+        # residual and the state are FP64 in every case
+        "dtype": "f32" if inner32 else "f64",
+        "precision": (f"{args.blocks} blocks; " + ("FP32 SpMV row sums and inner vectors; " if inner32 else
+                                                   "FP64 SpMV row sums and vectors; ")
+                      + "FP64 dots, refinement residual and state"),
         "data": "synthetic",
         "config": {
             "workload": f"{cloth.name}: {nt} triangles, {nv} vertices, {nh} hinges, nnzb {nnzb}"
