@@ -359,11 +359,16 @@ __global__ void k_check_contacts(int nc, int nv, const int *cv, const double *w,
     if (!ok) atomicOr(bad, 1);
 }
 
-struct RowLDS {
+// LDS of the pattern pass (incidences, their vertices, column candidates,
+// columns) and of the assembly pass, which adds the element data.  The
+// pattern kernel declares only the first, so more of its rows fit per CU.
+struct RowPatLDS {
     unsigned inc[64];
     int ev[64][4];
     unsigned cand[256];
     int cols[64];
+};
+struct RowLDS : RowPatLDS {
     double ed[64][14];   // element data of each incidence
     double fk[64][3];    // force on this row's corner of each incidence
 };
@@ -392,7 +397,7 @@ struct AsmArgs {
 };
 
 // Load the row's incidences (sorted) and the vertices of each element.
-__device__ __forceinline__ int row_load(RowLDS &L, const AsmArgs &A, int i) {
+__device__ __forceinline__ int row_load(RowPatLDS &L, const AsmArgs &A, int i) {
     const int t = threadIdx.x;
     const int p0 = A.inc_ptr[i];
     const int n = A.inc_ptr[i + 1] - p0;
@@ -428,7 +433,7 @@ __device__ __forceinline__ int row_load(RowLDS &L, const AsmArgs &A, int i) {
 // candidates (4 slots per lane, 256 in all), sorted and de-duplicated.
 // Returns the row length or -1 when it exceeds MAX_COLS; L.cols holds the
 // columns.
-__device__ __forceinline__ int row_columns(RowLDS &L, int i, int n) {
+__device__ __forceinline__ int row_columns(RowPatLDS &L, int i, int n) {
     const int t = threadIdx.x;
     unsigned c[4] = {NONE, NONE, NONE, NONE};
     if (t < n) {
@@ -479,7 +484,7 @@ __device__ __forceinline__ int row_columns(RowLDS &L, int i, int n) {
 }
 
 __global__ void __launch_bounds__(64) k_row_pattern(AsmArgs A) {
-    __shared__ RowLDS L;
+    __shared__ RowPatLDS L;
     const int i = xcd_remap(blockIdx.x, gridDim.x);
     if (i >= A.nv) return;
     const int n = row_load(L, A, i);
