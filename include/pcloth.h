@@ -307,19 +307,23 @@ pc_status pc_ws_train_step(pc_ctx *ctx, const double *x, const double *v, const 
  * the two 16x16 FP32 results, row-major (512 floats). */
 pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
 
-/* Context options (launch schedule; results do not depend on them).
+/* Context options.  The schedule options (graph chunk, slices and rows per
+ * block, LDS window, narrow columns) do not change results bit for bit,
+ * except that the rows per vector block regroup the partial sums of the CG
+ * dots; PC_OPT_INNER_FP32 changes them at the inner solves' rounding level.
  * PC_OPT_GRAPH_CHUNK: when > 0, CG iterations are captured once into a HIP
  *   graph of that many iterations (rounded up to even) and replayed on the
- *   caller's stream; the
- *   per-instance convergence flags make iterations after convergence exit at
- *   once.  0 (default): plain launches.  While pc_profile sampling is on,
- *   one chunk in 8 runs as plain launches, which the sampled events time.
+ *   caller's stream; the per-instance convergence flags make iterations
+ *   after convergence exit at once.  0 (default): plain launches.  While
+ *   pc_profile sampling is on, one chunk in 8 runs as plain launches, which
+ *   the sampled events time.
  * PC_OPT_SPMV_SLICES_PER_BLOCK: 64-row slices per SpMV work item / block
  *   (1, 2, 4, 8 (default) or 16).
  * PC_OPT_VECTOR_ROWS_PER_BLOCK: rows per work item of the CG vector kernels
- *   (multiple of 64 in [64, 4096], default 2048; 1024 threads per block).  Every block of the direction
- *   kernel sums its instance's partials of the update kernel, so fewer,
- *   larger work items cost less per iteration on large instances.
+ *   (multiple of 64 in [64, 4096], default 2048; 1024 threads per block).
+ *   Every block of the update kernel sums its instance's SpMV partials and
+ *   every block of the direction kernel its instance's update partials, so
+ *   fewer, larger work items cost less per iteration on large instances.
  * PC_OPT_LDS_WINDOW: 1 (default): each SpMV work item whose block columns
  *   span at most 4096 rows first copies that window of the search direction
  *   to LDS and gathers from there; 0: all gathers from global memory.
