@@ -26,6 +26,10 @@ struct PcgState {
     double beta, gprev, aprev;
     int iters, maxit, done, flags;   // flags: 1 breakdown (p.Ap <= 0), 2 non-finite
     int kc, pad_;                    // iterations of the current sweep (single-reduction form)
+    // textbook form: live[par] = 1 when the update of the iteration of parity
+    // par ran (its alpha is in `alpha`); the direction kernel of that iteration
+    // clears the other slot for the next one
+    int live[2];
 };
 
 // Sampled kernel timing with HIP events on the launch stream: every

@@ -103,6 +103,7 @@ __global__ void k_state_init(int ninst, PcgState *st, const uint8_t *restart, do
     S.rz0 = 0.0;
     S.beta = S.gprev = S.aprev = 0.0;
     S.kc = 0;
+    S.live[0] = S.live[1] = 0;
     S.iters = 0;
     S.maxit = maxit[i];
     S.done = 0;
@@ -143,68 +144,103 @@ __global__ void __launch_bounds__(256) k_item_windows(Sched S, const int *slice_
     }
 }
 
-// alpha, then x += alpha p, r -= alpha q over the item's rows (flat
-// component indexing: consecutive threads touch consecutive elements);
-// partials of r.z (z = P^-1 r) and r.r with r as stored.  TV: FP64 vectors, or FP32 for the
-// correction, residual and product inside a refinement sweep.  Block Jacobi
-// stages each VT-row chunk of r in LDS, then one thread per row applies the
-// inverse block and stores z.
+// One VT-row chunk of an update item, as thread t sees it: components
+// k = t, t + VT, t + 2 VT of the chunk (flat component indexing, so that
+// consecutive threads touch consecutive elements) and, for block Jacobi, the
+// inverse diagonal block of the chunk's row t.  A chunk's loads are all
+// issued before its stores, so a thread waits for memory once per chunk
+// instead of once per component.
 template <typename TV>
-__global__ void __launch_bounds__(VT) k_pcg_update(Sched S, int par, TV *x, TV *r, const float *pf, const TV *q,
-                                                    PreArgs P, PcgState *st, const double *part_s,
-                                                    double *part_u) {
+struct UpdChunk {
+    TV r[3], q[3];
+    float d[3];
+    float2 b[3];
+
+    __device__ __forceinline__ void load(int r0, int nr, const TV *r_, const TV *q_, const PreArgs &P) {
+        const int t = threadIdx.x, n3 = 3 * nr;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int k = t + u * VT;
+            if (k < n3) {
+                const int kk = 3 * r0 + k;
+                r[u] = r_[kk];
+                q[u] = q_[kk];
+                if (P.kind == 0) d[u] = P.dinv[kk];
+            }
+        }
+        if (P.kind != 0 && t < nr) {
+            const float2 *bb = (const float2 *)(P.binv + 6 * (int64_t)(r0 + t));
+            b[0] = bb[0]; b[1] = bb[1]; b[2] = bb[2];
+        }
+    }
+};
+
+// alpha, then r -= alpha q over the item's rows; partials of r.z
+// (z = P^-1 r) and r.r with r as stored.  x += alpha p is left to the
+// direction kernel, which reads p anyway.  TV: FP64 vectors, or FP32 for the
+// correction, residual and product inside a refinement sweep.  The first
+// chunk's operands are loaded before alpha is formed, so that their latency
+// overlaps the read of the SpMV's partials.  Block Jacobi stages each chunk
+// of r in LDS, then one thread per row applies the inverse block and stores z.
+template <typename TV>
+__global__ void __launch_bounds__(VT) k_pcg_update(Sched S, int par, TV *r, const TV *q, PreArgs P, PcgState *st,
+                                                    const double *part_s, double *part_u) {
     __shared__ double rs[3 * VT];
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
     if (st[I.x].done) return;
+    const int t = threadIdx.x;
+    UpdChunk<TV> cur;
+    cur.load(I.y, min(VT, I.z - I.y), r, q, P);
     // alpha = rz / p.q from the SpMV's partials (every block sums its
     // instance's in the same order, so all blocks agree bit for bit); a
-    // non-positive or non-finite p.q ends the sweep (the first block records it)
+    // non-positive or non-finite p.q ends the sweep (the first block records
+    // it), otherwise the first block hands alpha to the direction kernel
     double pq[1];
     instance_sum<1>(part_s, S.n_sitems, S.inst_sitem0[I.x], S.inst_sitem0[I.x + 1], pq);
     const double alpha = st[I.x].rzp[par] / pq[0];
+    const bool first = it == S.inst_vitem0[I.x] && t == 0;
     if (!(pq[0] > 0.0) || !isfinite(alpha)) {
-        if (it == S.inst_vitem0[I.x] && threadIdx.x == 0) {
+        if (first) {
             st[I.x].flags |= isfinite(pq[0]) ? 1 : 2;
             st[I.x].done = 1;
         }
         return;
     }
+    if (first) {
+        st[I.x].alpha = alpha;
+        st[I.x].live[par] = 1;
+    }
     double rz = 0.0, rr = 0.0;
-    if (P.kind == 0) {
-        for (int k = 3 * I.y + threadIdx.x; k < 3 * I.z; k += blockDim.x) {
-            const int i = k / 3;
-            const double pk = pf[4 * i + (k - 3 * i)];
-            x[k] = (TV)((double)x[k] + alpha * pk);
-            const TV rv = (TV)((double)r[k] - alpha * (double)q[k]);
-            r[k] = rv;
-            const double rk = rv;
-            rz += rk * rk * (double)P.dinv[k];
-            rr += rk * rk;
-        }
-    } else {
-        for (int r0 = I.y; r0 < I.z; r0 += VT) {
-            const int nr = min(VT, I.z - r0);
-            for (int k = threadIdx.x; k < 3 * nr; k += blockDim.x) {
-                const int kk = 3 * r0 + k;
-                const int i = kk / 3;
-                const double pk = pf[4 * i + (kk - 3 * i)];
-                x[kk] = (TV)((double)x[kk] + alpha * pk);
-                const TV rv = (TV)((double)r[kk] - alpha * (double)q[kk]);
-                r[kk] = rv;
+    for (int r0 = I.y; r0 < I.z; r0 += VT) {
+        const int nr = min(VT, I.z - r0);
+        if (r0 != I.y) cur.load(r0, nr, r, q, P);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int k = t + u * VT;
+            if (k < 3 * nr) {
+                const TV rv = (TV)((double)cur.r[u] - alpha * (double)cur.q[u]);
+                r[3 * r0 + k] = rv;
                 const double rk = rv;
-                rs[k] = rk;
                 rr += rk * rk;
+                if (P.kind == 0)
+                    rz += rk * rk * (double)cur.d[u];
+                else
+                    rs[k] = rk;
             }
+        }
+        if (P.kind != 0) {
             __syncthreads();
-            if ((int)threadIdx.x < nr) {
-                const int t = threadIdx.x, i = r0 + t;
+            if (t < nr) {
                 const double a0 = rs[3 * t], a1 = rs[3 * t + 1], a2 = rs[3 * t + 2];
-                double z[3];
-                precond3(P, i, a0, a1, a2, z);
-                rz += a0 * z[0] + a1 * z[1] + a2 * z[2];
-                P.z[i] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
+                const double xx = cur.b[0].x, xy = cur.b[0].y, xz = cur.b[1].x;
+                const double yy = cur.b[1].y, yz = cur.b[2].x, zz = cur.b[2].y;
+                const double z0 = xx * a0 + xy * a1 + xz * a2;
+                const double z1 = xy * a0 + yy * a1 + yz * a2;
+                const double z2 = xz * a0 + yz * a1 + zz * a2;
+                rz += a0 * z0 + a1 * z1 + a2 * z2;
+                P.z[r0 + t] = make_float4((float)z0, (float)z1, (float)z2, 0.0f);
             }
             __syncthreads();
         }
@@ -213,25 +249,59 @@ __global__ void __launch_bounds__(VT) k_pcg_update(Sched S, int par, TV *x, TV *
     block_partials<2>(v, part_u, it, S.n_vitems);
 }
 
-// beta = rz_new / rz (every block from the update's partials, fixed order),
-// then p = P^-1 r + beta p over the item's rows (Jacobi: from r and dinv;
-// block Jacobi: from the z stored by the update).  The first block of each
-// instance advances the instance state: rzp[1 - par] = rz_new, ||r||^2, the
-// iteration count and the convergence test ||r||^2 <= thresh.  Blocks that
-// see the instance converged skip the direction (it is not used again).
+// x += alpha p with the update's alpha, then beta = rz_new / rz (every block
+// from the update's partials, fixed order) and p = P^-1 r + beta p over the
+// item's rows (Jacobi: from r and dinv; block Jacobi: from the z stored by
+// the update).  The first block of each instance advances the instance
+// state: rzp[1 - par] = rz_new, ||r||^2, the iteration count and the
+// convergence test ||r||^2 <= thresh.  Blocks that see the instance
+// converged skip the direction (it is not used again) but not x.  Whether
+// the iteration is live comes from live[par], which only the update wrote;
+// `done` may be set by this launch's first block while others still read it.
+// One thread per row; the first row's operands are loaded before the
+// partial sums are read.
 template <typename TV>
-__global__ void __launch_bounds__(VT) k_pcg_dir(Sched S, int par, const TV *r, float4 *p, PreArgs P,
+struct DirRow {
+    float4 p, z;   // z: block Jacobi's stored P^-1 r
+    TV x[3];
+    TV r[3];       // Jacobi: r and dinv
+    float d[3];
+
+    __device__ __forceinline__ void load(int i, const TV *x_, const TV *r_, const float4 *p_, const PreArgs &P) {
+        p = p_[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x[c] = x_[3 * i + c];
+        if (P.kind == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                r[c] = r_[3 * i + c];
+                d[c] = P.dinv[3 * i + c];
+            }
+        } else {
+            z = P.z[i];
+        }
+    }
+};
+
+template <typename TV>
+__global__ void __launch_bounds__(VT) k_pcg_dir(Sched S, int par, TV *x, const TV *r, float4 *p, PreArgs P,
                                                  PcgState *st, const double *part_u) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
-    if (st[I.x].done) return;
+    const bool first = it == S.inst_vitem0[I.x] && threadIdx.x == 0;
+    if (first) st[I.x].live[1 - par] = 0;
+    if (!st[I.x].live[par]) return;
+    DirRow<TV> row;
+    int i = I.y + (int)threadIdx.x;
+    if (i < I.z) row.load(i, x, r, p, P);
+    const double alpha = st[I.x].alpha;
     double tot[2];
     instance_sum<2>(part_u, S.n_vitems, S.inst_vitem0[I.x], S.inst_vitem0[I.x + 1], tot);
     const double beta = tot[0] / st[I.x].rzp[par];
     const bool bad = !isfinite(tot[1]) || !isfinite(tot[0]);
     const bool conv = tot[1] <= st[I.x].thresh;
-    if (it == S.inst_vitem0[I.x] && threadIdx.x == 0) {
+    if (first) {
         PcgState &T = st[I.x];
         T.rzp[1 - par] = tot[0];
         T.rr = tot[1];
@@ -243,24 +313,28 @@ __global__ void __launch_bounds__(VT) k_pcg_dir(Sched S, int par, const TV *r, f
             T.done = 1;
         }
     }
-    if (bad || conv) return;
-    for (int i = I.y + threadIdx.x; i < I.z; i += blockDim.x) {
-        const float4 pv = p[i];
-        double z0, z1, z2;
-        if (P.kind == 0) {
-            z0 = (double)r[3 * i] * (double)P.dinv[3 * i];
-            z1 = (double)r[3 * i + 1] * (double)P.dinv[3 * i + 1];
-            z2 = (double)r[3 * i + 2] * (double)P.dinv[3 * i + 2];
-        } else {
-            const float4 zv = P.z[i];
-            z0 = zv.x; z1 = zv.y; z2 = zv.z;
+    const bool new_dir = !(bad || conv);
+    for (; i < I.z; i += VT) {
+        if (i != I.y + (int)threadIdx.x) row.load(i, x, r, p, P);
+        const float4 pv = row.p;
+        x[3 * i] = (TV)((double)row.x[0] + alpha * (double)pv.x);
+        x[3 * i + 1] = (TV)((double)row.x[1] + alpha * (double)pv.y);
+        x[3 * i + 2] = (TV)((double)row.x[2] + alpha * (double)pv.z);
+        if (new_dir) {
+            double z[3];
+            if (P.kind == 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) z[c] = (double)row.r[c] * (double)row.d[c];
+            } else {
+                z[0] = row.z.x; z[1] = row.z.y; z[2] = row.z.z;
+            }
+            float4 o;
+            o.x = (float)(z[0] + beta * pv.x);
+            o.y = (float)(z[1] + beta * pv.y);
+            o.z = (float)(z[2] + beta * pv.z);
+            o.w = 0.0f;
+            p[i] = o;
         }
-        float4 o;
-        o.x = (float)(z0 + beta * pv.x);
-        o.y = (float)(z1 + beta * pv.y);
-        o.z = (float)(z2 + beta * pv.z);
-        o.w = 0.0f;
-        p[i] = o;
     }
 }
 
@@ -461,6 +535,7 @@ __global__ void __launch_bounds__(256) k_fin_start(Sched S, int use_sitems, int 
         T.rr = tot[1];
         T.bb = tot[2];
         T.rr0 = tot[1];
+        T.live[0] = T.live[1] = 0;
         T.thresh = fmax(T.tol2 * tot[2], T.rho2 * tot[1]);
         if (!isfinite(tot[1]) || !isfinite(tot[2])) {
             T.flags |= 2;
@@ -740,8 +815,9 @@ static void launch_spmv(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids
 }
 
 // One CG iteration of parity par (the parity selects the rz slot, see
-// PcgState): SpMV with its partials, alpha, update, direction (beta from
-// the update partials, state advance).  TV: type of the iterate, residual
+// PcgState): SpMV with its partials; update (alpha, r, z); direction
+// (x += alpha p, beta from the update partials, p, state advance).  TV: type
+// of the iterate, residual
 // and product (FP64, or FP32 inside a refinement sweep, where the iterate
 // is the sweep's correction e).
 template <typename TB, typename TV>
@@ -751,11 +827,11 @@ static void launch_iter_v(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Gri
     launch_spmv<TB, TV>(ctx, M, S, g, s, q);
     ctx->prof.end(slot, s);
     slot = ctx->prof.begin(PK_UPDATE, s);
-    hipLaunchKernelGGL(k_pcg_update<TV>, dim3(g.vblocks), dim3(VT), 0, s, S, par, x, r, (const float *)ctx->p,
-                       (const TV *)q, pre_args(ctx), ctx->st, (const double *)ctx->partials, ctx->partials_u);
+    hipLaunchKernelGGL(k_pcg_update<TV>, dim3(g.vblocks), dim3(VT), 0, s, S, par, r, (const TV *)q, pre_args(ctx),
+                       ctx->st, (const double *)ctx->partials, ctx->partials_u);
     ctx->prof.end(slot, s);
     slot = ctx->prof.begin(PK_DIR, s);
-    hipLaunchKernelGGL(k_pcg_dir<TV>, dim3(g.vblocks), dim3(VT), 0, s, S, par, (const TV *)r, ctx->p,
+    hipLaunchKernelGGL(k_pcg_dir<TV>, dim3(g.vblocks), dim3(VT), 0, s, S, par, x, (const TV *)r, ctx->p,
                        pre_args(ctx), ctx->st, ctx->partials_u);
     ctx->prof.end(slot, s);
 }
