@@ -257,7 +257,10 @@ pc_status cloth_export_pattern(pc_ctx *ctx, int32_t *rowptr_out, int32_t *colidx
 
 /* Kernel timing with HIP events on the launch stream: with every > 0, one in
  * `every` launches of each timed kernel is bracketed by an event pair (0 turns
- * sampling off; any call resets the statistics).  pc_profile_read synchronises
+ * sampling off; any call resets the statistics).  Inside a CG solve only one
+ * chunk of iterations in 8 is sampled, so that the events add little to the
+ * solve's time (with graph replay that chunk runs as plain launches).
+ * pc_profile_read synchronises
  * the device and writes, for each kind k in 0..7 (0 SpMV in CG, 1 CG vector
  * update, 2 CG direction update, 3 row assembly, 4 row pattern, 5 whole
  * assembly), out[5k..5k+4] = {samples, mean ms, min ms, max ms, median ms}
@@ -315,8 +318,8 @@ pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
  *   graph of that many iterations (rounded up to even) and replayed on the
  *   caller's stream; the per-instance convergence flags make iterations
  *   after convergence exit at once.  0 (default): plain launches.  While
- *   pc_profile sampling is on, one chunk in 8 runs as plain launches, which
- *   the sampled events time.
+ *   pc_profile sampling is on, the sampled chunk (one in 8) runs as plain
+ *   launches, which the events time.
  * PC_OPT_SPMV_SLICES_PER_BLOCK: 64-row slices per SpMV work item / block
  *   (1, 2, 4, 8 (default) or 16).
  * PC_OPT_VECTOR_ROWS_PER_BLOCK: rows per work item of the CG vector kernels

@@ -1114,18 +1114,22 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
                 }
             }
             if (all_done) break;
-            // with profiling on, one chunk in 8 runs as plain launches so that
-            // the sampled events time the same kernels the graph replays
+            // with profiling on, events are recorded in one chunk in 8 only, so
+            // that they add little to the solve's time; with graph replay that
+            // chunk runs as plain launches, which the events time
             const bool sample = ctx->prof.every > 0 && (nchunk++ % 8) == 0;
             if (graph && !sample && ctx->cg_par == 0) {
                 PC_HIP(hipGraphLaunch(ctx->gexec[variant], s));
             } else {
                 int chunk = graph ? ctx->graph_chunk : (check > 0 ? check : std::min(256, std::max(16, most / 4)));
                 if (graph && ctx->cg_par != 0) chunk = 1;   // back to even parity for the graph
+                const int every = ctx->prof.every;
+                if (!sample) ctx->prof.every = 0;
                 if (inner_hi)
                     launch_iters<double>(ctx, Mhi, S, g, s, chunk);
                 else
                     launch_iters<TB>(ctx, M, S, g, s, chunk);
+                ctx->prof.every = every;
             }
             PC_HIP(hipGetLastError());
             if ((st = read_states(ctx, s))) return st;
