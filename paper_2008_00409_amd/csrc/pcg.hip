@@ -34,7 +34,7 @@
 namespace pc {
 
 // Threads per block of the vector kernels (one block per vector work item;
-// block Jacobi stages VT rows of r at a time in LDS).
+// the single-reduction vector kernel stages VT rows of r at a time in LDS).
 constexpr int VT = 1024;
 
 // Preconditioner z = P^-1 r: kind 0 Jacobi (dinv, 3 per row), kind 1 block
@@ -144,59 +144,59 @@ __global__ void __launch_bounds__(256) k_item_windows(Sched S, const int *slice_
     }
 }
 
-// One VT-row chunk of an update item, as thread t sees it: components
-// k = t, t + VT, t + 2 VT of the chunk (flat component indexing, so that
-// consecutive threads touch consecutive elements) and, for block Jacobi, the
-// inverse diagonal block of the chunk's row t.  A chunk's loads are all
-// issued before its stores, so a thread waits for memory once per chunk
-// instead of once per component.
+// Rows i0 + t + u VT (u < U) of an update item, as thread t sees them: the
+// row's three components of r and q and its preconditioner entries.
 template <typename TV>
-struct UpdChunk {
-    TV r[3], q[3];
-    float d[3];
-    float2 b[3];
+struct UpdRows {
+    static constexpr int U = 1;   // rows per thread in flight (2 needs more than 64 VGPRs)
+    TV r[U][3], q[U][3];
+    float d[U][3];
+    float2 b[U][3];
 
-    __device__ __forceinline__ void load(int r0, int nr, const TV *r_, const TV *q_, const PreArgs &P) {
-        const int t = threadIdx.x, n3 = 3 * nr;
+    __device__ __forceinline__ void load(int i0, int i1, const TV *r_, const TV *q_, const PreArgs &P) {
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            const int k = t + u * VT;
-            if (k < n3) {
-                const int kk = 3 * r0 + k;
-                r[u] = r_[kk];
-                q[u] = q_[kk];
-                if (P.kind == 0) d[u] = P.dinv[kk];
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + (int)threadIdx.x + u * VT;
+            if (i < i1) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    r[u][c] = r_[3 * i + c];
+                    q[u][c] = q_[3 * i + c];
+                }
+                if (P.kind == 0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) d[u][c] = P.dinv[3 * i + c];
+                } else {
+                    const float2 *bb = (const float2 *)(P.binv + 6 * (int64_t)i);
+                    b[u][0] = bb[0]; b[u][1] = bb[1]; b[u][2] = bb[2];
+                }
             }
-        }
-        if (P.kind != 0 && t < nr) {
-            const float2 *bb = (const float2 *)(P.binv + 6 * (int64_t)(r0 + t));
-            b[0] = bb[0]; b[1] = bb[1]; b[2] = bb[2];
         }
     }
 };
 
 // alpha, then r -= alpha q over the item's rows; partials of r.z
-// (z = P^-1 r) and r.r with r as stored.  x += alpha p is left to the
-// direction kernel, which reads p anyway.  TV: FP64 vectors, or FP32 for the
-// correction, residual and product inside a refinement sweep.  The first
-// chunk's operands are loaded before alpha is formed, so that their latency
-// overlaps the read of the SpMV's partials.  Block Jacobi stages each chunk
-// of r in LDS, then one thread per row applies the inverse block and stores z.
+// (z = P^-1 r) and r.r with r as stored; block Jacobi stores z.  x += alpha p
+// is left to the direction kernel, which reads p anyway.  TV: FP64 vectors,
+// or FP32 for the correction, residual and product inside a refinement
+// sweep.  One thread per row (all of a row's operands are then in one thread,
+// so neither Jacobi form needs LDS or a barrier); the first rows' operands
+// are loaded before alpha is formed, so that their latency overlaps the read
+// of the SpMV's partials.  alpha = rz / p.q comes from the SpMV's partials
+// (every block sums its instance's in the same order, so all blocks agree bit
+// for bit); a non-positive or non-finite p.q ends the sweep (the first block
+// records it), otherwise the first block hands alpha to the direction kernel.
 template <typename TV>
 __global__ void __launch_bounds__(VT) k_pcg_update(Sched S, int par, TV *r, const TV *q, PreArgs P, PcgState *st,
                                                     const double *part_s, double *part_u) {
-    __shared__ double rs[3 * VT];
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
     if (st[I.x].done) return;
     const int t = threadIdx.x;
-    UpdChunk<TV> cur;
-    cur.load(I.y, min(VT, I.z - I.y), r, q, P);
-    // alpha = rz / p.q from the SpMV's partials (every block sums its
-    // instance's in the same order, so all blocks agree bit for bit); a
-    // non-positive or non-finite p.q ends the sweep (the first block records
-    // it), otherwise the first block hands alpha to the direction kernel
+    constexpr int G = UpdRows<TV>::U * VT;
+    UpdRows<TV> cur;
+    cur.load(I.y, I.z, r, q, P);
     double pq[1];
     instance_sum<1>(part_s, S.n_sitems, S.inst_sitem0[I.x], S.inst_sitem0[I.x + 1], pq);
     const double alpha = st[I.x].rzp[par] / pq[0];
@@ -213,36 +213,35 @@ __global__ void __launch_bounds__(VT) k_pcg_update(Sched S, int par, TV *r, cons
         st[I.x].live[par] = 1;
     }
     double rz = 0.0, rr = 0.0;
-    for (int r0 = I.y; r0 < I.z; r0 += VT) {
-        const int nr = min(VT, I.z - r0);
-        if (r0 != I.y) cur.load(r0, nr, r, q, P);
+    for (int i0 = I.y; i0 < I.z; i0 += G) {
+        if (i0 != I.y) cur.load(i0, I.z, r, q, P);
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            const int k = t + u * VT;
-            if (k < 3 * nr) {
-                const TV rv = (TV)((double)cur.r[u] - alpha * (double)cur.q[u]);
-                r[3 * r0 + k] = rv;
-                const double rk = rv;
-                rr += rk * rk;
-                if (P.kind == 0)
-                    rz += rk * rk * (double)cur.d[u];
-                else
-                    rs[k] = rk;
+        for (int u = 0; u < UpdRows<TV>::U; ++u) {
+            const int i = i0 + t + u * VT;
+            if (i < I.z) {
+                TV rv[3];
+                double rk[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    rv[c] = (TV)((double)cur.r[u][c] - alpha * (double)cur.q[u][c]);
+                    rk[c] = rv[c];
+                    rr += rk[c] * rk[c];
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) r[3 * i + c] = rv[c];
+                if (P.kind == 0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) rz += rk[c] * rk[c] * (double)cur.d[u][c];
+                } else {
+                    const double xx = cur.b[u][0].x, xy = cur.b[u][0].y, xz = cur.b[u][1].x;
+                    const double yy = cur.b[u][1].y, yz = cur.b[u][2].x, zz = cur.b[u][2].y;
+                    const double z0 = xx * rk[0] + xy * rk[1] + xz * rk[2];
+                    const double z1 = xy * rk[0] + yy * rk[1] + yz * rk[2];
+                    const double z2 = xz * rk[0] + yz * rk[1] + zz * rk[2];
+                    rz += rk[0] * z0 + rk[1] * z1 + rk[2] * z2;
+                    P.z[i] = make_float4((float)z0, (float)z1, (float)z2, 0.0f);
+                }
             }
-        }
-        if (P.kind != 0) {
-            __syncthreads();
-            if (t < nr) {
-                const double a0 = rs[3 * t], a1 = rs[3 * t + 1], a2 = rs[3 * t + 2];
-                const double xx = cur.b[0].x, xy = cur.b[0].y, xz = cur.b[1].x;
-                const double yy = cur.b[1].y, yz = cur.b[2].x, zz = cur.b[2].y;
-                const double z0 = xx * a0 + xy * a1 + xz * a2;
-                const double z1 = xy * a0 + yy * a1 + yz * a2;
-                const double z2 = xz * a0 + yz * a1 + zz * a2;
-                rz += a0 * z0 + a1 * z1 + a2 * z2;
-                P.z[r0 + t] = make_float4((float)z0, (float)z1, (float)z2, 0.0f);
-            }
-            __syncthreads();
         }
     }
     double v[2] = {rz, rr};
