@@ -324,6 +324,7 @@ def main():
                         + ("" if contacts is None else f", {contacts.n} proximity pairs"),
             "h": cloth.h, "tol": tol, "block_storage": args.blocks, "warm_start": args.warm,
             "refinement_sweeps": [i["sweeps"] for i in infos], "starts_used": [i["warm_used"] for i in infos],
+            "fallback_steps": sum(1 for i in infos if i["fallback"]),   # steps that fell back to FP64 blocks
             "preconditioner": args.precond, "inner_rho": args.inner_rho, "cg_form": args.method,
             "cg_iters_per_step": {"mean": float(np.mean(iters)), "min": int(min(iters)), "max": int(max(iters))},
             "rel_res_true_max": max(i["rel_res_true"] for i in infos),

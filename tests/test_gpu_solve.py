@@ -128,6 +128,38 @@ def test_solve_edge_cases(torch, B, oracle_mod):
         ctx.close()
 
 
+@pytest.mark.parametrize("precond", ["jacobi", "block"])
+@pytest.mark.parametrize("chunk", [0, 16])
+def test_iteration_budget_returns_kth_iterate(torch, B, oracle_mod, precond, chunk):
+    """A sweep ended by the iteration budget returns the k-th CG iterate from
+    the zero start (FP64 blocks): it matches the oracle's k-th iterate, and the
+    (k-1)-th is far from it, so the last iteration's x += alpha p is in the
+    result.  With 16-iteration graph chunks the launches past the budget must
+    leave x alone.  Bar: the preconditioners are stored in FP32, which moves
+    the k-th iterate by about 2e-8 of its largest entry in the oracle; a lost
+    final update moves it by 0.09 to 0.36."""
+    c = sheet(24, 20, seed=21)
+    v = random_velocity(c, 0.05, seed=22)
+    P = oracle_mod.Problem.from_cloth(c)
+    A = P.assemble(c.x0, v)
+    ctx = B.Context.from_cloth(c)
+    try:
+        ctx.set_option(B.PC_OPT_GRAPH_CHUNK, chunk)
+        b = ctx.cloth_assemble(to_dev(torch, c.x0), to_dev(torch, v), "f64")
+        for k in (5, 12):
+            dv, info = ctx.cloth_pcg_solve(b, tol=1e-14, maxit=k, precond=precond, raise_on_error=False)
+            assert info["status"] == B.PC_ERR_NOT_CONVERGED and info["iters"] == k
+            xk, oinfo = P.pcg(A, tol=1e-14, maxit=k, precond=precond)
+            xprev, _ = P.pcg(A, tol=1e-14, maxit=k - 1, precond=precond)
+            assert oinfo["iters"] == k
+            scale = np.abs(xk).max()
+            err = np.abs(dv.cpu().numpy() - xk).max() / scale
+            assert err <= 1e-5, (k, err)
+            assert np.abs(xprev - xk).max() / scale > 1e-2
+    finally:
+        ctx.close()
+
+
 def test_solve_deterministic(torch, B):
     c = sheet(40, 40, seed=13, flips=0.1)
     ctx = B.Context.from_cloth(c)
