@@ -350,8 +350,9 @@ pc_status pc_get_option(pc_ctx *ctx, int32_t option, int64_t *value);
 
 /* Autotuner: on the assembled system and right-hand side b (device nv*3),
  * time `iters` CG iterations for every candidate schedule (slices per SpMV
- * block 2/4/8/16 x rows per vector block 1024/2048/4096 x graph chunk 0/32)
- * with HIP events on the stream, and keep the fastest.  precond: the
+ * block 2/4/8/16 x rows per vector block 1024/2048/4096 and, for k = 1, 2, the
+ * smallest multiple of 64 giving at most k vector work items per compute unit
+ * x graph chunk 0/32) with HIP events on the stream, and keep the fastest.  precond: the
  * preconditioner the iterations use (as pc_solve_opts.precond).  chosen
  * (host, optional) receives {slices per block, rows per block, graph chunk};
  * ms_per_iter (host, optional) the best time per iteration.  Overwrites the

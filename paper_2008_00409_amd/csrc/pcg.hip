@@ -1292,8 +1292,28 @@ pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, fl
         return PC_ERR_ARG;
     }
     const int spbs[4] = {2, 4, 8, 16};
-    const int rpbs[3] = {1024, 2048, 4096};
     const int chunks[2] = {0, 32};
+    // rows per vector block: fixed sizes, plus for k = 1, 2 the smallest
+    // multiple of 64 that gives at most k work items per compute unit over all
+    // instances.  The vector kernels then run in one round with every CU
+    // holding k blocks, so no CU still runs an extra block at the end of the
+    // launch (at 1.65M rows 2,048-row items leave 149 of 256 CUs with two).
+    std::vector<int> rpbs = {1024, 2048, 4096};
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0) {
+        for (int k = 1; k <= 2; ++k) {
+            for (int rp = 64; rp <= 4096; rp += 64) {
+                int64_t n = 0;
+                for (size_t i = 0; i + 1 < ctx->inst_row0_h.size(); ++i)
+                    n += (ctx->inst_row0_h[i + 1] - ctx->inst_row0_h[i] + rp - 1) / rp;
+                if (n <= (int64_t)k * ncu) {
+                    if (std::find(rpbs.begin(), rpbs.end(), rp) == rpbs.end()) rpbs.push_back(rp);
+                    break;
+                }
+            }
+        }
+    }
     float best = 1e30f;
     int bs = ctx->spb, br = ctx->rpb, bc = ctx->graph_chunk;
     const bool was = ctx->assembled;
