@@ -81,11 +81,28 @@ def cpu_baseline(cloth, gpu_iters_per_step, seconds_budget=25.0, contacts=None):
     P.pcg_fixed(A, n2)
     t_it = (time.perf_counter() - t0) / n2
     t_step = t_asm + gpu_iters_per_step * t_it
-    return {"value": 1.0 / t_step, "unit": "steps/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": (f"FP64 oracle on {cloth.name}: one assembly ({t_asm:.2f} s) and {n2} Jacobi-PCG "
-                       f"iterations ({1e3 * t_it:.1f} ms each), steps/s = 1/(assembly + "
-                       f"{gpu_iters_per_step:.0f} iterations), the GPU's mean iterations per step at the "
-                       f"same tolerance")}
+    cores = oracle.num_threads()
+    rec = {"value": 1.0 / t_step, "unit": "steps/s", "cores": cores, "kind": "oracle",
+           "sample": (f"FP64 oracle on {cloth.name}: one assembly ({t_asm:.2f} s) and {n2} Jacobi-PCG "
+                      f"iterations ({1e3 * t_it:.1f} ms each), steps/s = 1/(assembly + "
+                      f"{gpu_iters_per_step:.0f} iterations), the GPU's mean iterations per step at the "
+                      f"same tolerance")}
+    # the same on one host thread (one assembly and 10 iterations)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        A1 = P.assemble(cloth.x0, cloth.v0)
+        t_asm1 = time.perf_counter() - t0
+        n1 = 10
+        t0 = time.perf_counter()
+        P.pcg_fixed(A1, n1)
+        t_it1 = (time.perf_counter() - t0) / n1
+    finally:
+        oracle.set_threads(cores)
+    rec["single_thread"] = {
+        "value": 1.0 / (t_asm1 + gpu_iters_per_step * t_it1), "unit": "steps/s", "cores": 1,
+        "sample": f"one assembly ({t_asm1:.2f} s) and {n1} iterations ({1e3 * t_it1:.1f} ms each), extrapolated alike"}
+    return rec
 
 
 def time_steps(ctx, x, v, steps, warmup, blocks, tol, warm, prof_every, precond="jacobi", inner_rho=0.0,
