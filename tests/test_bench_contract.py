@@ -1,0 +1,32 @@
+"""Host-side parts of the benchmark's contract (no GPU): a request for more
+than one GPU ends with a message and exit status 2 before any device work,
+and the SpMV byte model that the roofline divides by the measured launch
+time gives the per-launch figures used at 1.65M triangles (828,153 rows,
+10,617,589 blocks of the flipped sheets): per block its stored values plus
+a 2-byte column offset, per row the float4 input, the product and the FP64
+mass, plus the row pointers."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert p.returncode == 2
+    assert "one GPU only" in p.stderr and p.stdout == ""
+
+
+def test_spmv_byte_model_at_full_size():
+    nv, nnzb = 828153, 10617589
+    # BF16 blocks (18 B), FP32 product (12 B per row)
+    assert bench.spmv_bytes(nv, nnzb, "bf16", 2, 12) == nnzb * 20 + nv * 36 + 4 * (nv + 1) == 245477904
+    # FP32 blocks (36 B), FP64 product (24 B per row)
+    assert bench.spmv_bytes(nv, nnzb, "f32", 2, 24) == nnzb * 38 + nv * 48 + 4 * (nv + 1) == 446532342
+    # 32-bit columns add 2 B per block
+    assert bench.spmv_bytes(nv, nnzb, "bf16", 4, 12) - bench.spmv_bytes(nv, nnzb, "bf16", 2, 12) == 2 * nnzb
