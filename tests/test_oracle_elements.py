@@ -219,3 +219,100 @@ def test_hinge_rest_coefficient_closed_form(oracle_mod):
     ch, tb = oracle_mod.rest_hinges(X, np.array([[0, 1, 2, 3]]))
     assert ch[0] == pytest.approx(6.0, rel=1e-14)
     assert tb[0] == pytest.approx(0.0, abs=1e-15)
+
+
+# ------------------------------------------------- PSD part of the stress
+def _deformed_unit_triangle(S, R):
+    """Corners of the unit right triangle (rest legs along x and y, so B = I
+    and A0 = 1/2) deformed so that its StVK stress is the given symmetric S,
+    then rotated by R.  The strain follows from inverting S = 2 mu G + lam
+    tr(G) I; the in-plane deformation is the symmetric square root of
+    C = I + 2 G (taken with eigh)."""
+    trG = np.trace(S) / (2 * MU + 2 * LAM)
+    G = (S - LAM * trG * np.eye(2)) / (2 * MU)
+    w, V = np.linalg.eigh(np.eye(2) + 2 * G)
+    assert w.min() > 0
+    F2 = V @ np.diag(np.sqrt(w)) @ V.T
+    rest2 = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    x = np.zeros((3, 3))
+    x[:, :2] = rest2 @ F2.T
+    return x @ R.T
+
+
+def _psd_correction_from_K(oracle_mod, x):
+    """S+ - S read off the oracle's stiffness: solver-mode K minus exact K is
+    A0 (beta_k^T (S+ - S) beta_l) I_3 per block (k, l); with beta_1 = (1, 0)
+    and beta_2 = (0, 1) the blocks (1,1), (1,2), (2,2) give the three entries.
+    Also checks that every block of the difference is a multiple of I_3."""
+    X = np.array([[0, 0, 0], [1.0, 0, 0], [0, 1.0, 0]])
+    B, A0 = oracle_mod.rest_triangles(X, np.array([[0, 1, 2]]))
+    np.testing.assert_allclose(B[0], [1, 0, 0, 1], atol=1e-15)
+    Ks = oracle_mod.stretch_K(x.ravel(), B[0], A0[0], MU, LAM, exact=False)
+    Ke = oracle_mod.stretch_K(x.ravel(), B[0], A0[0], MU, LAM, exact=True)
+    D = (Ks - Ke).reshape(3, 3, 3, 3) / A0[0]          # (k, a, l, b)
+    scale = np.abs(Ke).max()
+    for k in range(3):
+        for l in range(3):
+            blk = D[k, :, l, :]
+            np.testing.assert_allclose(blk, blk[0, 0] * np.eye(3), atol=1e-12 * scale)
+    return np.array([[D[1, 0, 1, 0], D[1, 0, 2, 0]], [D[2, 0, 1, 0], D[2, 0, 2, 0]]])
+
+
+def _psd_by_eigh(S):
+    w, V = np.linalg.eigh(S)
+    return V @ np.diag(np.maximum(w, 0.0)) @ V.T
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_stretch_psd_projection_matches_eigh_mixed_sign(oracle_mod, seed):
+    """Solver Jacobian of Eq. 3 (Sec. 2.5): the geometric-stiffness term uses
+    the positive part of the 2x2 stress.  For stresses with one positive and
+    one negative eigenvalue (the indefinite case, in any orientation), the
+    S+ that the oracle applies equals numpy's eigendecomposition with the
+    negative eigenvalue set to zero."""
+    rng = np.random.default_rng(700 + seed)
+    ang = rng.uniform(0, np.pi)
+    Q = np.array([[np.cos(ang), -np.sin(ang)], [np.sin(ang), np.cos(ang)]])
+    s_pos, s_neg = rng.uniform(1.0, 40.0), -rng.uniform(1.0, 40.0)
+    S = Q @ np.diag([s_pos, s_neg]) @ Q.T
+    x = _deformed_unit_triangle(S, rand_rot(rng))
+    got = _psd_correction_from_K(oracle_mod, x)
+    want = _psd_by_eigh(S) - S
+    np.testing.assert_allclose(got, want, atol=1e-9 * np.abs(S).max())
+
+
+@pytest.mark.parametrize("ang_deg", [0.0, 30.0, 90.0, 135.0])
+def test_stretch_psd_projection_stretched_x_compressed_y(oracle_mod, ang_deg):
+    """A triangle stretched by 2% along one in-plane direction and compressed
+    by 1% across it (direction at ang_deg to the first leg; 0 and 90 degrees
+    take the diagonal-stress branch, the others the general one): the
+    oracle's S+ - S equals the eigh projection of the stress computed from
+    that deformation, and is nonzero."""
+    a = np.deg2rad(ang_deg)
+    d = np.array([np.cos(a), np.sin(a)])
+    n = np.array([-d[1], d[0]])
+    F2 = 1.02 * np.outer(d, d) + 0.99 * np.outer(n, n)
+    G = 0.5 * (F2.T @ F2 - np.eye(2))
+    S = 2 * MU * G + LAM * np.trace(G) * np.eye(2)
+    w = np.linalg.eigvalsh(S)
+    assert w[0] < 0 < w[1]
+    rest2 = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    x = np.zeros((3, 3))
+    x[:, :2] = rest2 @ F2.T
+    got = _psd_correction_from_K(oracle_mod, x)
+    want = _psd_by_eigh(S) - S
+    assert np.abs(want).max() > 1.0
+    np.testing.assert_allclose(got, want, atol=1e-9 * np.abs(S).max())
+
+
+def test_stretch_psd_projection_definite_cases(oracle_mod):
+    """Both eigenvalues positive: no change (S+ = S).  Both negative: the
+    whole stress term is dropped (S+ = 0)."""
+    rng = np.random.default_rng(77)
+    for sgn in (1.0, -1.0):
+        ang = rng.uniform(0, np.pi)
+        Q = np.array([[np.cos(ang), -np.sin(ang)], [np.sin(ang), np.cos(ang)]])
+        S = sgn * Q @ np.diag([rng.uniform(1, 30), rng.uniform(1, 30)]) @ Q.T
+        got = _psd_correction_from_K(oracle_mod, _deformed_unit_triangle(S, rand_rot(rng)))
+        want = np.zeros((2, 2)) if sgn > 0 else -S
+        np.testing.assert_allclose(got, want, atol=1e-9 * np.abs(S).max())

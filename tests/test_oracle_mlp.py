@@ -95,6 +95,98 @@ def test_adam_first_step_closed_form(M):
     np.testing.assert_allclose(delta, -1e-3 * gflat / (np.abs(gflat) + 1e-8), rtol=1e-12)
 
 
+def test_adam_constant_gradient_every_step(M):
+    """With the same gradient g at every step, the bias-corrected moments are
+    m_hat = g and v_hat = g^2 at every t (m_t = (1 - b1^t) g, v_t = (1 - b2^t)
+    g^2), so every update is -lr g / (|g| + eps), not only the first."""
+    params = M.init_params(4)
+    rng = np.random.default_rng(8)
+    grads = [[rng.normal(size=W.shape), rng.normal(size=c.shape)] for W, c in params]
+    gflat = M.flatten(grads)
+    state = {}
+    for t in range(1, 6):
+        before = M.flatten(params)
+        M.adam_step(params, grads, state, lr=2e-3)
+        delta = M.flatten(params) - before
+        np.testing.assert_allclose(delta, -2e-3 * gflat / (np.abs(gflat) + 1e-8), rtol=1e-9,
+                                   err_msg=f"step {t}")
+
+
+def test_adam_alternating_gradient_closed_form(M):
+    """Gradient +g, -g, +g: worked by hand from the moment recurrences
+    (b1 = 0.9, b2 = 0.999).  v_hat = g^2 at every step since |g| is constant;
+    m_1 = 0.1 g -> m_hat = g; m_2 = 0.09 g - 0.1 g = -0.01 g -> m_hat = -g/19
+    (1 - 0.81 = 0.19); m_3 = -0.009 g + 0.1 g = 0.091 g -> m_hat = 91 g/271
+    (1 - 0.729 = 0.271).  Updates: -lr g/(|g|+eps) times 1, -1/19, 91/271."""
+    params = M.init_params(6)
+    rng = np.random.default_rng(9)
+    g = [[rng.normal(size=W.shape), rng.normal(size=c.shape)] for W, c in params]
+    gflat = M.flatten(g)
+    unit = gflat / (np.abs(gflat) + 1e-8)
+    state = {}
+    for sign, factor in ((1.0, 1.0), (-1.0, -1.0 / 19.0), (1.0, 91.0 / 271.0)):
+        gs = [[sign * W, sign * c] for W, c in g]
+        before = M.flatten(params)
+        M.adam_step(params, gs, state, lr=1e-3)
+        delta = M.flatten(params) - before
+        np.testing.assert_allclose(delta, -1e-3 * factor * unit, rtol=1e-8, atol=1e-18)
+
+
+def test_features_written_out_per_vertex(M, oracle_mod):
+    """Every feature group of three vertices written out from its definition:
+    neighbours from the oracle's dense matrix (nonzero off-diagonal blocks of
+    row i), diag(A) from the dense diagonal, plain Python sums."""
+    c, P, A, x, v = small_system(oracle_mod)
+    rng = np.random.default_rng(12)
+    dvp = rng.normal(size=x.shape)
+    ell, h = 0.2, c.h
+    sv = ell / h
+    F = M.features(P.rowptr, P.colidx, x, v, A.b, A.diag, c.mass, c.pinned, dvp, ell, h)
+    Ad = A.dense()
+    nv = x.shape[0]
+    pat = np.zeros((nv, nv), dtype=bool)
+    for i in range(nv):
+        for j in P.colidx[P.rowptr[i]:P.rowptr[i + 1]]:
+            pat[i, j] = True
+    for i in (0, 9, 17):
+        nb = [j for j in range(nv) if j != i and pat[i, j]]
+        d = np.array([Ad[3 * i + a, 3 * i + a] for a in range(3)])
+        m = c.mass[i]
+        mean = lambda arr: sum(arr[j] for j in nb) / len(nb)
+        bm = A.b / c.mass[:, None]
+        want = np.concatenate([
+            v[i] / sv, (A.b[i] / m) / sv, dvp[i] / sv, mean(dvp) / sv, (A.b[i] / d) / sv,
+            (mean(bm) - bm[i]) / sv, (mean(v) - v[i]) / sv, (mean(x) - x[i]) / ell,
+            [float(c.pinned[i])], [np.log10(d.mean() / m)], [len(nb) / 12.0]])
+        np.testing.assert_allclose(F[i], want, rtol=1e-12, atol=1e-14)
+
+
+def test_features_invariances(M, oracle_mod):
+    """Features 3-5 and 15-17 are linear in b; 6-8 and 9-11 linear in the
+    previous increment; the Laplacian features (15-17, 18-20, 21-23) vanish
+    for constant fields (b/m, v, a translation of x); feature 25 is unchanged
+    when diag(A) and the masses are scaled together, and is 0 for a pinned
+    vertex (diag(A)_i = m_i)."""
+    c, P, A, x, v = small_system(oracle_mod)
+    rng = np.random.default_rng(13)
+    dvp = rng.normal(size=x.shape)
+    ell, h = 0.2, c.h
+    f = lambda x_, v_, b_, dg, m_, dv_: M.features(P.rowptr, P.colidx, x_, v_, b_, dg, m_, c.pinned, dv_, ell, h)
+    F = f(x, v, A.b, A.diag, c.mass, dvp)
+    F2 = f(x, v, 3 * A.b, A.diag, c.mass, -2 * dvp)
+    np.testing.assert_allclose(F2[:, 3:6], 3 * F[:, 3:6], rtol=1e-13)
+    np.testing.assert_allclose(F2[:, 15:18], 3 * F[:, 15:18], rtol=1e-12, atol=1e-14 * np.abs(F[:, 15:18]).max())
+    np.testing.assert_allclose(F2[:, 6:12], -2 * F[:, 6:12], rtol=1e-13)
+    const = np.tile([0.3, -1.2, 2.0], (x.shape[0], 1))
+    Fc = f(const, const, const * c.mass[:, None], A.diag, c.mass, dvp)
+    np.testing.assert_allclose(Fc[:, 15:24], 0.0, atol=1e-12 * np.abs(const).max() / min(ell, h))
+    F4 = f(x, v, A.b, 5 * A.diag, 5 * c.mass, dvp)
+    np.testing.assert_allclose(F4[:, 25], F[:, 25], rtol=1e-13, atol=1e-15)
+    pinned = np.flatnonzero(c.pinned == 1)
+    assert pinned.size > 0
+    np.testing.assert_allclose(F[pinned, 25], 0.0, atol=1e-15)
+
+
 def test_features_definitions_and_invariance(M, oracle_mod):
     c, P, A, x, v = small_system(oracle_mod)
     rng = np.random.default_rng(4)
