@@ -52,8 +52,21 @@ typedef enum {
                                   element corners, 64 distinct block columns) */
 } pc_status;
 
-/* Storage type of the matrix blocks.  Arithmetic is FP64 in every case. */
+/* Storage type of the matrix blocks.  The assembly evaluates every element
+ * and sums every block in FP64 and then rounds to this type.  The state,
+ * b, the dots of the CG recurrences and the refinement residual b - A dv
+ * (through the FP64 copy of the blocks) stay FP64 for every type.  With FP32
+ * or FP64 blocks the CG product accumulates in FP64.  With BF16 blocks the
+ * CG product's row sums are FP32, and (PC_OPT_INNER_FP32, the default) each
+ * refinement sweep keeps its correction, residual and product in FP32; the
+ * sweep's start residual and the final convergence test are FP64. */
 typedef enum { PC_F64 = 0, PC_F32 = 1, PC_BF16 = 2 } pc_dtype;
+
+/* Device memory allocator of a context (pc_set_allocator): alloc returns
+ * `bytes` of device memory on the current device (NULL on failure), free
+ * releases a block that alloc returned.  `user` is passed through. */
+typedef void *(*pc_alloc_fn)(size_t bytes, void *user);
+typedef void (*pc_free_fn)(void *ptr, void *user);
 
 typedef struct {
     double h;            /* time step (s) */
@@ -126,16 +139,43 @@ typedef struct {
                                   network's correction) */
 } pc_solve_info;
 
-/* Create a context: copies the mesh to the device, derives the rest shape
- * data (per-triangle inverse rest frame and area, per-hinge coefficient and
- * rest angle) and the hinge list (one per interior edge) on the GPU.
- * Ownership: *out is owned by the caller and released by pc_destroy.
+/* Create a context for one cloth (or several, pc_set_instances): the
+ * problem statement of Sec. 2.5 (Eq. 1-3) fixes its inputs, i.e. the
+ * triangle mesh with its rest shape (the reference configuration of the
+ * elastic forces), the lumped masses M, the Dirichlet vertices and the
+ * material constants and time step of Eq. 3 (params).  pc_create copies the
+ * mesh to the device, derives the rest shape data (per-triangle inverse rest
+ * frame and area, per-hinge coefficient and rest angle) and the hinge list
+ * (one per interior edge; the bending elements, Sec. 5) on the GPU.
+ * Ownership: *out is owned by the caller and released by pc_destroy; the
+ * host mesh arrays are only read during the call.  Device memory comes from
+ * the allocator installed with pc_set_allocator(NULL, ...), else hipMalloc.
  * Errors: PC_ERR_ARG (sizes, null), PC_ERR_MESH (index out of range,
  * degenerate rest triangle, non-manifold or misoriented mesh), PC_ERR_OOM,
  * PC_ERR_HIP.  Synchronises the default stream. */
 pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out);
+/* Release a context and every device buffer it owns (each returned to the
+ * allocator it came from), after draining the device.  The caller's x, v,
+ * b and dv buffers are not touched.  PC_ERR_ARG for NULL. */
 pc_status pc_destroy(pc_ctx *ctx);
+/* Replace the time step and material constants of Eq. 3 for the following
+ * assemblies (same checks as pc_create). */
 pc_status pc_set_params(pc_ctx *ctx, const pc_params *params);
+/* Device memory of the library.  With ctx != NULL, the context's following
+ * device allocations (workspaces, the assembled matrix, buffers that grow
+ * with contact sets or schedules, the warm-start network's state) call
+ * alloc, and each block goes back to the free routine of the allocator that
+ * allocated it, so allocators may be switched at any time.  With ctx ==
+ * NULL the pair becomes the default of contexts created afterwards,
+ * including pc_create's own buffers.  alloc = free = NULL restores
+ * hipMalloc / hipFree; giving only one is PC_ERR_ARG.  Before a block goes
+ * back to a caller's free routine the library synchronises the device,
+ * since such an allocator (a caching allocator such as PyTorch's) may hand
+ * the block out again at once; this happens only when a buffer grows and at
+ * pc_destroy.  Pinned host staging (a few bytes per instance) stays with
+ * hipHostMalloc.  The routines are called from the thread that calls the
+ * library. */
+pc_status pc_set_allocator(pc_ctx *ctx, pc_alloc_fn alloc, pc_free_fn free, void *user);
 const char *pc_last_error(const pc_ctx *ctx);   /* NULL ctx: last pc_create error */
 
 /* Topology sizes: [nv, nt, nhinges, nnzb capacity]. */
@@ -164,25 +204,34 @@ pc_status cloth_assemble(pc_ctx *ctx, const double *x, const double *v, pc_dtype
  * of the stored blocks does not disturb the mass term.  CG runs on the
  * solver copy of the blocks (the assembled dtype); each sweep starts from the
  * residual b - A dv computed with the FP64 copy, and sweeps repeat (iterative
- * refinement) until that FP64 residual meets tol.  Dots and all
- * accumulation are FP64; vectors are FP64 except the search direction
- * (FP32) and, with BF16 blocks and PC_OPT_INNER_FP32, the sweep's
- * correction, residual and product (FP32; x stays FP64).
+ * refinement) until that FP64 residual meets tol.  Dots accumulate in
+ * FP64.  The product accumulates in FP64 for FP32 and FP64 blocks and in
+ * FP32 for BF16 blocks (whose values carry 8 significant bits).  Vectors
+ * are FP64 except the search direction (FP32) and, with BF16 blocks and
+ * PC_OPT_INNER_FP32, the sweep's correction, residual and product (FP32;
+ * x stays FP64).  The sweep's start residual and the final test use FP64
+ * vectors and the FP64 blocks, so the returned dv meets tol through an FP64
+ * matrix whatever the storage.
  * dv: device nv*3 doubles, the start when opts->warm = 1, the solution on
  * return (also when PC_ERR_NOT_CONVERGED).  info: host, optional.
  * Synchronises the stream. */
 pc_status cloth_pcg_solve(pc_ctx *ctx, const double *b, double *dv, const pc_solve_opts *opts,
                           pc_solve_info *info, void *stream);
 
-/* nsteps backward-Euler steps: assemble, solve, v += dv, x += h v (pinned
- * vertices keep x, and v = 0).  x, v: device nv*3 doubles, updated in place.
- * A step whose solve fails (not converged, non-finite) is not committed and
- * the call returns that status.  infos: host array of nsteps, optional.
+/* nsteps backward-Euler steps of Eq. 3 (Sec. 2.5): assemble A and b at
+ * (x, v) (Sec. 3.2), solve A dv = b (Sec. 3.1), then v += dv (dv is the
+ * velocity increment of Eq. 3) and x += h v (pinned vertices keep x, and
+ * v = 0).  x, v: device nv*3 doubles, updated in place.
+ * A step whose solve fails (not converged, non-finite) is not committed:
+ * x and v keep the values they had before that step, bit for bit, and the
+ * call returns that status (infos[k] of the failed step is still filled).
+ * infos: host array of nsteps, optional.
  * The previous step's dv is used as the start when opts->warm = 1. */
 pc_status cloth_step(pc_ctx *ctx, double *x, double *v, int32_t nsteps, pc_dtype dtype,
                      const pc_solve_opts *opts, pc_solve_info *infos, void *stream);
 
-/* y = A x with the assembled matrix (difference form, FP64 accumulation),
+/* y = A x with the assembled matrix (difference form; FP64 accumulation,
+ * FP32 row sums of the BF16 copy),
  * using the FP64 blocks (solver_blocks = 0) or the solver copy in the
  * assembled dtype (solver_blocks = 1).  x, y: device nv*3 doubles. */
 pc_status cloth_spmv(pc_ctx *ctx, const double *x, double *y, int32_t solver_blocks, void *stream);
@@ -274,8 +323,10 @@ pc_status pc_profile_read(pc_ctx *ctx, double *out);
  * (s_v = mean rest edge length / h).  As the CG start of Eq. 3 (warm = 2) it
  * is dv_prev + g u with the step g = u.(b - A dv_prev) / u.A u that minimises
  * the A-norm error along u (g = 0 when u.A u <= 0), so the start is never
- * worse in the A-norm than dv_prev itself; one step g is taken for all
- * instances of the context.  Features of vertex i (N(i): block
+ * worse in the A-norm than dv_prev itself.  One step g is taken for all
+ * instances of the context (pc_set_instances), so with several instances
+ * the guarantee holds for the sum of their A-norm errors, not for each
+ * instance.  Features of vertex i (N(i): block
  * columns of row i other than i): v/s_v, (b/m)/s_v, dv_prev/s_v, mean_N dv_prev/s_v,
  * (b/diag A)/s_v, (mean_N b/m - b_i/m_i)/s_v, (mean_N v - v_i)/s_v,
  * (mean_N x - x_i)/l, pinned, log10(mean diag A_i / m_i), |N(i)|/12.

@@ -3,12 +3,16 @@
 Every computation runs in the HIP library.  If the library is missing the
 import fails; there is no fallback path.  Device buffers are torch tensors on
 ``cuda:0`` (float64, shape (nv, 3), contiguous); the current torch stream is
-passed to every call.
+passed to every call.  By default the library's own device memory comes from
+torch's caching allocator (pc_set_allocator), so the library and torch share
+one pool.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -29,7 +33,7 @@ ABI_SYMBOLS = ["pc_create", "pc_destroy", "pc_set_params", "pc_last_error", "pc_
                "pc_ws_set_params", "pc_ws_get_params", "pc_ws_features", "pc_ws_predict", "pc_ws_gradient",
                "pc_ws_train_step", "pc_mfma_probe", "pc_get_option", "pc_set_instances", "pc_get_instance_info",
                "pc_autotune", "cloth_export_precond", "pc_ws_start", "cloth_set_contacts",
-               "cloth_assemble_bell", "cloth_spmv_bell", "cloth_export_bell"]
+               "cloth_assemble_bell", "cloth_spmv_bell", "cloth_export_bell", "pc_set_allocator"]
 WS_PARAMS = 10307
 # Warm-start network layer shapes (inputs x outputs); the flat parameter
 # vector holds, per layer, W row-major then the bias.
@@ -133,11 +137,74 @@ def lib():
         L.pc_autotune.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_double), vp]
         L.pc_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.pc_set_allocator.argtypes = [vp, _ALLOC_FN, _FREE_FN, vp]
         for name in ABI_SYMBOLS:
             if name not in ("pc_last_error",):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """torch's caching allocator as the library's device allocator
+    (pc_set_allocator).  Counts the blocks it hands out and takes back."""
+
+    def __init__(self):
+        self.live = {}
+        self.n_alloc = 0
+        self.n_free = 0
+        self.bytes = 0
+        self.alloc_fn = _ALLOC_FN(self._alloc)
+        self.free_fn = _FREE_FN(self._free)
+
+    def _alloc(self, nbytes, _user):
+        try:
+            import torch
+            ptr = int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+        except Exception:      # the library turns NULL into PC_ERR_OOM
+            return None
+        self.live[ptr] = int(nbytes)
+        self.n_alloc += 1
+        self.bytes += int(nbytes)
+        return ptr
+
+    def _free(self, ptr, _user):
+        self.live.pop(ptr, None)
+        self.n_free += 1
+        try:
+            import torch
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
+
+_TORCH_ALLOCATOR = None
+
+
+def torch_allocator():
+    """The process-wide TorchAllocator the contexts use by default."""
+    global _TORCH_ALLOCATOR
+    if _TORCH_ALLOCATOR is None:
+        _TORCH_ALLOCATOR = TorchAllocator()
+    return _TORCH_ALLOCATOR
+
+
+# Contexts still open at interpreter exit are closed while torch (whose
+# allocator takes their memory back) is still usable.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    for c in list(_LIVE):
+        try:
+            c.close()
+        except Exception:
+            pass
 
 
 class PclothError(RuntimeError):
@@ -178,8 +245,18 @@ def make_params(h, mu=1000.0, lam=500.0, k_bend=1e-5, beta=0.0, gravity=(0.0, 0.
 class Context:
     """One cloth on the GPU: wraps pc_create / pc_destroy and the step calls."""
 
-    def __init__(self, rest, tris, mass, pinned, params: PcParams):
+    def __init__(self, rest, tris, mass, pinned, params: PcParams, allocator="torch"):
+        """allocator: "torch" (torch's caching allocator, the default), None
+        (hipMalloc inside the library) or a TorchAllocator-like object with
+        alloc_fn / free_fn ctypes callbacks."""
         L = lib()
+        if allocator == "torch":
+            allocator = torch_allocator()
+        self.allocator = allocator
+        if allocator is None:
+            L.pc_set_allocator(None, _ALLOC_FN(), _FREE_FN(), None)
+        else:
+            L.pc_set_allocator(None, allocator.alloc_fn, allocator.free_fn, None)
         self._keep = [np.ascontiguousarray(rest, dtype=np.float64),
                       np.ascontiguousarray(tris, dtype=np.int32),
                       np.ascontiguousarray(mass, dtype=np.float64),
@@ -197,14 +274,15 @@ class Context:
         if st != PC_OK:
             raise PclothError(st, L.pc_last_error(None).decode())
         self.h = h
+        _LIVE.add(self)
         self.nv, self.nt = int(m.nv), int(m.nt)
         sz = (ctypes.c_int64 * 4)()
         L.pc_sizes(self.h, sz)
         self.nh, self.cap = int(sz[2]), int(sz[3])
 
     @classmethod
-    def from_cloth(cls, c, **kw):
-        return cls(c.rest, c.tris, c.mass, c.pinned, make_params(c.h, **kw))
+    def from_cloth(cls, c, allocator="torch", **kw):
+        return cls(c.rest, c.tris, c.mass, c.pinned, make_params(c.h, **kw), allocator=allocator)
 
     def close(self):
         if getattr(self, "h", None):

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,10 +20,28 @@ struct pc_ctx {
 
 static thread_local std::string g_create_err;
 
+// Allocator installed with pc_set_allocator(NULL, ...): contexts created
+// afterwards start with it, so their pc_create buffers come from it too.
+static std::mutex g_alloc_mu;
+static pc_alloc_fn g_alloc_fn = nullptr;
+static pc_free_fn g_free_fn = nullptr;
+static void *g_alloc_user = nullptr;
+
 namespace pc {
 
 pc_status dev_alloc(Ctx *ctx, void **p, size_t bytes) {
     if (bytes == 0) bytes = 8;
+    *p = nullptr;
+    if (ctx->alloc_fn) {
+        void *q = ctx->alloc_fn(bytes, ctx->alloc_user);
+        if (!q) {
+            ctx->err = "allocator returned NULL for " + std::to_string(bytes) + " bytes";
+            return PC_ERR_OOM;
+        }
+        ctx->blocks[q] = AllocRec{ctx->free_fn, ctx->alloc_user};
+        *p = q;
+        return PC_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -30,7 +49,24 @@ pc_status dev_alloc(Ctx *ctx, void **p, size_t bytes) {
         ctx->err = "hipMalloc(" + std::to_string(bytes) + " bytes): " + hipGetErrorString(e);
         return e == hipErrorOutOfMemory ? PC_ERR_OOM : PC_ERR_HIP;
     }
+    ctx->blocks[*p] = AllocRec{nullptr, nullptr};
     return PC_OK;
+}
+
+// A block from a caller's allocator may be handed out again as soon as it is
+// returned, so the device is drained first (frees happen only when a buffer
+// grows and at pc_destroy).
+void dev_free(Ctx *ctx, void *p) {
+    if (!p) return;
+    auto it = ctx->blocks.find(p);
+    const AllocRec r = it != ctx->blocks.end() ? it->second : AllocRec{nullptr, nullptr};
+    if (it != ctx->blocks.end()) ctx->blocks.erase(it);
+    if (r.free_fn) {
+        (void)hipDeviceSynchronize();
+        r.free_fn(p, r.user);
+    } else {
+        (void)hipFree(p);
+    }
 }
 
 }  // namespace pc
@@ -68,12 +104,11 @@ static void free_all(Ctx *c) {
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
                     c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn, c->jdel, c->cg_pd, c->cg_s, c->e32, c->r32, c->q32,
                     c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    for (void *p : ptrs) dev_free(c, p);
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->restart_h) (void)hipHostFree(c->restart_h);
     if (c->status_host) (void)hipHostFree(c->status_host);
-    bell_free(c->bell);
+    bell_free(c, c->bell);
 }
 
 extern "C" {
@@ -102,6 +137,12 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
     pc_ctx *h = new (std::nothrow) pc_ctx();
     if (!h) { g_create_err = "host allocation failed"; return PC_ERR_OOM; }
     Ctx *ctx = &h->c;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        ctx->alloc_fn = g_alloc_fn;
+        ctx->free_fn = g_free_fn;
+        ctx->alloc_user = g_alloc_user;
+    }
     ctx->nv = nv;
     ctx->nt = nt;
     ctx->nslices = (nv + WAVE - 1) / WAVE;
@@ -206,6 +247,25 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
         return fail(PC_ERR_HIP);
     }
     *out = h;
+    return PC_OK;
+}
+
+pc_status pc_set_allocator(pc_ctx *h, pc_alloc_fn alloc, pc_free_fn free_fn, void *user) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) {
+        if (h) h->c.err = "pc_set_allocator: give both routines or neither";
+        else g_create_err = "pc_set_allocator: give both routines or neither";
+        return PC_ERR_ARG;
+    }
+    if (!h) {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        g_alloc_fn = alloc;
+        g_free_fn = free_fn;
+        g_alloc_user = alloc ? user : nullptr;
+        return PC_OK;
+    }
+    h->c.alloc_fn = alloc;
+    h->c.free_fn = free_fn;
+    h->c.alloc_user = alloc ? user : nullptr;
     return PC_OK;
 }
 
@@ -481,7 +541,7 @@ pc_status pc_destroy(pc_ctx *h) {
     if (!h) return PC_ERR_ARG;
     (void)hipDeviceSynchronize();
     if (h->c.mlp) {
-        mlp_free(h->c.mlp);
+        mlp_free(&h->c, h->c.mlp);
         delete h->c.mlp;
         h->c.mlp = nullptr;
     }
@@ -669,7 +729,7 @@ pc_status cloth_set_contacts(pc_ctx *h, int32_t ncontacts, const int32_t *verts,
         const size_t sizes[] = {sizeof(int) * 4 * (size_t)nc, sizeof(double) * 4 * (size_t)nc,
                                 sizeof(double) * 3 * (size_t)nc};
         for (int k = 0; k < 3; ++k) {
-            if (*bufs[k]) (void)hipFree(*bufs[k]);
+            dev_free(ctx, *bufs[k]);
             *bufs[k] = nullptr;
         }
         ctx->nc_cap = 0;
@@ -694,7 +754,7 @@ pc_status cloth_set_contacts(pc_ctx *h, int32_t ncontacts, const int32_t *verts,
     // capacities: 4 incidences and at most 12 more blocks per contact
     const int64_t ninc = 3 * (int64_t)ctx->nt + 4 * (int64_t)ctx->nh + 4 * nc;
     if (ninc > ctx->ninc_cap) {
-        if (ctx->inc) (void)hipFree(ctx->inc);
+        dev_free(ctx, ctx->inc);
         ctx->inc = nullptr;
         ctx->ninc_cap = 0;
         if ((st = dev_alloc(ctx, (void **)&ctx->inc, sizeof(int) * (size_t)ninc))) return st;
@@ -707,7 +767,7 @@ pc_status cloth_set_contacts(pc_ctx *h, int32_t ncontacts, const int32_t *verts,
         return PC_ERR_CAPACITY;
     }
     if (cap > ctx->cap) {
-        if (ctx->colidx) (void)hipFree(ctx->colidx);
+        dev_free(ctx, ctx->colidx);
         ctx->colidx = nullptr;
         if ((st = dev_alloc(ctx, (void **)&ctx->colidx, sizeof(int) * (size_t)cap))) return st;
         ctx->cap = cap;

@@ -95,7 +95,7 @@ __global__ void k_scan_add(int *out, const int *tile_sums, int n) {
 pc_status scan_excl(Ctx *ctx, const int *in, int *out, int n, hipStream_t s) {
     const int ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     if ((size_t)ntiles > ctx->scan_tmp_elems) {
-        if (ctx->scan_tmp) (void)hipFree(ctx->scan_tmp);
+        if (ctx->scan_tmp) dev_free(ctx, ctx->scan_tmp);
         ctx->scan_tmp = nullptr;
         pc_status st = dev_alloc(ctx, (void **)&ctx->scan_tmp, sizeof(int) * (size_t)(ntiles + 1));
         if (st) return st;
@@ -264,7 +264,7 @@ pc_status topo_build(Ctx *ctx, const pc_mesh *mesh, hipStream_t s) {
     PC_HIP(hipMemcpyAsync(&bits, ctx->status, sizeof(int), hipMemcpyDeviceToHost, s));
     PC_HIP(hipStreamSynchronize(s));
     if (bits) {
-        (void)hipFree(elist); (void)hipFree(hcnt); (void)hipFree(hptr);
+        dev_free(ctx, elist); dev_free(ctx, hcnt); dev_free(ctx, hptr);
         if (bits & ST_BUCKET_OVERFLOW) {
             ctx->err = "a vertex is the lower end of more than 64 directed triangle edges";
             return PC_ERR_CAPACITY;
@@ -284,9 +284,9 @@ pc_status topo_build(Ctx *ctx, const pc_mesh *mesh, hipStream_t s) {
     PC_HIP(hipGetLastError());
     PC_HIP(hipMemcpyAsync(&bits, ctx->status, sizeof(int), hipMemcpyDeviceToHost, s));
     PC_HIP(hipStreamSynchronize(s));
-    (void)hipFree(elist);
-    (void)hipFree(hcnt);
-    (void)hipFree(hptr);
+    dev_free(ctx, elist);
+    dev_free(ctx, hcnt);
+    dev_free(ctx, hptr);
     if (bits) {
         ctx->err = "mesh rejected (device check bits " + std::to_string(bits) + ")";
         return PC_ERR_MESH;
@@ -904,7 +904,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     pc_status st;
     const size_t need = (size_t)ctx->vcap * 9 * dtype_size(dtype);
     if (need > ctx->jval_bytes) {
-        if (ctx->jval) (void)hipFree(ctx->jval);
+        if (ctx->jval) dev_free(ctx, ctx->jval);
         ctx->jval = nullptr;
         ctx->jval_bytes = 0;
         if ((st = dev_alloc(ctx, &ctx->jval, need))) return st;
@@ -915,7 +915,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     ctx->last_x = x;
     ctx->last_v = v;
     if (dtype != PC_F64 && ctx->hi_blocks < ctx->vcap) {
-        if (ctx->jval_hi) (void)hipFree(ctx->jval_hi);
+        if (ctx->jval_hi) dev_free(ctx, ctx->jval_hi);
         ctx->jval_hi = nullptr;
         ctx->hi_blocks = 0;
         if ((st = dev_alloc(ctx, (void **)&ctx->jval_hi, (size_t)ctx->vcap * 9 * sizeof(double)))) return st;

@@ -399,7 +399,7 @@ __global__ void k_bell_export(int nv, int Wv, const TB *val, double *out) {
 constexpr int BELL_STAGE_SLOTS = 256;   // 64 rows x 256 slots x 4 B = 64 KiB of LDS
 static pc_status grow(Ctx *ctx, void **p, size_t *have, size_t bytes) {
     if (bytes <= *have) return PC_OK;
-    if (*p) (void)hipFree(*p);
+    if (*p) dev_free(ctx, *p);
     *p = nullptr;
     *have = 0;
     pc_status st = dev_alloc(ctx, p, bytes);
@@ -541,10 +541,10 @@ pc_status bell_export(Ctx *ctx, int32_t *width, int32_t *cols, double *vals, hip
     return PC_OK;
 }
 
-void bell_free(BellState &Bs) {
+void bell_free(Ctx *ctx, BellState &Bs) {
     void *ptrs[] = {Bs.cnt, Bs.len, Bs.f, Bs.idx, Bs.col, Bs.val, Bs.x4};
     for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+        if (p) dev_free(ctx, p);
     Bs = BellState{};
 }
 

@@ -715,15 +715,15 @@ pc_status mlp_probe(Ctx *ctx, float *host_out) {
     hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, 0, d);
     PC_HIP(hipGetLastError());
     PC_HIP(hipMemcpy(host_out, d, sizeof(float) * 512, hipMemcpyDeviceToHost));
-    (void)hipFree(d);
+    dev_free(ctx, d);
     return PC_OK;
 }
 
-void mlp_free(MlpState *M) {
+void mlp_free(Ctx *ctx, MlpState *M) {
     void *ptrs[] = {M->w, M->m, M->v, M->g, M->wb, M->X, M->H1, M->H2, M->H3, M->G1, M->G2, M->G3,
                     M->G4, M->Ad, M->part, M->dots, M->dpart};
     for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+        if (p) dev_free(ctx, p);
     *M = MlpState{};
 }
 

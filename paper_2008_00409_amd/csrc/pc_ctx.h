@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <algorithm>
 #include <vector>
@@ -125,8 +126,20 @@ struct BellState {
     bool valid = false;
 };
 
+// Where a device block came from: free_fn == nullptr means hipMalloc.
+struct AllocRec {
+    pc_free_fn free_fn;
+    void *user;
+};
+
 struct Ctx {
     std::string err;
+    // device allocator of the following allocations (nullptr: hipMalloc) and
+    // the origin of every live block
+    pc_alloc_fn alloc_fn = nullptr;
+    pc_free_fn free_fn = nullptr;
+    void *alloc_user = nullptr;
+    std::unordered_map<void *, AllocRec> blocks;
     Prof prof;
     double ell = 0.0;          // mean rest edge length (over the 3 edges of every triangle)
     const double *last_x = nullptr, *last_v = nullptr;  // state of the last assembly (caller's buffers)
@@ -275,14 +288,18 @@ pc_status pcg_run(Ctx *ctx, const double *b, double *dv, const pc_solve_opts *o,
                   hipStream_t s);
 pc_status update_run(Ctx *ctx, const double *dv, double *x, double *v, hipStream_t s);
 pc_status scan_excl(Ctx *ctx, const int *in, int *out, int n, hipStream_t s);
+// Device memory of the library: through the context's allocator
+// (pc_set_allocator) when one is installed, else hipMalloc.  Every block is
+// returned by dev_free to the routine that allocated it.
 pc_status dev_alloc(Ctx *ctx, void **p, size_t bytes);
+void dev_free(Ctx *ctx, void *p);
 pc_status read_status(Ctx *ctx, hipStream_t s, int *bits);
 pc_status build_schedule(Ctx *ctx);
 pc_status check_contacts(Ctx *ctx, int nc, int *bad, hipStream_t s);
 pc_status bell_assemble(Ctx *ctx, const double *x, const double *v, pc_dtype dtype, double *b, hipStream_t s);
 pc_status bell_spmv(Ctx *ctx, const double *x, double *y, hipStream_t s);
 pc_status bell_export(Ctx *ctx, int32_t *width, int32_t *cols, double *vals, hipStream_t s);
-void bell_free(BellState &Bs);
+void bell_free(Ctx *ctx, BellState &Bs);
 pc_status set_inner_vectors(Ctx *ctx);
 pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, float *best_ms, hipStream_t s);
 

@@ -38,6 +38,6 @@ pc_status mlp_adam(Ctx *ctx, MlpState *M, double lr, hipStream_t s);
 pc_status mlp_start(Ctx *ctx, MlpState *M, const double *x, const double *v, const double *b, const double *dvp,
                     double *dv0, double *u_buf, int *used, hipStream_t s);
 pc_status mlp_probe(Ctx *ctx, float *host_out);
-void mlp_free(MlpState *M);
+void mlp_free(Ctx *ctx, MlpState *M);
 
 }  // namespace pc

@@ -680,7 +680,7 @@ pc_status build_schedule(Ctx *ctx) {
     const int nslices = (int)slice_row0.size() - 1;
     pc_status st;
     auto realloc = [&](void **p, size_t bytes) -> pc_status {
-        if (*p) (void)hipFree(*p);
+        if (*p) dev_free(ctx, *p);
         *p = nullptr;
         return dev_alloc(ctx, p, bytes);
     };
@@ -764,7 +764,7 @@ static Grids grids(Ctx *ctx) {
 static pc_status ensure_windows(Ctx *ctx, hipStream_t s) {
     if (ctx->win_valid) return PC_OK;
     if (ctx->win_items < ctx->n_sitems) {
-        if (ctx->sitem_win) (void)hipFree(ctx->sitem_win);
+        if (ctx->sitem_win) dev_free(ctx, ctx->sitem_win);
         ctx->sitem_win = nullptr;
         ctx->win_items = 0;
         pc_status st = dev_alloc(ctx, (void **)&ctx->sitem_win, sizeof(int2) * (size_t)ctx->n_sitems);

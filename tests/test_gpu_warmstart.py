@@ -216,3 +216,88 @@ def test_trained_network_gain_on_held_out_step(torch, B, oracle_mod):
           f"learned {iters['learned']}; energy previous {e_prev:.6e}, learned {e_learned:.6e}")
     assert e_learned < e_prev
     assert iters["learned"] <= iters["zero"]
+
+
+def test_training_steps_match_oracle_adam(torch, B, oracle_mod, M):
+    """k calls of pc_ws_train_step against k rounds of the oracle's forward
+    pass, backward pass and Adam step (bias-corrected moments, Kingma and Ba
+    2015), from the same parameters on the same assembled system of Eq. 3:
+
+    1. before every step, the gradient the step applies (pc_ws_gradient at
+       the GPU's current parameters) matches the oracle's gradient at those
+       parameters per tensor, at the gradient bar above;
+    2. after every step, the GPU's FP32 parameters equal the oracle's Adam
+       driven by those same gradients, element by element to FP32 rounding
+       of the update: this pins the first and second moments and the bias
+       correction 1 - beta^t at every t (a correction frozen at t = 1, or
+       one moment's factor swapped, moves some update by far more than the
+       bar);
+    3. after k steps, the GPU's parameter change matches the change of the
+       oracle's own k-step trajectory (its gradients, its Adam) per tensor.
+       Adam normalises each element's update to about lr, so an element whose
+       gradient is near zero could take either sign on the two sides; with
+       gradients within 2e-4 of the oracle's (measured) the change agrees to
+       about 2e-3 per tensor, and the bar is 5e-2.  The figures are printed."""
+    c, P, A, v, dvp, ctx, (x_d, v_d, dvp_d, b_d), ell, X = setup_case(torch, B, oracle_mod, M)
+    k_steps, lr = 4, 2e-3
+    sv = ell / c.h
+    apply_A = lambda z: P.spmv(A, z)
+
+    def oracle_grad(flat):
+        pb = [[M.bf16_round(W), cb] for W, cb in M.unflatten(flat)]
+        y, hs = M.forward(pb, X, bf16=True)
+        dv0 = M.start_from_output(y, dvp, c.pinned, sv)
+        L, gy = M.energy_loss_grad(apply_A, A.b, A.diag, dv0, c.pinned, sv)
+        return M.flatten(M.backward(pb, X, hs, gy, bf16=True)), L
+
+    def segments():
+        o = 0
+        for a, bdim in M.SHAPES:
+            for n in (a * bdim, bdim):
+                yield o, n
+                o += n
+
+    try:
+        ctx.ws_set_params(M.flatten(random_params(M, 23)))
+        p0 = ctx.ws_get_params().astype(np.float64)     # the FP32 values both sides start from
+        p_fed = M.unflatten(p0)          # oracle Adam driven by the GPU's gradients
+        st_fed, st_own = {}, {}
+        p_own = M.unflatten(p0)          # oracle's own trajectory
+        worst_grad, worst_step = 0.0, 0.0
+        for t in range(1, k_steps + 1):
+            p_gpu_before = ctx.ws_get_params().astype(np.float64)
+            g_gpu, loss_gpu = ctx.ws_gradient(x_d, v_d, b_d, dvp_d)
+            g_or, L_or = oracle_grad(p_gpu_before)
+            assert loss_gpu == pytest.approx(L_or, rel=2e-2, abs=1e-3 * abs(L_or))
+            for o, n in segments():
+                rel = np.linalg.norm(g_gpu[o:o + n] - g_or[o:o + n]) / max(np.linalg.norm(g_or[o:o + n]), 1e-30)
+                worst_grad = max(worst_grad, rel)
+                assert rel < 3e-2, (t, o, n, rel)
+            ctx.ws_train_step(x_d, v_d, b_d, dvp_d, lr=lr, want_loss=False)
+            p_gpu = ctx.ws_get_params().astype(np.float64)
+            M.adam_step(p_fed, M.unflatten(g_gpu.astype(np.float64)), st_fed, lr=lr)
+            want = M.flatten(p_fed)
+            # FP32 arithmetic of the update and FP32 storage of the weights, per step taken
+            bar = t * (1e-5 * lr + 2.4e-7 * np.abs(want))
+            err = np.abs(p_gpu - want)
+            worst_step = max(worst_step, float(np.max(err / (1e-5 * lr + 2.4e-7 * np.abs(want)))) / t)
+            assert np.all(err <= bar), (t, int(np.argmax(err - bar)), float(np.max(err)))
+            # the step moved the weights: the comparison is not vacuous
+            assert np.linalg.norm(p_gpu - p_gpu_before) > 0.3 * lr * np.sqrt(np.count_nonzero(g_gpu))
+            g_own, _ = oracle_grad(M.flatten(p_own))
+            M.adam_step(p_own, M.unflatten(g_own), st_own, lr=lr)
+        d_gpu = ctx.ws_get_params().astype(np.float64) - p0
+        d_own = M.flatten(p_own) - p0
+        rels = []
+        for o, n in segments():
+            den = np.linalg.norm(d_own[o:o + n])
+            if den == 0.0:
+                assert np.linalg.norm(d_gpu[o:o + n]) == 0.0
+                continue
+            rels.append(np.linalg.norm(d_gpu[o:o + n] - d_own[o:o + n]) / den)
+        print(f"adam parity: worst per-tensor gradient error {worst_grad:.2e}; worst element error "
+              f"{worst_step:.3f} of the FP32 bar; k-step change against the oracle's own trajectory, per tensor: "
+              + " ".join(f"{r:.3f}" for r in rels))
+        assert max(rels) < 5e-2, rels
+    finally:
+        ctx.close()
