@@ -10,7 +10,13 @@ resident in HBM.  Two configurations run on the same workload:
           timed again with the previous-step start, and the speedup is
           taken against the faster of the two
   value   the project configuration: BF16 blocks with FP64 refinement sweeps,
-          block-Jacobi, learned warm start (network trained online first)
+          block-Jacobi, learned warm start (network trained online first);
+          timed again with the previous-step start, so that the learned
+          start's own share of the speedup is a number of its own
+
+After the timed runs an untimed replay of the same trajectory solves every
+timed step's system from the zero, previous-step and learned starts to the
+same tolerance and reports the iterations per step (paired evaluation).
 
 Both use the autotuned launch schedule.  Prints one JSON line (stdout);
 progress goes to stderr.
@@ -59,10 +65,23 @@ def assembly_bytes(nv, nt, nh, nnzb, blocks):
     return reads + writes
 
 
-def cpu_baseline(cloth, gpu_iters_per_step, seconds_budget=25.0, contacts=None):
-    """The FP64 oracle on the host: one assembly of the same step and a
-    bounded number of Jacobi-PCG iterations; steps/s extrapolated with the
-    iteration count the GPU needed for the same tolerance."""
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(cloth, iters_per_step, iters_source, seconds_budget=25.0, contacts=None):
+    """The FP64 oracle on the host: one assembly of the same step and as many
+    Jacobi-PCG iterations as fit the time budget (at most 2,000); steps/s
+    extrapolated with `iters_per_step`, the Jacobi iteration count per step
+    at the same tolerance (its source is recorded in the sample text)."""
     from oracle import oracle
     oracle.build()
     P = oracle.Problem.from_cloth(cloth)
@@ -76,17 +95,17 @@ def cpu_baseline(cloth, gpu_iters_per_step, seconds_budget=25.0, contacts=None):
     t0 = time.perf_counter()
     P.pcg_fixed(A, iters)
     t_it = (time.perf_counter() - t0) / iters
-    n2 = int(max(5, min(60, (seconds_budget - t_asm) / max(t_it, 1e-6) - iters)))
+    n2 = int(max(5, min(2000, (seconds_budget - t_asm) / max(t_it, 1e-6) - iters)))
     t0 = time.perf_counter()
     P.pcg_fixed(A, n2)
     t_it = (time.perf_counter() - t0) / n2
-    t_step = t_asm + gpu_iters_per_step * t_it
+    t_step = t_asm + iters_per_step * t_it
     cores = oracle.num_threads()
-    rec = {"value": 1.0 / t_step, "unit": "steps/s", "cores": cores, "kind": "oracle",
+    rec = {"value": 1.0 / t_step, "unit": "steps/s", "cores": cores, "kind": "oracle", "cpu_model": host_cpu_model(),
+           "iters_per_step": iters_per_step, "iters_source": iters_source,
            "sample": (f"FP64 oracle on {cloth.name}: one assembly ({t_asm:.2f} s) and {n2} Jacobi-PCG "
-                      f"iterations ({1e3 * t_it:.1f} ms each), steps/s = 1/(assembly + "
-                      f"{gpu_iters_per_step:.0f} iterations), the GPU's mean iterations per step at the "
-                      f"same tolerance")}
+                      f"iterations ({1e3 * t_it:.1f} ms each) on {cores} threads, steps/s = 1/(assembly + "
+                      f"{iters_per_step:.0f} iterations); iterations per step: {iters_source}")}
     # the same on one host thread (one assembly and 10 iterations)
     oracle.set_threads(1)
     try:
@@ -100,8 +119,9 @@ def cpu_baseline(cloth, gpu_iters_per_step, seconds_budget=25.0, contacts=None):
     finally:
         oracle.set_threads(cores)
     rec["single_thread"] = {
-        "value": 1.0 / (t_asm1 + gpu_iters_per_step * t_it1), "unit": "steps/s", "cores": 1,
-        "sample": f"one assembly ({t_asm1:.2f} s) and {n1} iterations ({1e3 * t_it1:.1f} ms each), extrapolated alike"}
+        "value": 1.0 / (t_asm1 + iters_per_step * t_it1), "unit": "steps/s", "cores": 1,
+        "sample": (f"one assembly ({t_asm1:.2f} s) and {n1} iterations ({1e3 * t_it1:.1f} ms each) on one "
+                   f"thread, extrapolated with the same {iters_per_step:.0f} iterations per step")}
     return rec
 
 
@@ -221,6 +241,10 @@ def main():
                     help="CG form of the project configuration: textbook recurrences or single reduction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 / Jacobi / zero-start run")
+    ap.add_argument("--no-value-prev", action="store_true",
+                    help="skip the timed run of the project configuration with the previous-step start")
+    ap.add_argument("--no-paired", action="store_true",
+                    help="skip the untimed replay that solves every timed step's system from each start")
     ap.add_argument("--prof-every", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=30)
     ap.add_argument("--autotune", type=int, default=1)
@@ -303,22 +327,68 @@ def main():
         ii = [d["iters"] for d in ctx.instance_info()]
         per_instance = {"instances": len(ii), "iters_min": min(ii), "iters_median": float(np.median(ii)),
                         "iters_max": max(ii)}
-    # paired comparison of the starts on one further system of the same
-    # trajectory: one more step gives the previous increment, then the next
-    # system is solved from each start to the same tolerance
-    v_before = v.clone()
-    ctx.cloth_step(x, v, nsteps=1, dtype=args.blocks, tol=tol, warm=args.warm, precond=args.precond,
-                   inner_rho=args.inner_rho, method=args.method)
-    dv_prev = v - v_before
-    b = ctx.cloth_assemble(x, v, args.blocks)
-    paired = {}
-    for mode in (["zero", "prev"] + (["learned"] if params is not None else [])):
-        dv0 = torch.zeros_like(x) if mode == "zero" else dv_prev.clone()
-        _, pinfo = ctx.cloth_pcg_solve(b, dv=dv0, tol=tol, warm=mode, precond=args.precond,
-                                       inner_rho=args.inner_rho, method=args.method)
-        paired[mode] = {"iters": pinfo["iters"], "start_used": pinfo["warm_used"],
-                        "rel_res_true": pinfo["rel_res_true"]}
-    log(f"# paired starts on one system: {paired}")
+    # the learned start's own share: the same configuration, schedule and
+    # initial state with the previous-step start instead, timed alike
+    rec_value_prev = None
+    if args.warm == "learned" and not args.no_value_prev:
+        x.copy_(torch.from_numpy(cloth.x0))
+        v.copy_(torch.from_numpy(cloth.v0))
+        el_vp, infos_vp, _ = time_steps(ctx, x, v, args.steps, args.warmup, args.blocks, tol, "prev", 0,
+                                        args.precond, args.inner_rho, args.method)
+        rec_value_prev = {"steps_per_s": args.steps / el_vp, "warm_start": "prev",
+                          "cg_iters_per_step": [i["iters"] for i in infos_vp],
+                          "refinement_sweeps": [i["sweeps"] for i in infos_vp],
+                          "rel_res_true_max": max(i["rel_res_true"] for i in infos_vp)}
+        log(f"# value configuration, previous-step start: {rec_value_prev['steps_per_s']:.3f} steps/s, "
+            f"iters {rec_value_prev['cg_iters_per_step']}")
+    # paired evaluation (untimed replay): the trajectory of the timed run is
+    # replayed from the same initial state, and at every timed step the same
+    # system (A, b) is solved from each start to the same tolerance; the
+    # trajectory advances with the configured start's solution
+    paired = None
+    if not args.no_paired:
+        modes = ["zero", "prev"] + (["learned"] if params is not None else [])
+        x.copy_(torch.from_numpy(cloth.x0))
+        v.copy_(torch.from_numpy(cloth.v0))
+        kw = dict(tol=tol, precond=args.precond, inner_rho=args.inner_rho, method=args.method)
+        dv_prev = torch.zeros_like(x)
+        if args.warmup:
+            if args.warmup > 1:
+                ctx.cloth_step(x, v, nsteps=args.warmup - 1, dtype=args.blocks, warm=args.warm, **kw)
+            v_before = v.clone()
+            ctx.cloth_step(x, v, nsteps=1, dtype=args.blocks, warm=args.warm, **kw)
+            dv_prev = v - v_before
+        pin = torch.from_numpy(cloth.pinned.astype(bool)).cuda()
+        paired = {m: {"iters": [], "sweeps": [], "start_used": []} for m in modes}
+        paired["missed"] = 0     # solves that ended above the tolerance (none expected)
+        t_rep = time.perf_counter()
+        for k in range(args.steps):
+            b = ctx.cloth_assemble(x, v, args.blocks)
+            keep = None
+            for mode in modes:
+                dv0 = torch.zeros_like(x) if mode == "zero" else dv_prev.clone()
+                dv, pinfo = ctx.cloth_pcg_solve(b, dv=dv0, warm=mode, raise_on_error=False, **kw)
+                if pinfo["status"] != 0 or not pinfo["rel_res_true"] <= tol:
+                    paired["missed"] = paired.get("missed", 0) + 1
+                paired[mode]["iters"].append(pinfo["iters"])
+                paired[mode]["sweeps"].append(pinfo["sweeps"])
+                paired[mode]["start_used"].append(pinfo["warm_used"])
+                if mode == args.warm:
+                    keep = dv
+            v.add_(keep)
+            v[pin] = 0.0
+            x.add_(cloth.h * v)
+            dv_prev = keep
+        for m in modes:
+            it = paired[m]["iters"]
+            paired[m].update({"mean": float(np.mean(it)), "median": float(np.median(it)), "total": int(sum(it))})
+        if "learned" in paired:
+            paired["learned_over_prev_iters"] = paired["learned"]["total"] / paired["prev"]["total"]
+            paired["learned_over_zero_iters"] = paired["learned"]["total"] / paired["zero"]["total"]
+            paired["steps_learned_fewer_than_prev"] = int(sum(
+                1 for a, b_ in zip(paired["learned"]["iters"], paired["prev"]["iters"]) if a < b_))
+        paired["seconds"] = time.perf_counter() - t_rep
+        log(f"# paired starts per step: " + ", ".join(f"{m} mean {paired[m]['mean']:.0f}" for m in modes))
     spmv = prof.get("spmv", {})
     spmv_ms = spmv.get("median_ms", float("nan"))
     narrow = bool(ctx.get_option(binding.PC_OPT_SPMV_NARROW_ACTIVE))
@@ -361,7 +431,11 @@ def main():
             "per_instance": per_instance,
         },
         "plain": rec_plain,
-        "paired_starts": paired,
+        "value_prev_start": rec_value_prev,
+        # value with the learned start over the same configuration with the
+        # previous-step start: the learned network's own share of the speedup
+        "learned_share": ((args.steps / el) / rec_value_prev["steps_per_s"]) if rec_value_prev else None,
+        "paired_per_step": paired,
         # against the faster of the plain solver's zero and previous-step starts
         "speedup_vs_plain": ((args.steps / el) / max(rec_plain["steps_per_s"], rec_plain["prev_start"]["steps_per_s"])
                              if rec_plain else None),
@@ -385,7 +459,14 @@ def main():
     ctx.close()
     if not args.no_cpu_baseline:
         log("# cpu baseline (oracle)...")
-        rec["cpu_baseline"] = cpu_baseline(cloth, float(np.mean(iters)), contacts=contacts)
+        if rec_plain is not None:
+            it_cpu = float(np.mean(rec_plain["cg_iters_per_step"]))
+            src = ("mean of the plain run (FP32 blocks, Jacobi, zero start, the oracle's preconditioner and "
+                   "start) over the timed steps at the same tolerance")
+        else:
+            it_cpu = float(np.mean(iters))
+            src = "mean of the timed configuration (no plain run in this invocation)"
+        rec["cpu_baseline"] = cpu_baseline(cloth, it_cpu, src, contacts=contacts)
     print(json.dumps(rec), flush=True)
 
 
