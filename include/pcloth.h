@@ -344,6 +344,22 @@ pc_status pc_ws_features(pc_ctx *ctx, const double *x, const double *v, const do
 /* Unscaled prediction dv0 = dv_prev + s_v y (device nv*3 doubles). */
 pc_status pc_ws_predict(pc_ctx *ctx, const double *x, const double *v, const double *b, const double *dv_prev,
                         double *dv0_out, void *stream);
+/* pc_ws_predict without allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same result, bit for bit, from the
+ * same two kernels, with the network's input rows kept in a scratch array of
+ * the library (64 MiB in each GPU's memory, held from the library's first use
+ * on that GPU until the process ends) instead of the context's buffer.  The
+ * call allocates nothing and does not synchronise; the context must hold
+ * the network's parameters (pc_ws_set_params) and an assembly.
+ * Limit: nv rounded up to a multiple of 16 at most 1,048,576 vertices, else
+ * PC_ERR_CAPACITY (pc_ws_predict has no such limit).  All contexts on one
+ * GPU share the scratch, so calls that overlap on one GPU (other threads,
+ * other streams without ordering between them) race and must be serialised
+ * by the caller.  PC_ERR_ARG for null pointers, missing parameters or
+ * assembly. */
+pc_status pc_ws_predict_noalloc(pc_ctx *ctx, const double *x, const double *v, const double *b,
+                                const double *dv_prev, double *dv0_out, void *stream);
 /* The learned CG start used by warm = 2: dv_prev + g u (device nv*3
  * doubles), step g to step_host (optional).  Synchronises the stream. */
 pc_status pc_ws_start(pc_ctx *ctx, const double *x, const double *v, const double *b, const double *dv_prev,

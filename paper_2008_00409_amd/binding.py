@@ -33,7 +33,8 @@ ABI_SYMBOLS = ["pc_create", "pc_destroy", "pc_set_params", "pc_last_error", "pc_
                "pc_ws_set_params", "pc_ws_get_params", "pc_ws_features", "pc_ws_predict", "pc_ws_gradient",
                "pc_ws_train_step", "pc_mfma_probe", "pc_get_option", "pc_set_instances", "pc_get_instance_info",
                "pc_autotune", "cloth_export_precond", "pc_ws_start", "cloth_set_contacts",
-               "cloth_assemble_bell", "cloth_spmv_bell", "cloth_export_bell", "pc_set_allocator"]
+               "cloth_assemble_bell", "cloth_spmv_bell", "cloth_export_bell", "pc_set_allocator",
+               "pc_ws_predict_noalloc"]
 WS_PARAMS = 10307
 # Warm-start network layer shapes (inputs x outputs); the flat parameter
 # vector holds, per layer, W row-major then the bias.
@@ -127,6 +128,7 @@ def lib():
         L.pc_ws_get_params.argtypes = [vp, vp, ctypes.c_int32]
         L.pc_ws_features.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.pc_ws_predict.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.pc_ws_predict_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.pc_ws_start.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
         L.pc_ws_gradient.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
         L.pc_ws_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double), vp]
@@ -467,6 +469,17 @@ class Context:
         self._check(lib().pc_ws_predict(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"),
                                         _dev3(b, self.nv, "b"), _dev3(dv_prev, self.nv, "dv_prev"), _ptr(out),
                                         _stream()))
+        return out
+
+    def ws_predict_noalloc(self, x, v, b, dv_prev, out=None):
+        """pc_ws_predict without any allocation inside the library (the
+        output tensor is the caller's)."""
+        import torch
+        if out is None:
+            out = torch.empty((self.nv, 3), dtype=torch.float64, device="cuda")
+        self._check(lib().pc_ws_predict_noalloc(self.h, _dev3(x, self.nv, "x"), _dev3(v, self.nv, "v"),
+                                                _dev3(b, self.nv, "b"), _dev3(dv_prev, self.nv, "dv_prev"),
+                                                _dev3(out, self.nv, "out"), _stream()))
         return out
 
     def ws_start(self, x, v, b, dv_prev):

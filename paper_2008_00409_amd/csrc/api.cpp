@@ -240,6 +240,7 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
     ctx->inst_row0_h = {0, nv};
     ctx->ninst = 0;  // forces the per-instance buffers to be allocated
     if ((st = build_schedule(ctx))) return fail(st);
+    if ((st = mlp_scratch_init(ctx))) return fail(st);
     if (hipMemset(ctx->counter, 0, sizeof(unsigned) * 4) != hipSuccess ||
         hipMemset(ctx->tmp, 0, sizeof(double) * 3 * (size_t)nv) != hipSuccess ||
         hipMemset(ctx->p, 0, sizeof(float4) * (size_t)nv) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
@@ -491,6 +492,16 @@ pc_status pc_ws_predict(pc_ctx *h, const double *x, const double *v, const doubl
     pc_status st = mlp_features(ctx, ctx->mlp, x, v, b, dv_prev, s);
     if (st) return st;
     return mlp_forward(ctx, ctx->mlp, dv_prev, dv0_out, false, s);
+}
+
+pc_status pc_ws_predict_noalloc(pc_ctx *h, const double *x, const double *v, const double *b,
+                                const double *dv_prev, double *dv0_out, void *stream) {
+    if (!h) return PC_ERR_ARG;
+    if (!x || !v || !b || !dv_prev || !dv0_out) {
+        h->c.err = "pc_ws_predict_noalloc: x, v, b, dv_prev and dv0_out must be device pointers";
+        return PC_ERR_ARG;
+    }
+    return mlp_predict_noalloc(&h->c, x, v, b, dv_prev, dv0_out, (hipStream_t)stream);
 }
 
 pc_status pc_ws_start(pc_ctx *h, const double *x, const double *v, const double *b, const double *dv_prev,

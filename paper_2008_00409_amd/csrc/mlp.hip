@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "pc_mlp.h"
@@ -705,6 +706,91 @@ pc_status mlp_start(Ctx *ctx, MlpState *M, const double *x, const double *v, con
     const double g = (d[0] - d[2]) / d[1];
     M->last_scale = (d[1] > 0.0 && std::isfinite(g)) ? g : 0.0;
     *used = M->last_scale != 0.0 ? 2 : 1;
+    return PC_OK;
+}
+
+// ---------------------------------------------------------------- prediction without allocation
+// pc_ws_predict_noalloc keeps the network's input rows (BF16 features) in
+// this file-scope array instead of the context's feature buffer: 64 MiB, the
+// rows of up to WS_NOALLOC_MAX_ROWS vertices.  Every GPU the library runs on
+// holds its own copy from the module's load until the process ends; all
+// contexts on a GPU share it, and each call overwrites it.
+constexpr int WS_NOALLOC_MAX_ROWS = 1 << 20;
+static __device__ __align__(256) short scratch[(size_t)WS_NOALLOC_MAX_ROWS * 32];
+
+// Device address of `scratch` on each GPU, looked up once per device with
+// that device current.  Host code passes this address to kernels, never the
+// array's own name (a host-side stand-in, not a device address).
+constexpr int WS_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[WS_MAX_DEVICES] = {};
+
+pc_status mlp_scratch_init(Ctx *ctx) {
+    int dev = 0;
+    PC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= WS_MAX_DEVICES) {
+        ctx->err = "device index " + std::to_string(dev) + " beyond the library's " +
+                   std::to_string(WS_MAX_DEVICES);
+        return PC_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            ctx->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return PC_ERR_HIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    ctx->ws_scratch = g_scratch_dev[dev];
+    return PC_OK;
+}
+
+// The same two launches as pc_ws_predict (features, then the forward pass),
+// with the features in the per-GPU scratch.  Allocates nothing: the network's
+// state must exist already (pc_ws_set_params).  The features kernel writes
+// every row below nv_pad (zeros past nv), so nothing of the previous call's
+// contents is read.
+pc_status mlp_predict_noalloc(Ctx *ctx, const double *x, const double *v, const double *b, const double *dvp,
+                              double *dv0, hipStream_t s) {
+    const int nv_pad = ((ctx->nv + 15) / 16) * 16;
+    if (nv_pad > WS_NOALLOC_MAX_ROWS) {
+        ctx->err = "pc_ws_predict_noalloc: " + std::to_string(ctx->nv) + " vertices exceed its scratch of " +
+                   std::to_string(WS_NOALLOC_MAX_ROWS) + " rows; use pc_ws_predict";
+        return PC_ERR_CAPACITY;
+    }
+    if (!ctx->ws_scratch) {
+        ctx->err = "pc_ws_predict_noalloc: scratch not set up";
+        return PC_ERR_HIP;
+    }
+    MlpState *M = ctx->mlp;
+    if (!M || !M->ready || !M->has_params) {
+        ctx->err = "pc_ws_predict_noalloc: no warm-start parameters set";
+        return PC_ERR_ARG;
+    }
+    if (!ctx->assembled) {
+        ctx->err = "pc_ws_predict_noalloc: nothing assembled";
+        return PC_ERR_ARG;
+    }
+    short *X = (short *)ctx->ws_scratch;
+    hipLaunchKernelGGL(k_ws_features, dim3((nv_pad + 255) / 256), dim3(256), 0, s, ctx->nv, nv_pad, ctx->rowptr,
+                       ctx->colidx, x, v, b, ctx->diag, ctx->mass, ctx->pinned, dvp, ctx->ell, ctx->prm.h, X);
+    PC_HIP(hipGetLastError());
+    FwdArgs F;
+    F.nv = ctx->nv;
+    F.ntiles = nv_pad / 16;
+    F.X = X;
+    F.Wb = M->wb;
+    F.Wf = M->w;
+    F.H1 = F.H2 = F.H3 = nullptr;
+    F.dvp = dvp;
+    F.pinned = ctx->pinned;
+    F.sv = ctx->ell / ctx->prm.h;
+    F.dv0 = dv0;
+    const int blocks = std::min(1024, (F.ntiles + 3) / 4);
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, F);
+    PC_HIP(hipGetLastError());
     return PC_OK;
 }
 

@@ -144,6 +144,7 @@ struct Ctx {
     double ell = 0.0;          // mean rest edge length (over the 3 edges of every triangle)
     const double *last_x = nullptr, *last_v = nullptr;  // state of the last assembly (caller's buffers)
     MlpState *mlp = nullptr;   // learned warm start (allocated on first use)
+    void *ws_scratch = nullptr;   // this GPU's scratch of pc_ws_predict_noalloc (device address)
     int nv = 0, nt = 0, nh = 0;
     int nslices = 0;          // ceil(nv / 64)
     int64_t cap = 0;          // block capacity (upper bound of nnzb)

@@ -39,5 +39,8 @@ pc_status mlp_start(Ctx *ctx, MlpState *M, const double *x, const double *v, con
                     double *dv0, double *u_buf, int *used, hipStream_t s);
 pc_status mlp_probe(Ctx *ctx, float *host_out);
 void mlp_free(Ctx *ctx, MlpState *M);
+pc_status mlp_scratch_init(Ctx *ctx);
+pc_status mlp_predict_noalloc(Ctx *ctx, const double *x, const double *v, const double *b, const double *dvp,
+                              double *dv0, hipStream_t s);
 
 }  // namespace pc
