@@ -48,8 +48,9 @@ typedef enum {
     PC_ERR_OOM = 4,            /* device allocation failed */
     PC_ERR_NONFINITE = 5,      /* NaN/Inf in the right-hand side or the residual */
     PC_ERR_NOT_CONVERGED = 6,  /* maxit reached; dv holds the last iterate */
-    PC_ERR_CAPACITY = 7        /* a vertex exceeds the per-row limits (64 incident
-                                  element corners, 64 distinct block columns) */
+    PC_ERR_CAPACITY = 7        /* a vertex exceeds the per-row limits (512 incident
+                                  element corners, 64 distinct block columns), or at
+                                  pc_create is the lower end of more than 64 edges */
 } pc_status;
 
 /* Storage type of the matrix blocks.  The assembly evaluates every element
@@ -312,7 +313,7 @@ pc_status cloth_export_pattern(pc_ctx *ctx, int32_t *rowptr_out, int32_t *colidx
  * pc_profile_read synchronises
  * the device and writes, for each kind k in 0..7 (0 SpMV in CG, 1 CG vector
  * update, 2 CG direction update, 3 row assembly, 4 row pattern, 5 whole
- * assembly), out[5k..5k+4] = {samples, mean ms, min ms, max ms, median ms}
+ * assembly, 6 element evaluation), out[5k..5k+4] = {samples, mean ms, min ms, max ms, median ms}
  * (host, 40 doubles; the median is over the first 65536 samples). */
 pc_status pc_profile(pc_ctx *ctx, int32_t every);
 pc_status pc_profile_read(pc_ctx *ctx, double *out);

@@ -103,7 +103,8 @@ static void free_all(Ctx *c) {
                     c->inc_cnt, c->inc_ptr, c->inc, c->rowlen, c->rowptr, c->colidx, c->jcol, c->lane_row,
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
                     c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn, c->jdel, c->cg_pd, c->cg_s, c->e32, c->r32, c->q32,
-                    c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d};
+                    c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d,
+                    c->slot_off, c->row_state, c->wide_rows, c->trec, c->hrec, c->crec};
     for (void *p : ptrs) dev_free(c, p);
     if (c->st_host) (void)hipHostFree(c->st_host);
     if (c->restart_h) (void)hipHostFree(c->restart_h);
@@ -630,7 +631,7 @@ pc_status pc_check(pc_ctx *h, void *stream) {
     pc_status st = read_status(ctx, (hipStream_t)stream, &bits);
     if (st) return st;
     if (bits & (ST_INC_OVERFLOW | ST_COL_OVERFLOW | ST_BUCKET_OVERFLOW)) {
-        ctx->err = "a vertex exceeds the per-row limits (64 incident corners / 64 block columns)";
+        ctx->err = "a vertex exceeds the per-row limits (512 incident element corners, 64 block columns; at pc_create: 64 directed edges from a lower-numbered vertex)";
         return PC_ERR_CAPACITY;
     }
     if (bits & ST_NONFINITE) {

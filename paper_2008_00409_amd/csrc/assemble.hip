@@ -359,35 +359,150 @@ __global__ void k_check_contacts(int nc, int nv, const int *cv, const double *w,
     if (!ok) atomicOr(bad, 1);
 }
 
-// LDS of the pattern pass (incidences, their vertices, column candidates,
-// columns) and of the assembly pass, which adds the element data.  The
-// pattern kernel declares only the first, so more of its rows fit per CU.
-struct RowPatLDS {
-    unsigned inc[64];
-    int ev[64][4];
-    unsigned cand[256];
-    int cols[64];
-};
-struct RowLDS : RowPatLDS {
-    double ed[64][14];   // element data of each incidence
-    double fk[64][3];    // force on this row's corner of each incidence
-};
+// ---------------------------------------------------------------- element records
+// Every element is evaluated once per assembly, one thread per element, into
+// SoA planes of FP64 (plane q of element e at rec[q * n + e]):
+//   triangle  0..5  F at x (3x2, row-major), 6..8 S+ at x (xx, xy, yy; the
+//                   stress's PSD part, for the stiffness), 9..11 S at the
+//                   force state, and with the lookahead force (rhs_mode 0)
+//                   12..17 F at the force state x + h v;
+//   hinge     0..11 G = sqrt(2 k_b c_h) grad theta at x (corner-major xyz),
+//                   12 phi = -sqrt(2 k_b c_h) (theta - theta_bar) at the force
+//                   state, and with the lookahead force 13..24 G at the force
+//                   state; the force on corner k is phi G_k (of the force
+//                   state), the stiffness block (k, l) is G_k G_l^T;
+//   contact   0 k_c while the gap at x is below the thickness (else 0),
+//             1 k_c (eta - g) at the force state while below it (else 0).
+constexpr int TREC = 12, TREC_LOOK = 18;
+constexpr int HREC = 13, HREC_LOOK = 25;
+constexpr int CREC = 2;
+
+__global__ void __launch_bounds__(256) k_tri_eval(int nt, const int *tri, const double *Bm, const double *x,
+                                                  const double *v, DevParams P, double *rec) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nt) return;
+    TriShape sh;
+    const double B0 = Bm[e], B1 = Bm[nt + e], B2 = Bm[2 * nt + e], B3 = Bm[3 * nt + e];
+    sh.b[1][0] = B0; sh.b[1][1] = B1;
+    sh.b[2][0] = B2; sh.b[2][1] = B3;
+    sh.b[0][0] = -B0 - B2; sh.b[0][1] = -B1 - B3;
+    d3 xs[3];
+    int vid[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        vid[q] = tri[q * nt + e];
+        xs[q] = ld3(x, vid[q]);
+    }
+    double F[3][2], S[3], Sp[3];
+    tri_F(xs, sh, F);
+    tri_stress(F, P.mu, P.lam, S);
+    psd_part(S, Sp);
+    const int64_t n = nt;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rec[(2 * a) * n + e] = F[a][0];
+        rec[(2 * a + 1) * n + e] = F[a][1];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) rec[(6 + q) * n + e] = Sp[q];
+    if (P.s_look != 0.0) {
+        d3 ys[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) ys[q] = xs[q] + (P.s_look * P.h) * ld3(v, vid[q]);
+        double Fy[3][2], Sy[3];
+        tri_F(ys, sh, Fy);
+        tri_stress(Fy, P.mu, P.lam, Sy);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) rec[(9 + q) * n + e] = Sy[q];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            rec[(12 + 2 * a) * n + e] = Fy[a][0];
+            rec[(13 + 2 * a) * n + e] = Fy[a][1];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) rec[(9 + q) * n + e] = S[q];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_hinge_eval(int nh, const int *hinge, const double *hcoef,
+                                                    const double *htbar, const double *x, const double *v,
+                                                    DevParams P, double *rec) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nh) return;
+    const double sc = sqrt(2.0 * P.kb * hcoef[e]), tb = htbar[e];
+    d3 xs[4], g[4];
+    int vid[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        vid[q] = hinge[q * nh + e];
+        xs[q] = ld3(x, vid[q]);
+    }
+    const int64_t n = nh;
+    double th = 0.0;
+    const bool ok = hinge_eval(xs, th, g);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        rec[(3 * q) * n + e] = ok ? sc * g[q].x : 0.0;
+        rec[(3 * q + 1) * n + e] = ok ? sc * g[q].y : 0.0;
+        rec[(3 * q + 2) * n + e] = ok ? sc * g[q].z : 0.0;
+    }
+    if (P.s_look != 0.0) {
+        d3 ys[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ys[q] = xs[q] + (P.s_look * P.h) * ld3(v, vid[q]);
+        double thf = 0.0;
+        const bool okf = hinge_eval(ys, thf, g);
+        rec[12 * n + e] = okf ? -sc * (thf - tb) : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            rec[(13 + 3 * q) * n + e] = okf ? sc * g[q].x : 0.0;
+            rec[(14 + 3 * q) * n + e] = okf ? sc * g[q].y : 0.0;
+            rec[(15 + 3 * q) * n + e] = okf ? sc * g[q].z : 0.0;
+        }
+    } else {
+        rec[12 * n + e] = ok ? -sc * (th - tb) : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_contact_eval(int nc, const int *cverts, const double *cw, const double *cn,
+                                                      double eta, double kc, const double *x, const double *v,
+                                                      DevParams P, double *rec) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nc) return;
+    const d3 nrm = mk(cn[3 * e], cn[3 * e + 1], cn[3 * e + 2]);
+    double gx = 0.0, gy = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double c = cw[4 * e + q];
+        const int vq = cverts[4 * e + q];
+        const d3 xq = ld3(x, vq);
+        const d3 yq = xq + (P.s_look * P.h) * ld3(v, vq);
+        gx += c * dot(nrm, xq);
+        gy += c * dot(nrm, yq);
+    }
+    rec[e] = gx < eta ? kc : 0.0;
+    rec[(int64_t)nc + e] = gy < eta ? kc * (eta - gy) : 0.0;
+}
 
 struct AsmArgs {
     int nv, nt, nh;
-    const int *tri, *hinge, *inc_ptr, *inc;
+    const int *tri, *hinge, *inc_ptr;
+    int *inc;                    // per-row incidence codes; the pattern pass sorts each row in place
     int nc;                      // contacts: vertices (nc x 4), weights (nc x 4), normals (nc x 3)
     const int *cverts;
     const double *cw, *cn;
-    double ceta, ckc;            // thickness, stiffness
-    const double *Bm, *A0, *hcoef, *htbar, *mass;
+    const double *Bm, *A0, *mass;
+    const double *trec, *hrec, *crec;   // element records of this assembly
     const uint8_t *pinned;
-    const double *x, *v;
+    const double *v;
     DevParams prm;
     int *rowlen, *rowptr, *colidx, *jcol;
     int16_t *jdel;
-    const int *row_lane, *row_slice, *slice_row0, *slice_vbase;
+    const int *row_lane, *row_slice, *slice_row0, *slice_vbase, *slot_off;
     const uint8_t *slot_cnt;
+    uint8_t *row_state;          // ROW_GROUP, ROW_WIDE, ROW_OVERFLOW or ROW_WIDE_OVERFLOW
+    int *wide_rows, *wide_count; // rows of the wide-row pass (list and its length)
     void *jval;
     double *jval_hi;   // FP64 copy (nullptr when the solver copy is FP64)
     double *b, *diag;
@@ -396,111 +511,193 @@ struct AsmArgs {
     int *status;
 };
 
-// Load the row's incidences (sorted) and the vertices of each element.
-__device__ __forceinline__ int row_load(RowPatLDS &L, const AsmArgs &A, int i) {
-    const int t = threadIdx.x;
-    const int p0 = A.inc_ptr[i];
-    const int n = A.inc_ptr[i + 1] - p0;
-    if (n > MAX_INC) return -1;
-    L.inc[t] = t < n ? (unsigned)A.inc[p0 + t] : NONE;
-    __syncthreads();
-    bitonic_lds<64>(L.inc);
-    if (t < n) {
-        const unsigned code = L.inc[t];
-        const int e = inc_elem(code);
-        const unsigned type = inc_type(code);
-        if (type == INC_HINGE) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) L.ev[t][q] = A.hinge[q * A.nh + e];
-        } else if (type == INC_CONTACT) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) L.ev[t][q] = A.cverts[4 * e + q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < 3; ++q) L.ev[t][q] = A.tri[q * A.nt + e];
-            L.ev[t][3] = -1;
-        }
-    }
-    __syncthreads();
-    return n;
+// ---------------------------------------------------------------- row groups
+// A row is handled by a group of G lanes: G = 16 in the main passes (four
+// rows per 64-lane workgroup), G = 64 in the wide-row passes (one row per
+// workgroup, larger capacities), for rows with more than RG_NI incidences.
+// The group's LDS holds the row's incidence codes (sorted: triangles, hinges,
+// contacts, each by index), the vertices of each incidence's element, the
+// column candidates (the element neighbours of the row's vertex) and the
+// row's distinct columns.
+constexpr int RG = 16, RG_ROWS = 4, RG_NI = 32;
+constexpr int WIDE_NI = 512;
+// Which pass assembles a row: the row group pass, the wide-row pass, or
+// neither because the row exceeds the capacities (found by the row group
+// pass: more than MAX_COLS columns; by the wide-row pass: more than WIDE_NI
+// incidences or MAX_COLS columns).  Such a row gets a zero diagonal block
+// and the status word makes every solve refuse the matrix.
+enum : uint8_t { ROW_GROUP = 0, ROW_WIDE = 1, ROW_OVERFLOW = 2, ROW_WIDE_OVERFLOW = 3 };
+
+template <int NI>
+struct RowGroupLDS {
+    unsigned code[NI];
+    int4 ev[NI];             // element vertices (w = -1 for triangles)
+    int cand[3 * NI];        // column candidates, in no particular order
+    uint8_t first[3 * NI];   // candidate p is the first of its value
+    int cols[3 * NI + 1];    // distinct columns ascending, diagonal included; the
+                             // pattern pass also stages the unsorted codes here
+    int ncand;
+};
+
+__device__ __forceinline__ int4 element_vertices(const AsmArgs &A, unsigned code) {
+    const int e = inc_elem(code);
+    const unsigned type = inc_type(code);
+    if (type == INC_HINGE)
+        return make_int4(A.hinge[e], A.hinge[A.nh + e], A.hinge[2 * A.nh + e], A.hinge[3 * A.nh + e]);
+    if (type == INC_CONTACT)
+        return make_int4(A.cverts[4 * e], A.cverts[4 * e + 1], A.cverts[4 * e + 2], A.cverts[4 * e + 3]);
+    return make_int4(A.tri[e], A.tri[A.nt + e], A.tri[2 * A.nt + e], -1);
 }
 
-// Distinct block columns of row i, ascending, diagonal included.  The column
-// set is {i} together with the other corners of every incident triangle, the
-// opposite wing of every hinge in which i is a wing (edge endpoints of a
-// hinge already share a triangle with its wings) and the other three
-// vertices of every incident contact.  Each incidence offers up to 3
-// candidates (4 slots per lane, 256 in all), sorted and de-duplicated.
-// Returns the row length or -1 when it exceeds MAX_COLS; L.cols holds the
-// columns.
-__device__ __forceinline__ int row_columns(RowPatLDS &L, int i, int n) {
-    const int t = threadIdx.x;
-    unsigned c[4] = {NONE, NONE, NONE, NONE};
-    if (t < n) {
-        const unsigned code = L.inc[t];
-        const int k = inc_corner(code);
-        const unsigned type = inc_type(code);
-        if (type == INC_TRI) {
-            c[0] = (unsigned)L.ev[t][(k + 1) % 3];
-            c[1] = (unsigned)L.ev[t][(k + 2) % 3];
-        } else if (type == INC_HINGE) {
-            if (k == 2) c[0] = (unsigned)L.ev[t][3];
-            if (k == 3) c[0] = (unsigned)L.ev[t][2];
-        } else {   // the three corners other than k, in order
-            c[0] = (unsigned)L.ev[t][k == 0 ? 1 : 0];
-            c[1] = (unsigned)L.ev[t][k <= 1 ? 2 : 1];
-            c[2] = (unsigned)L.ev[t][k <= 2 ? 3 : 2];
+// Column candidates of one incidence: the other corners of a triangle, the
+// opposite wing of a hinge in which the row's vertex is a wing (the edge's
+// endpoints already share a triangle with both wings), the other three
+// vertices of a contact, appended to the group's list.
+template <int NI>
+__device__ __forceinline__ void push_candidates(RowGroupLDS<NI> &L, unsigned code, int4 ev) {
+    const int k = inc_corner(code);
+    const unsigned type = inc_type(code);
+    if (type == INC_TRI) {
+        const int pos = atomicAdd(&L.ncand, 2);
+        L.cand[pos] = k == 0 ? ev.y : (k == 1 ? ev.z : ev.x);
+        L.cand[pos + 1] = k == 0 ? ev.z : (k == 1 ? ev.x : ev.y);
+    } else if (type == INC_HINGE) {
+        if (k >= 2) L.cand[atomicAdd(&L.ncand, 1)] = k == 2 ? ev.w : ev.z;
+    } else {
+        const int pos = atomicAdd(&L.ncand, 3);
+        L.cand[pos] = k == 0 ? ev.y : ev.x;
+        L.cand[pos + 1] = k <= 1 ? ev.z : ev.y;
+        L.cand[pos + 2] = k <= 2 ? ev.w : ev.z;
+    }
+}
+
+// Sum over the G lanes of a group (fixed butterfly order; G divides 64).
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
+    return v;
+}
+template <int G>
+__device__ __forceinline__ int group_sum_int(int v) {
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, WAVE);
+    return v;
+}
+
+// Steps shared by both passes, called by every lane of the workgroup (they
+// contain its barriers).  `act`: the group works on row i with n incidences
+// (n <= NI), whose sorted codes are in L.code.
+// 1. element vertices and column candidates of each incidence;
+// 2. first occurrence of each candidate value;
+// 3. distinct columns ascending with the diagonal, returns their number.
+template <int G, int NI>
+__device__ __forceinline__ int row_columns_g(RowGroupLDS<NI> &L, const AsmArgs &A, int i, int n, bool act, int t) {
+    if (act) {
+        if (t == 0) L.ncand = 0;
+    }
+    __syncthreads();
+    if (act) {
+        for (int m = t; m < n; m += G) {
+            const unsigned code = L.code[m];
+            const int4 ev = element_vertices(A, code);
+            L.ev[m] = ev;
+            push_candidates(L, code, ev);
         }
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) L.cand[4 * t + q] = c[q];
     __syncthreads();
-    bitonic_lds<256>(L.cand);
-    int u[4], cnt = 0, below = 0;
-    const unsigned ui = (unsigned)i;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int idx = 4 * t + q;
-        c[q] = L.cand[idx];
-        const unsigned prev = idx > 0 ? L.cand[idx - 1] : NONE;
-        u[q] = (c[q] != NONE) && (idx == 0 || c[q] != prev);
-        cnt += u[q];
-        below += (u[q] && c[q] < ui);
+    const int nc = act ? L.ncand : 0;
+    for (int p = t; p < nc; p += G) {
+        const int c = L.cand[p];
+        bool f = true;
+        for (int q = 0; q < p; ++q) f = f && L.cand[q] != c;
+        L.first[p] = f ? 1 : 0;
     }
-    const int pre = wave_excl_scan(cnt);
-    const int total = __shfl(pre + cnt, WAVE - 1, WAVE);
-    const int dpos = wave_sum_int(below);
-    if (total + 1 > MAX_COLS) return -1;
-    int o = pre;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (u[q]) {
-            L.cols[o + (c[q] > ui ? 1 : 0)] = (int)c[q];
-            ++o;
-        }
-    if (t == 0) L.cols[dpos] = i;
     __syncthreads();
-    return total + 1;
+    int nd = 0, below = 0;
+    for (int p = 0; p < nc; ++p) {
+        const int f = L.first[p];
+        nd += f;
+        below += f && L.cand[p] < i;
+    }
+    for (int p = t; p < nc; p += G) {
+        if (!L.first[p]) continue;
+        const int c = L.cand[p];
+        int r = 0;
+        for (int q = 0; q < nc; ++q) r += L.first[q] && L.cand[q] < c;
+        L.cols[r + (c > i ? 1 : 0)] = c;
+    }
+    if (act && t == 0) L.cols[below] = i;
+    __syncthreads();
+    return nd + 1;
+}
+
+// Pattern pass of one row: sort its incidence codes (rank sort; codes of a
+// row are distinct) and write them back in place, then count its distinct
+// columns.  Returns the row length, 0 when n > NI (not handled here).
+template <int G, int NI>
+__device__ __forceinline__ int row_pattern_g(RowGroupLDS<NI> &L, const AsmArgs &A, int i, bool act, int t) {
+    int p0 = 0, n = 0;
+    if (act) {
+        p0 = A.inc_ptr[i];
+        n = A.inc_ptr[i + 1] - p0;
+    }
+    const bool fits = act && n <= NI;
+    if (fits)
+        for (int m = t; m < n; m += G) L.cols[m] = A.inc[p0 + m];
+    __syncthreads();
+    if (fits)
+        for (int m = t; m < n; m += G) {
+            const unsigned key = (unsigned)L.cols[m];
+            int r = 0;
+            for (int q = 0; q < n; ++q) r += (unsigned)L.cols[q] < key;
+            L.code[r] = key;
+        }
+    __syncthreads();
+    if (fits)
+        for (int m = t; m < n; m += G) A.inc[p0 + m] = (int)L.code[m];
+    const int len = row_columns_g<G, NI>(L, A, i, n, fits, t);
+    return fits ? len : 0;
+}
+
+// Lane-level: rows a group passes on to the wide-row pass, and rows beyond
+// every capacity (length 1, reported through the status word).
+__device__ __forceinline__ void row_record(const AsmArgs &A, int i, int len, bool wide_pass) {
+    if (len > MAX_COLS || (len == 0 && wide_pass)) {
+        atomicOr(A.status, len > MAX_COLS ? ST_COL_OVERFLOW : ST_INC_OVERFLOW);
+        A.rowlen[i] = 1;
+        A.row_state[i] = wide_pass ? ROW_WIDE_OVERFLOW : ROW_OVERFLOW;
+    } else if (len == 0) {
+        A.row_state[i] = ROW_WIDE;
+        A.wide_rows[atomicAdd(A.wide_count, 1)] = i;
+    } else {
+        A.rowlen[i] = len;
+        A.row_state[i] = wide_pass ? ROW_WIDE : ROW_GROUP;
+    }
 }
 
 __global__ void __launch_bounds__(64) k_row_pattern(AsmArgs A) {
-    __shared__ RowPatLDS L;
-    const int i = xcd_remap(blockIdx.x, gridDim.x);
-    if (i >= A.nv) return;
-    const int n = row_load(L, A, i);
-    if (n < 0) {
-        if (threadIdx.x == 0) {
-            atomicOr(A.status, ST_INC_OVERFLOW);
-            A.rowlen[i] = 1;
-        }
-        return;
-    }
-    const int len = row_columns(L, i, n);
-    if (threadIdx.x == 0) {
-        if (len < 0) atomicOr(A.status, ST_COL_OVERFLOW);
-        A.rowlen[i] = len < 0 ? 1 : len;
+    __shared__ RowGroupLDS<RG_NI> Ls[RG_ROWS];
+    const int g = threadIdx.x / RG, t = threadIdx.x % RG;
+    const int i = xcd_remap(blockIdx.x, gridDim.x) * RG_ROWS + g;
+    const bool act = i < A.nv;
+    const int len = row_pattern_g<RG, RG_NI>(Ls[g], A, i, act, t);
+    if (act && t == 0) row_record(A, i, len, false);
+}
+
+// Wide rows: one workgroup per row, a grid-stride loop over the list the
+// row group pass made (every workgroup leaves the loop once the list ends).
+__global__ void __launch_bounds__(64) k_row_pattern_wide(AsmArgs A) {
+    __shared__ RowGroupLDS<WIDE_NI> L;
+    const int nw = *A.wide_count;
+    for (int idx = blockIdx.x; idx < nw; idx += gridDim.x) {
+        const int i = A.wide_rows[idx];
+        const int len = row_pattern_g<WAVE, WIDE_NI>(L, A, i, true, threadIdx.x);
+        if (threadIdx.x == 0) row_record(A, i, len, true);
+        __syncthreads();
     }
 }
+
 
 // Solver layout of one slice (up to 64 consecutive rows of one instance):
 // rows ordered by decreasing length (ties by row), lane_row / row_lane give
@@ -510,7 +707,7 @@ __global__ void __launch_bounds__(64) k_row_pattern(AsmArgs A) {
 // slice_psize, the padded block count of each slice).
 __global__ void __launch_bounds__(64) k_slice_layout(int nslices, const int *slice_row0, const int *rowlen,
                                                      int *lane_row, int *row_lane, uint8_t *slot_cnt,
-                                                     int *slice_psize) {
+                                                     int *slot_off, int *slice_psize) {
     const int s = blockIdx.x;
     if (s >= nslices) return;
     const int t = threadIdx.x;
@@ -529,6 +726,7 @@ __global__ void __launch_bounds__(64) k_slice_layout(int nslices, const int *sli
         if (t == k) c = __popcll(bal);
     }
     slot_cnt[s * WAVE + t] = (uint8_t)c;
+    slot_off[s * WAVE + t] = wave_excl_scan(slot_width(c));
     const int padded = wave_sum_int(slot_width(c));
     if (t == 0) slice_psize[s] = padded;
 }
@@ -578,255 +776,234 @@ __device__ __forceinline__ void store_block_inverse(float *out, double a, double
     }
 }
 
-template <typename TB>
-__global__ void __launch_bounds__(64) k_row_assemble(AsmArgs A) {
-    __shared__ RowLDS L;
-    const int i = xcd_remap(blockIdx.x, gridDim.x);
-    if (i >= A.nv) return;
-    const int t = threadIdx.x;
-    const int n = row_load(L, A, i);
-    if (n < 0) {  // reported by the pattern pass; keep the layout valid
-        if (t == 0) write_overflow_row<TB>(A, i);
-        return;
-    }
+// ---------------------------------------------------------------- values
+// Stiffness block K_kl of one incidence (the row's vertex is corner k, the
+// column's vertex corner l) from the element records, added to acc:
+//   triangle  A0 [mu (b_k.b_l) F F^T + mu u_l u_k^T + lam u_k u_l^T + (b_k^T S+ b_l) I],  u = F b
+//   hinge     G_k G_l^T
+//   contact   kc_act c_k c_l n n^T
+__device__ __forceinline__ void add_stiffness(const AsmArgs &A, unsigned code, int l, double acc[9]) {
+    const int e = inc_elem(code), k = inc_corner(code);
+    const unsigned type = inc_type(code);
     const DevParams &P = A.prm;
+    if (type == INC_TRI) {
+        const int64_t n = A.nt;
+        const double B0 = A.Bm[e], B1 = A.Bm[n + e], B2 = A.Bm[2 * n + e], B3 = A.Bm[3 * n + e];
+        double bk0, bk1, bl0, bl1;
+        if (k == 0) { bk0 = -B0 - B2; bk1 = -B1 - B3; }
+        else if (k == 1) { bk0 = B0; bk1 = B1; }
+        else { bk0 = B2; bk1 = B3; }
+        if (l == 0) { bl0 = -B0 - B2; bl1 = -B1 - B3; }
+        else if (l == 1) { bl0 = B0; bl1 = B1; }
+        else { bl0 = B2; bl1 = B3; }
+        const double a0 = A.A0[e];
+        const double *R = A.trec;
+        const double F00 = R[e], F01 = R[n + e], F10 = R[2 * n + e], F11 = R[3 * n + e], F20 = R[4 * n + e],
+                     F21 = R[5 * n + e];
+        const double S0 = R[6 * n + e], S1 = R[7 * n + e], S2 = R[8 * n + e];
+        const double uk[3] = {F00 * bk0 + F01 * bk1, F10 * bk0 + F11 * bk1, F20 * bk0 + F21 * bk1};
+        const double ul[3] = {F00 * bl0 + F01 * bl1, F10 * bl0 + F11 * bl1, F20 * bl0 + F21 * bl1};
+        const double Fr[3][2] = {{F00, F01}, {F10, F11}, {F20, F21}};
+        const double bb = bk0 * bl0 + bk1 * bl1;
+        const double bSb = bk0 * (S0 * bl0 + S1 * bl1) + bk1 * (S1 * bl0 + S2 * bl1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const double fft = Fr[a][0] * Fr[b][0] + Fr[a][1] * Fr[b][1];
+                double val = P.mu * bb * fft + P.mu * ul[a] * uk[b] + P.lam * uk[a] * ul[b];
+                if (a == b) val += bSb;
+                acc[3 * a + b] += a0 * val;
+            }
+    } else if (type == INC_HINGE) {
+        const int64_t n = A.nh;
+        const double *R = A.hrec;
+        const double gk[3] = {R[(3 * k) * n + e], R[(3 * k + 1) * n + e], R[(3 * k + 2) * n + e]};
+        const double gl[3] = {R[(3 * l) * n + e], R[(3 * l + 1) * n + e], R[(3 * l + 2) * n + e]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) acc[3 * a + b] += gk[a] * gl[b];
+    } else {
+        const double nr[3] = {A.cn[3 * e], A.cn[3 * e + 1], A.cn[3 * e + 2]};
+        const double sc = A.crec[e] * A.cw[4 * e + k] * A.cw[4 * e + l];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) acc[3 * a + b] += sc * nr[a] * nr[b];
+    }
+}
 
-    // ---- phase A: lane t evaluates incidence t's element
-    if (t < n) {
-        const unsigned code = L.inc[t];
-        const int e = inc_elem(code);
-        const int k = inc_corner(code);
-        const unsigned type = inc_type(code);
-        if (type == INC_CONTACT) {
-            // repulsion element: gap g = n . sum_q c_q x_q, energy kc/2 (eta - g)^2
-            // while g < eta; K_kl = kc c_k c_l n n^T (active at x), force on
-            // corner k kc (eta - g) c_k n (active at the force state)
-            const d3 nrm = mk(A.cn[3 * e], A.cn[3 * e + 1], A.cn[3 * e + 2]);
-            double cw[4];
-            double gx = 0.0, gy = 0.0;
+// Force of one incidence on the row's vertex (corner k) at the force state.
+__device__ __forceinline__ void add_force(const AsmArgs &A, unsigned code, double f[3]) {
+    const int e = inc_elem(code), k = inc_corner(code);
+    const unsigned type = inc_type(code);
+    const bool look = A.prm.s_look != 0.0;
+    if (type == INC_TRI) {
+        // f_k = -A0 F S beta_k
+        const int64_t n = A.nt;
+        const double B0 = A.Bm[e], B1 = A.Bm[n + e], B2 = A.Bm[2 * n + e], B3 = A.Bm[3 * n + e];
+        const double bk0 = k == 0 ? -B0 - B2 : (k == 1 ? B0 : B2);
+        const double bk1 = k == 0 ? -B1 - B3 : (k == 1 ? B1 : B3);
+        const double a0 = A.A0[e];
+        const double *R = A.trec;
+        const int fb = look ? 12 : 0;
+        const double S0 = R[9 * n + e], S1 = R[10 * n + e], S2 = R[11 * n + e];
+        const double sb0 = S0 * bk0 + S1 * bk1;
+        const double sb1 = S1 * bk0 + S2 * bk1;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                cw[q] = A.cw[4 * e + q];
-                const int vq = L.ev[t][q];
-                const d3 xq = ld3(A.x, vq);
-                const d3 yq = xq + (P.s_look * P.h) * ld3(A.v, vq);
-                gx += cw[q] * dot(nrm, xq);
-                gy += cw[q] * dot(nrm, yq);
-            }
-            double *ed = L.ed[t];
-            ed[0] = nrm.x; ed[1] = nrm.y; ed[2] = nrm.z;
-            ed[3] = cw[0]; ed[4] = cw[1]; ed[5] = cw[2]; ed[6] = cw[3];
-            ed[7] = gx < A.ceta ? A.ckc : 0.0;
-            const double ck = k == 0 ? cw[0] : (k == 1 ? cw[1] : (k == 2 ? cw[2] : cw[3]));
-            const double m = gy < A.ceta ? A.ckc * (A.ceta - gy) * ck : 0.0;
-            L.fk[t][0] = m * nrm.x; L.fk[t][1] = m * nrm.y; L.fk[t][2] = m * nrm.z;
-        } else if (type == INC_TRI) {
-            TriShape sh;
-            const double B0 = A.Bm[e], B1 = A.Bm[A.nt + e], B2 = A.Bm[2 * A.nt + e], B3 = A.Bm[3 * A.nt + e];
-            sh.b[1][0] = B0; sh.b[1][1] = B1;
-            sh.b[2][0] = B2; sh.b[2][1] = B3;
-            sh.b[0][0] = -B0 - B2; sh.b[0][1] = -B1 - B3;
-            const double a0 = A.A0[e];
-            d3 xs[3], ys[3];
+        for (int a = 0; a < 3; ++a)
+            f[a] += -a0 * (R[(fb + 2 * a) * n + e] * sb0 + R[(fb + 2 * a + 1) * n + e] * sb1);
+    } else if (type == INC_HINGE) {
+        const int64_t n = A.nh;
+        const double *R = A.hrec;
+        const double phi = R[12 * n + e];
+        const int gb = look ? 13 + 3 * k : 3 * k;
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const int vq = L.ev[t][q];
-                xs[q] = ld3(A.x, vq);
-                ys[q] = xs[q] + (P.s_look * P.h) * ld3(A.v, vq);
-            }
-            double F[3][2], S[3], Sp[3];
-            tri_F(xs, sh, F);
-            tri_stress(F, P.mu, P.lam, S);
-            psd_part(S, Sp);
-            double *ed = L.ed[t];
-            ed[0] = F[0][0]; ed[1] = F[0][1]; ed[2] = F[1][0]; ed[3] = F[1][1]; ed[4] = F[2][0]; ed[5] = F[2][1];
-            ed[6] = Sp[0]; ed[7] = Sp[1]; ed[8] = Sp[2];
-            ed[9] = B0; ed[10] = B1; ed[11] = B2; ed[12] = B3; ed[13] = a0;
-            // force on corner k at the lookahead state: f_k = -A0 F S beta_k
-            double Fy[3][2], Sy[3];
-            tri_F(ys, sh, Fy);
-            tri_stress(Fy, P.mu, P.lam, Sy);
-            // corner k's shape gradient, selected without indexing a private array
-            const double bk0 = k == 0 ? sh.b[0][0] : (k == 1 ? sh.b[1][0] : sh.b[2][0]);
-            const double bk1 = k == 0 ? sh.b[0][1] : (k == 1 ? sh.b[1][1] : sh.b[2][1]);
-            const double sb0 = Sy[0] * bk0 + Sy[1] * bk1;
-            const double sb1 = Sy[1] * bk0 + Sy[2] * bk1;
+        for (int a = 0; a < 3; ++a) f[a] += phi * R[(gb + a) * n + e];
+    } else {
+        const double m = A.crec[(int64_t)A.nc + e] * A.cw[4 * e + k];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) L.fk[t][a] = -a0 * (Fy[a][0] * sb0 + Fy[a][1] * sb1);
-        } else {
-            const double ch = A.hcoef[e], tb = A.htbar[e];
-            d3 xs[4], ys[4], g[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int vq = L.ev[t][q];
-                xs[q] = ld3(A.x, vq);
-                ys[q] = xs[q] + (P.s_look * P.h) * ld3(A.v, vq);
-            }
-            double th;
-            double *ed = L.ed[t];
-            if (hinge_eval(xs, th, g)) {
-                const double sc = sqrt(2.0 * P.kb * ch);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    ed[3 * q] = sc * g[q].x; ed[3 * q + 1] = sc * g[q].y; ed[3 * q + 2] = sc * g[q].z;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 12; ++q) ed[q] = 0.0;
-            }
-            if (hinge_eval(ys, th, g)) {
-                const double s = -2.0 * P.kb * ch * (th - tb);
-                d3 gk = g[0];
-#pragma unroll
-                for (int q = 1; q < 4; ++q)
-                    if (q == k) gk = g[q];
-                L.fk[t][0] = s * gk.x; L.fk[t][1] = s * gk.y; L.fk[t][2] = s * gk.z;
-            } else {
-                L.fk[t][0] = L.fk[t][1] = L.fk[t][2] = 0.0;
-            }
-        }
+        for (int a = 0; a < 3; ++a) f[a] += m * A.cn[3 * e + a];
+    }
+}
+
+// Block s of row i (column col) into the block-CSR column list and the
+// solver layout, in the solver's type and, when kept, in FP64.
+template <typename TB>
+__device__ __forceinline__ void store_row_block(const AsmArgs &A, int i, int s, int col, const double blk[9]) {
+    const int si = A.row_slice[i];
+    const int w = slot_width((int)A.slot_cnt[si * WAVE + s]);
+    const int64_t seg = (int64_t)A.slice_vbase[si] + A.slot_off[si * WAVE + s];
+    const int lane = A.row_lane[i];
+    A.colidx[A.rowptr[i] + s] = col;
+    A.jcol[seg + lane] = col;
+    // offset from the slice's first row; meaningful only when it fits (the
+    // solver checks every slice before using it)
+    A.jdel[seg + lane] = (int16_t)(col - A.slice_row0[si]);
+    BlockIO<TB>::store((TB *)A.jval + 9 * seg, w, lane, blk);
+    if (A.jval_hi) BlockIO<double>::store(A.jval_hi + 9 * seg, w, lane, blk);
+}
+
+// Values of one row.  Lane t of the group owns the column slots s = t, t + G,
+// ...; for each it sums, in the row's incidence order, the stiffness blocks
+// of every incident element containing the column's vertex (a deterministic
+// segmented reduce, no floating-point atomics), and writes c K_ij (zero when
+// row or column is pinned).  Row totals (K v, the diagonal of sum_j K_ij, the
+// pinned-column sums for D_i, the off-diagonal sums of the diagonal block)
+// and the element forces are summed per lane in slot / incidence order and
+// then over the group in a fixed butterfly order; the lane holding the
+// diagonal slot writes D_i, b_i, diag(A)_i and both preconditioners.
+template <typename TB, int G, int NI>
+__device__ __forceinline__ void row_values_g(RowGroupLDS<NI> &L, const AsmArgs &A, int i, bool act, int t) {
+    int p0 = 0, n = 0;
+    if (act) {
+        p0 = A.inc_ptr[i];
+        n = A.inc_ptr[i + 1] - p0;
+        for (int m = t; m < n; m += G) L.code[m] = (unsigned)A.inc[p0 + m];
     }
     __syncthreads();
-    const int len = row_columns(L, i, n);
-    if (len < 0) {
-        if (t == 0) write_overflow_row<TB>(A, i);
-        return;
-    }
-
-    // ---- phase B: lane t owns column cols[t]; sum the contributions of all
-    // incidences in their sorted order.
-    const bool active = t < len;
-    const int col = active ? L.cols[t] : i;
-    const bool isdiag = active && col == i;
-    double acc[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) acc[q] = 0.0;
-    if (active && !isdiag) {
-        for (int m = 0; m < n; ++m) {
-            const unsigned code = L.inc[m];
-            const int k = inc_corner(code);
-            const unsigned type = inc_type(code);
-            int l = -1;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (L.ev[m][q] == col) l = q;
-            if (l < 0) continue;
-            const double *ed = L.ed[m];
-            if (type == INC_CONTACT) {
-                const double ck = ed[3 + k], cl = ed[3 + l];
-                const double sc = ed[7] * ck * cl;
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) acc[3 * a + b] += sc * ed[a] * ed[b];
-            } else if (type == INC_TRI) {
-                // K_kl = A0 [mu (b_k.b_l) F F^T + mu u_l u_k^T + lam u_k u_l^T + (b_k^T S+ b_l) I]
-                double bk0, bk1, bl0, bl1;
-                const double B0 = ed[9], B1 = ed[10], B2 = ed[11], B3 = ed[12];
-                if (k == 0) { bk0 = -B0 - B2; bk1 = -B1 - B3; }
-                else if (k == 1) { bk0 = B0; bk1 = B1; }
-                else { bk0 = B2; bk1 = B3; }
-                if (l == 0) { bl0 = -B0 - B2; bl1 = -B1 - B3; }
-                else if (l == 1) { bl0 = B0; bl1 = B1; }
-                else { bl0 = B2; bl1 = B3; }
-                const double a0 = ed[13];
-                const double F00 = ed[0], F01 = ed[1], F10 = ed[2], F11 = ed[3], F20 = ed[4], F21 = ed[5];
-                const double uk[3] = {F00 * bk0 + F01 * bk1, F10 * bk0 + F11 * bk1, F20 * bk0 + F21 * bk1};
-                const double ul[3] = {F00 * bl0 + F01 * bl1, F10 * bl0 + F11 * bl1, F20 * bl0 + F21 * bl1};
-                const double Fr[3][2] = {{F00, F01}, {F10, F11}, {F20, F21}};
-                const double bb = bk0 * bl0 + bk1 * bl1;
-                const double bSb = bk0 * (ed[6] * bl0 + ed[7] * bl1) + bk1 * (ed[7] * bl0 + ed[8] * bl1);
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) {
-                        const double fft = Fr[a][0] * Fr[b][0] + Fr[a][1] * Fr[b][1];
-                        double val = P.mu * bb * fft + P.mu * ul[a] * uk[b] + P.lam * uk[a] * ul[b];
-                        if (a == b) val += bSb;
-                        acc[3 * a + b] += a0 * val;
-                    }
-            } else {
-#pragma unroll
-                for (int a = 0; a < 3; ++a)
-#pragma unroll
-                    for (int b = 0; b < 3; ++b) acc[3 * a + b] += ed[3 * k + a] * ed[3 * l + b];
-            }
-        }
-    }
-
-    // ---- phase C: row totals (fixed butterfly order) and outputs
-    const bool rowpin = A.pinned[i] != 0;
-    const bool colpin = active && !isdiag && A.pinned[col] != 0;
-    const d3 vi = ld3(A.v, i);
-    d3 dvv = mk(0.0, 0.0, 0.0);
-    if (active && !isdiag) dvv = ld3(A.v, col) - vi;
+    const int len = row_columns_g<G, NI>(L, A, i, n, act, t);
+    const DevParams &P = A.prm;
     double red[18];
-    red[0] = acc[0] * dvv.x + acc[1] * dvv.y + acc[2] * dvv.z;
-    red[1] = acc[3] * dvv.x + acc[4] * dvv.y + acc[5] * dvv.z;
-    red[2] = acc[6] * dvv.x + acc[7] * dvv.y + acc[8] * dvv.z;
-    red[3] = acc[0];
-    red[4] = acc[4];
-    red[5] = acc[8];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) red[6 + q] = colpin ? acc[q] : 0.0;
-    // off-diagonal entries of sum_j K_ij (symmetrised): the diagonal block is
-    // A_ii = m_i I - c sum_{j != i} K_ij since every element's block rows sum to zero
-    red[15] = 0.5 * (acc[1] + acc[3]);
-    red[16] = 0.5 * (acc[2] + acc[6]);
-    red[17] = 0.5 * (acc[5] + acc[7]);
+    for (int q = 0; q < 18; ++q) red[q] = 0.0;
+    double f[3] = {0.0, 0.0, 0.0};
+    int dslot = -1;
+    bool rowpin = false;
+    if (act) {
+        rowpin = A.pinned[i] != 0;
+        const d3 vi = ld3(A.v, i);
+        for (int s = t; s < len; s += G) {
+            const int col = L.cols[s];
+            if (col == i) {
+                dslot = s;
+                continue;
+            }
+            double acc[9];
 #pragma unroll
-    for (int q = 0; q < 18; ++q) red[q] = wave_sum(red[q]);
-
+            for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+            for (int m = 0; m < n; ++m) {
+                const int4 ev = L.ev[m];
+                const int l = ev.x == col ? 0 : (ev.y == col ? 1 : (ev.z == col ? 2 : (ev.w == col ? 3 : -1)));
+                if (l >= 0) add_stiffness(A, L.code[m], l, acc);
+            }
+            const bool colpin = A.pinned[col] != 0;
+            const d3 dvv = ld3(A.v, col) - vi;
+            red[0] += acc[0] * dvv.x + acc[1] * dvv.y + acc[2] * dvv.z;
+            red[1] += acc[3] * dvv.x + acc[4] * dvv.y + acc[5] * dvv.z;
+            red[2] += acc[6] * dvv.x + acc[7] * dvv.y + acc[8] * dvv.z;
+            red[3] += acc[0];
+            red[4] += acc[4];
+            red[5] += acc[8];
+            if (colpin)
+#pragma unroll
+                for (int q = 0; q < 9; ++q) red[6 + q] += acc[q];
+            // off-diagonal entries of sum_j K_ij (symmetrised): the diagonal block is
+            // A_ii = m_i I - c sum_{j != i} K_ij since every element's block rows sum to zero
+            red[15] += 0.5 * (acc[1] + acc[3]);
+            red[16] += 0.5 * (acc[2] + acc[6]);
+            red[17] += 0.5 * (acc[5] + acc[7]);
+            double blk[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) blk[q] = (rowpin || colpin) ? 0.0 : P.c * acc[q];
+            store_row_block<TB>(A, i, s, col, blk);
+        }
+        for (int m = t; m < n; m += G) add_force(A, L.code[m], f);
+    }
+#pragma unroll
+    for (int q = 0; q < 18; ++q) red[q] = group_sum<G>(red[q]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f[a] = group_sum<G>(f[a]);
+    if (dslot < 0) return;
+    // D_i = -c sum_{j pinned} K_ij for a free row, 0 for a pinned row
     const double mi = A.mass[i];
     double blk[9];
-    if (isdiag) {
-        // D_i = -c sum_{j pinned} K_ij for a free row, 0 for a pinned row
 #pragma unroll
-        for (int q = 0; q < 9; ++q) blk[q] = rowpin ? 0.0 : -P.c * red[6 + q];
-        // force: gravity plus element forces in incidence order
-        double f0 = mi * P.g[0], f1 = mi * P.g[1], f2 = mi * P.g[2];
-        for (int m = 0; m < n; ++m) {
-            f0 += L.fk[m][0];
-            f1 += L.fk[m][1];
-            f2 += L.fk[m][2];
-        }
-        double bi0 = P.h * (f0 - P.kv_coef * red[0]);
-        double bi1 = P.h * (f1 - P.kv_coef * red[1]);
-        double bi2 = P.h * (f2 - P.kv_coef * red[2]);
-        double d0 = mi - P.c * red[3], d1 = mi - P.c * red[4], d2 = mi - P.c * red[5];
-        if (rowpin) {
-            bi0 = bi1 = bi2 = 0.0;
-            d0 = d1 = d2 = mi;
-        }
-        if (!isfinite(bi0) || !isfinite(bi1) || !isfinite(bi2)) atomicOr(A.status, ST_NONFINITE);
-        A.b[3 * i] = bi0; A.b[3 * i + 1] = bi1; A.b[3 * i + 2] = bi2;
-        A.diag[3 * i] = d0; A.diag[3 * i + 1] = d1; A.diag[3 * i + 2] = d2;
-        A.dinv[3 * i] = (float)(1.0 / d0);
-        A.dinv[3 * i + 1] = (float)(1.0 / d1);
-        A.dinv[3 * i + 2] = (float)(1.0 / d2);
-        const double o01 = rowpin ? 0.0 : -P.c * red[15];
-        const double o02 = rowpin ? 0.0 : -P.c * red[16];
-        const double o12 = rowpin ? 0.0 : -P.c * red[17];
-        store_block_inverse(A.binv + 6 * (int64_t)i, d0, o01, o02, d1, o12, d2);
-    } else {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) blk[q] = (rowpin || colpin) ? 0.0 : P.c * acc[q];
+    for (int q = 0; q < 9; ++q) blk[q] = rowpin ? 0.0 : -P.c * red[6 + q];
+    // force: gravity plus the element forces
+    const double f0 = mi * P.g[0] + f[0], f1 = mi * P.g[1] + f[1], f2 = mi * P.g[2] + f[2];
+    double bi0 = P.h * (f0 - P.kv_coef * red[0]);
+    double bi1 = P.h * (f1 - P.kv_coef * red[1]);
+    double bi2 = P.h * (f2 - P.kv_coef * red[2]);
+    double d0 = mi - P.c * red[3], d1 = mi - P.c * red[4], d2 = mi - P.c * red[5];
+    if (rowpin) {
+        bi0 = bi1 = bi2 = 0.0;
+        d0 = d1 = d2 = mi;
     }
+    if (!isfinite(bi0) || !isfinite(bi1) || !isfinite(bi2)) atomicOr(A.status, ST_NONFINITE);
+    A.b[3 * i] = bi0; A.b[3 * i + 1] = bi1; A.b[3 * i + 2] = bi2;
+    A.diag[3 * i] = d0; A.diag[3 * i + 1] = d1; A.diag[3 * i + 2] = d2;
+    A.dinv[3 * i] = (float)(1.0 / d0);
+    A.dinv[3 * i + 1] = (float)(1.0 / d1);
+    A.dinv[3 * i + 2] = (float)(1.0 / d2);
+    const double o01 = rowpin ? 0.0 : -P.c * red[15];
+    const double o02 = rowpin ? 0.0 : -P.c * red[16];
+    const double o12 = rowpin ? 0.0 : -P.c * red[17];
+    store_block_inverse(A.binv + 6 * (int64_t)i, d0, o01, o02, d1, o12, d2);
+    store_row_block<TB>(A, i, dslot, i, blk);
+}
 
-    // block-CSR pattern and solver layout
-    const int s = A.row_slice[i];
-    const int w = slot_width((int)A.slot_cnt[s * WAVE + t]);
-    const int off = wave_excl_scan(w);
-    if (active) {
-        A.colidx[A.rowptr[i] + t] = col;
-        const int64_t seg = (int64_t)A.slice_vbase[s] + off;
-        const int lane = A.row_lane[i];
-        A.jcol[seg + lane] = col;
-        // offset from the slice's first row; meaningful only when it fits
-        // (the solver checks every slice before using it)
-        A.jdel[seg + lane] = (int16_t)(col - A.slice_row0[s]);
-        BlockIO<TB>::store((TB *)A.jval + 9 * seg, w, lane, blk);
-        if (A.jval_hi) BlockIO<double>::store(A.jval_hi + 9 * seg, w, lane, blk);
+template <typename TB>
+__global__ void __launch_bounds__(64) k_row_values(AsmArgs A) {
+    __shared__ RowGroupLDS<RG_NI> Ls[RG_ROWS];
+    const int g = threadIdx.x / RG, t = threadIdx.x % RG;
+    const int i = xcd_remap(blockIdx.x, gridDim.x) * RG_ROWS + g;
+    const int st = i < A.nv ? (int)A.row_state[i] : -1;
+    if (st == ROW_OVERFLOW && t == 0) write_overflow_row<TB>(A, i);
+    row_values_g<TB, RG, RG_NI>(Ls[g], A, i, st == ROW_GROUP, t);
+}
+
+template <typename TB>
+__global__ void __launch_bounds__(64) k_row_values_wide(AsmArgs A) {
+    __shared__ RowGroupLDS<WIDE_NI> L;
+    const int nw = *A.wide_count;
+    for (int idx = blockIdx.x; idx < nw; idx += gridDim.x) {
+        const int i = A.wide_rows[idx];
+        const int st = (int)A.row_state[i];
+        if (st == ROW_WIDE_OVERFLOW && threadIdx.x == 0) write_overflow_row<TB>(A, i);
+        row_values_g<TB, WAVE, WIDE_NI>(L, A, i, st == ROW_WIDE, threadIdx.x);
+        __syncthreads();
     }
 }
 
@@ -922,43 +1099,87 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
         ctx->hi_blocks = ctx->vcap;
     }
     ctx->hi_valid = dtype != PC_F64;
-    // 1. incidence buckets (the row-limit bits describe this assembly only)
-    const int slot_all = ctx->prof.begin(PK_ASM_ALL, s);
-    hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(64), 0, s, ctx->status, ST_INC_OVERFLOW | ST_COL_OVERFLOW);
+    // element records of this assembly (their size depends on the force state and the contact set)
+    const bool look = ctx->prm.s_look != 0.0;
     const int nc = ctx->nc;
+    struct Need { double **p; size_t *have; size_t n; } recs[3] = {
+        {&ctx->trec, &ctx->trec_elems, (size_t)(look ? TREC_LOOK : TREC) * nt},
+        {&ctx->hrec, &ctx->hrec_elems, (size_t)(look ? HREC_LOOK : HREC) * nh},
+        {&ctx->crec, &ctx->crec_elems, (size_t)CREC * nc}};
+    for (auto &r : recs)
+        if (r.n > *r.have) {
+            dev_free(ctx, *r.p);
+            *r.p = nullptr;
+            *r.have = 0;
+            if ((st = dev_alloc(ctx, (void **)r.p, sizeof(double) * r.n))) return st;
+            *r.have = r.n;
+        }
+    if (!ctx->row_state) {
+        if ((st = dev_alloc(ctx, (void **)&ctx->row_state, (size_t)nv))) return st;
+        if ((st = dev_alloc(ctx, (void **)&ctx->wide_rows, sizeof(int) * (size_t)nv))) return st;
+    }
+    const int slot_all = ctx->prof.begin(PK_ASM_ALL, s);
+    // 1. elements, each evaluated once
+    int slot = ctx->prof.begin(PK_ELEMENTS, s);
+    hipLaunchKernelGGL(k_tri_eval, dim3((nt + TB - 1) / TB), dim3(TB), 0, s, nt, ctx->tri, ctx->Bm, x, v, ctx->prm,
+                       ctx->trec);
+    if (nh > 0)
+        hipLaunchKernelGGL(k_hinge_eval, dim3((nh + TB - 1) / TB), dim3(TB), 0, s, nh, ctx->hinge, ctx->hcoef,
+                           ctx->htbar, x, v, ctx->prm, ctx->hrec);
+    if (nc > 0)
+        hipLaunchKernelGGL(k_contact_eval, dim3((nc + TB - 1) / TB), dim3(TB), 0, s, nc, ctx->cverts, ctx->cw,
+                           ctx->cn, ctx->ceta, ctx->ckc, x, v, ctx->prm, ctx->crec);
+    ctx->prof.end(slot, s);
+    // 2. incidence buckets (the row-limit bits describe this assembly only)
+    hipLaunchKernelGGL(k_clear_bits, dim3(1), dim3(64), 0, s, ctx->status, ST_INC_OVERFLOW | ST_COL_OVERFLOW);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, (int *)ctx->counter + 1, 0, (int64_t)1);
     const int64_t ni = 3 * (int64_t)nt + 4 * (int64_t)nh + 4 * (int64_t)nc;
     hipLaunchKernelGGL(k_inc_count, dim3((ni + TB - 1) / TB), dim3(TB), 0, s, nt, nh, nc, ctx->tri, ctx->hinge,
                        ctx->cverts, ctx->inc_cnt);
     if ((st = scan_excl(ctx, ctx->inc_cnt, ctx->inc_ptr, nv, s))) return st;
     hipLaunchKernelGGL(k_inc_fill, dim3((ni + TB - 1) / TB), dim3(TB), 0, s, nt, nh, nc, ctx->tri, ctx->hinge,
                        ctx->cverts, ctx->inc_cnt, ctx->inc_ptr, ctx->inc);
-    // 2. row lengths and pointers
+    // 3. row patterns: sorted incidences, row lengths, pointers
     AsmArgs a;
     a.nv = nv; a.nt = nt; a.nh = nh;
     a.tri = ctx->tri; a.hinge = ctx->hinge; a.inc_ptr = ctx->inc_ptr; a.inc = ctx->inc;
-    a.nc = nc; a.cverts = ctx->cverts; a.cw = ctx->cw; a.cn = ctx->cn; a.ceta = ctx->ceta; a.ckc = ctx->ckc;
-    a.Bm = ctx->Bm; a.A0 = ctx->A0; a.hcoef = ctx->hcoef; a.htbar = ctx->htbar; a.mass = ctx->mass;
-    a.pinned = ctx->pinned; a.x = x; a.v = v; a.prm = ctx->prm;
+    a.nc = nc; a.cverts = ctx->cverts; a.cw = ctx->cw; a.cn = ctx->cn;
+    a.Bm = ctx->Bm; a.A0 = ctx->A0; a.mass = ctx->mass;
+    a.trec = ctx->trec; a.hrec = ctx->hrec; a.crec = ctx->crec;
+    a.pinned = ctx->pinned; a.v = v; a.prm = ctx->prm;
     a.rowlen = ctx->rowlen; a.rowptr = ctx->rowptr; a.colidx = ctx->colidx; a.jcol = ctx->jcol; a.jdel = ctx->jdel;
-    a.row_lane = ctx->row_lane; a.slot_cnt = ctx->slot_cnt; a.jval = ctx->jval;
+    a.row_lane = ctx->row_lane; a.slot_cnt = ctx->slot_cnt; a.slot_off = ctx->slot_off; a.jval = ctx->jval;
     a.row_slice = ctx->row_slice; a.slice_row0 = ctx->slice_row0; a.slice_vbase = ctx->slice_vbase;
+    a.row_state = ctx->row_state; a.wide_rows = ctx->wide_rows; a.wide_count = (int *)ctx->counter + 1;
     a.jval_hi = dtype != PC_F64 ? ctx->jval_hi : nullptr;
     a.b = b; a.diag = diag_out ? diag_out : ctx->diag; a.dinv = ctx->dinv; a.binv = ctx->binv; a.status = ctx->status;
-    const int nb = ((nv + 7) / 8) * 8;
-    int slot = ctx->prof.begin(PK_ROW_PAT, s);
-    hipLaunchKernelGGL(k_row_pattern, dim3(nb), dim3(64), 0, s, a);
+    // four rows per workgroup; a multiple of 8 workgroups for the XCD mapping
+    const int ng = (((nv + RG_ROWS - 1) / RG_ROWS + 7) / 8) * 8;
+    const int nwide = 256;   // workgroups of the wide-row passes (grid-stride over the list)
+    slot = ctx->prof.begin(PK_ROW_PAT, s);
+    hipLaunchKernelGGL(k_row_pattern, dim3(ng), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_row_pattern_wide, dim3(nwide), dim3(64), 0, s, a);
     ctx->prof.end(slot, s);
     if ((st = scan_excl(ctx, ctx->rowlen, ctx->rowptr, nv, s))) return st;
-    // 3. solver layout
+    // 4. solver layout
     hipLaunchKernelGGL(k_slice_layout, dim3(ctx->nslices), dim3(64), 0, s, ctx->nslices, ctx->slice_row0,
-                       ctx->rowlen, ctx->lane_row, ctx->row_lane, ctx->slot_cnt, ctx->slice_psize);
+                       ctx->rowlen, ctx->lane_row, ctx->row_lane, ctx->slot_cnt, ctx->slot_off, ctx->slice_psize);
     if ((st = scan_excl(ctx, ctx->slice_psize, ctx->slice_vbase, ctx->nslices, s))) return st;
-    // 4. values
+    // 5. values
     slot = ctx->prof.begin(PK_ROW_ASM, s);
     switch (dtype) {
-        case PC_F64: hipLaunchKernelGGL(k_row_assemble<double>, dim3(nb), dim3(64), 0, s, a); break;
-        case PC_F32: hipLaunchKernelGGL(k_row_assemble<float>, dim3(nb), dim3(64), 0, s, a); break;
-        case PC_BF16: hipLaunchKernelGGL(k_row_assemble<bf16_t>, dim3(nb), dim3(64), 0, s, a); break;
+        case PC_F64:
+            hipLaunchKernelGGL(k_row_values<double>, dim3(ng), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(k_row_values_wide<double>, dim3(nwide), dim3(64), 0, s, a);
+            break;
+        case PC_F32:
+            hipLaunchKernelGGL(k_row_values<float>, dim3(ng), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(k_row_values_wide<float>, dim3(nwide), dim3(64), 0, s, a);
+            break;
+        case PC_BF16:
+            hipLaunchKernelGGL(k_row_values<bf16_t>, dim3(ng), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(k_row_values_wide<bf16_t>, dim3(nwide), dim3(64), 0, s, a);
+            break;
     }
     ctx->prof.end(slot, s);
     ctx->prof.end(slot_all, s);

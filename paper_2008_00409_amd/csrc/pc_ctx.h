@@ -37,7 +37,7 @@ struct PcgState {
 // `every`-th launch of a timed kind is bracketed by an event pair; pairs are
 // read back at the next synchronisation point.
 enum ProfKind { PK_SPMV = 0, PK_UPDATE = 1, PK_DIR = 2, PK_ROW_ASM = 3, PK_ROW_PAT = 4, PK_ASM_ALL = 5,
-                PK_NKINDS = 8 };
+                PK_ELEMENTS = 6, PK_NKINDS = 8 };
 
 struct Prof {
     int every = 0;
@@ -187,6 +187,12 @@ struct Ctx {
     int *lane_row = nullptr;  // nslices * 64 (row of each lane, -1 padding)
     int *row_lane = nullptr;  // nv
     uint8_t *slot_cnt = nullptr;  // nslices * 64
+    int *slot_off = nullptr;      // nslices * 64: first stored block of each slot, from the slice's first
+    uint8_t *row_state = nullptr; // nv: which assembly pass handles each row
+    int *wide_rows = nullptr;     // nv: rows of the wide-row passes
+    // element records of the last assembly (FP64 SoA planes; sizes in doubles)
+    double *trec = nullptr, *hrec = nullptr, *crec = nullptr;
+    size_t trec_elems = 0, hrec_elems = 0, crec_elems = 0;
     int *slice_row0 = nullptr;    // nslices + 1: first row of each slice
     int *row_slice = nullptr;     // nv: slice of each row
     int *slice_psize = nullptr;   // nslices: stored (padded) blocks of each slice

@@ -687,6 +687,7 @@ pc_status build_schedule(Ctx *ctx) {
     if (nslices > ctx->slice_cap) {
         if ((st = realloc((void **)&ctx->lane_row, sizeof(int) * (size_t)nslices * WAVE))) return st;
         if ((st = realloc((void **)&ctx->slot_cnt, (size_t)nslices * WAVE))) return st;
+        if ((st = realloc((void **)&ctx->slot_off, sizeof(int) * (size_t)nslices * WAVE))) return st;
         if ((st = realloc((void **)&ctx->slice_row0, sizeof(int) * (size_t)(nslices + 1)))) return st;
         if ((st = realloc((void **)&ctx->slice_psize, sizeof(int) * (size_t)nslices))) return st;
         if ((st = realloc((void **)&ctx->slice_vbase, sizeof(int) * (size_t)(nslices + 1)))) return st;

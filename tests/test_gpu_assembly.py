@@ -172,12 +172,13 @@ def fan(n, centre_last):
 
 
 def test_capacity_overflow_reported(torch, B):
-    # closed fan of 40 triangles: the centre has 40 triangle and 40 hinge
-    # corners (> 64 incidences); with the centre numbered last every edge
-    # bucket is small, so creation succeeds and the solve reports
-    # PC_ERR_CAPACITY (without a fault)
-    rest, tris = fan(40, centre_last=True)
-    ctx = B.Context(rest, tris, np.ones(41), np.zeros(41, np.uint8), B.make_params(0.01))
+    # closed fan of 70 triangles: the centre has 71 block columns, more than
+    # the solver layout's 64; with the centre numbered last every edge bucket
+    # is small, so creation succeeds and the solve reports PC_ERR_CAPACITY
+    # (without a fault).  Rows with many incident corners but at most 64
+    # columns are assembled (tests/test_gpu_wide_rows.py).
+    rest, tris = fan(70, centre_last=True)
+    ctx = B.Context(rest, tris, np.ones(71), np.zeros(71, np.uint8), B.make_params(0.01))
     try:
         x = to_dev(torch, rest)
         b = ctx.cloth_assemble(x, torch.zeros_like(x), "f32")
