@@ -362,23 +362,47 @@ __global__ void k_check_contacts(int nc, int nv, const int *cv, const double *w,
 // ---------------------------------------------------------------- element records
 // Every element is evaluated once per assembly, one thread per element, into
 // SoA planes of FP64 (plane q of element e at rec[q * n + e]):
-//   triangle  0..5  F at x (3x2, row-major), 6..8 S+ at x (xx, xy, yy; the
-//                   stress's PSD part, for the stiffness), 9..11 S at the
-//                   force state, and with the lookahead force (rhs_mode 0)
-//                   12..17 F at the force state x + h v;
+//   triangle  the three off-diagonal stiffness blocks K_01, K_02, K_12 at x
+//             (planes 9 p .. 9 p + 8 for pair p = (0,1), (0,2), (1,2), 3x3
+//             row-major; K_lk = K_kl^T), then the forces on corners 0, 1, 2
+//             at the force state (planes 27 + 3 k .. 29 + 3 k);
 //   hinge     0..11 G = sqrt(2 k_b c_h) grad theta at x (corner-major xyz),
-//                   12 phi = -sqrt(2 k_b c_h) (theta - theta_bar) at the force
-//                   state, and with the lookahead force 13..24 G at the force
-//                   state; the force on corner k is phi G_k (of the force
-//                   state), the stiffness block (k, l) is G_k G_l^T;
+//             12 phi = -sqrt(2 k_b c_h) (theta - theta_bar) at the force
+//             state, and with the lookahead force 13..24 G at the force
+//             state; the force on corner k is phi G_k (of the force state),
+//             the stiffness block (k, l) is G_k G_l^T;
 //   contact   0 k_c while the gap at x is below the thickness (else 0),
 //             1 k_c (eta - g) at the force state while below it (else 0).
-constexpr int TREC = 12, TREC_LOOK = 18;
+// The force state is x + h v with the lookahead force (rhs_mode 0), else x.
+constexpr int TREC = 36;
 constexpr int HREC = 13, HREC_LOOK = 25;
 constexpr int CREC = 2;
 
-__global__ void __launch_bounds__(256) k_tri_eval(int nt, const int *tri, const double *Bm, const double *x,
-                                                  const double *v, DevParams P, double *rec) {
+// Membrane stiffness block K_kl (Sec. 2.5, solver Jacobian of Eq. 3):
+//   A0 [mu (b_k.b_l) F F^T + mu u_l u_k^T + lam u_k u_l^T + (b_k^T S+ b_l) I],  u_k = F b_k.
+__device__ __forceinline__ void tri_block(const double F[3][2], const double Sp[3], const double bk[2],
+                                          const double bl[2], double a0, double mu, double lam, double K[9]) {
+    double uk[3], ul[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        uk[a] = F[a][0] * bk[0] + F[a][1] * bk[1];
+        ul[a] = F[a][0] * bl[0] + F[a][1] * bl[1];
+    }
+    const double bb = bk[0] * bl[0] + bk[1] * bl[1];
+    const double bSb = bk[0] * (Sp[0] * bl[0] + Sp[1] * bl[1]) + bk[1] * (Sp[1] * bl[0] + Sp[2] * bl[1]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double fft = F[a][0] * F[b][0] + F[a][1] * F[b][1];
+            double val = mu * bb * fft + mu * ul[a] * uk[b] + lam * uk[a] * ul[b];
+            if (a == b) val += bSb;
+            K[3 * a + b] = a0 * val;
+        }
+}
+
+__global__ void __launch_bounds__(256) k_tri_eval(int nt, const int *tri, const double *Bm, const double *A0,
+                                                  const double *x, const double *v, DevParams P, double *rec) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nt) return;
     TriShape sh;
@@ -386,6 +410,7 @@ __global__ void __launch_bounds__(256) k_tri_eval(int nt, const int *tri, const 
     sh.b[1][0] = B0; sh.b[1][1] = B1;
     sh.b[2][0] = B2; sh.b[2][1] = B3;
     sh.b[0][0] = -B0 - B2; sh.b[0][1] = -B1 - B3;
+    const double a0 = A0[e];
     d3 xs[3];
     int vid[3];
 #pragma unroll
@@ -398,30 +423,28 @@ __global__ void __launch_bounds__(256) k_tri_eval(int nt, const int *tri, const 
     tri_stress(F, P.mu, P.lam, S);
     psd_part(S, Sp);
     const int64_t n = nt;
+    const int pk[3] = {0, 0, 1}, pl[3] = {1, 2, 2};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        rec[(2 * a) * n + e] = F[a][0];
-        rec[(2 * a + 1) * n + e] = F[a][1];
+    for (int p = 0; p < 3; ++p) {
+        double K[9];
+        tri_block(F, Sp, sh.b[pk[p]], sh.b[pl[p]], a0, P.mu, P.lam, K);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) rec[(9 * p + q) * n + e] = K[q];
     }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) rec[(6 + q) * n + e] = Sp[q];
+    // forces f_k = -A0 F S beta_k at the force state
     if (P.s_look != 0.0) {
         d3 ys[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) ys[q] = xs[q] + (P.s_look * P.h) * ld3(v, vid[q]);
-        double Fy[3][2], Sy[3];
-        tri_F(ys, sh, Fy);
-        tri_stress(Fy, P.mu, P.lam, Sy);
+        tri_F(ys, sh, F);
+        tri_stress(F, P.mu, P.lam, S);
+    }
 #pragma unroll
-        for (int q = 0; q < 3; ++q) rec[(9 + q) * n + e] = Sy[q];
+    for (int k = 0; k < 3; ++k) {
+        const double sb0 = S[0] * sh.b[k][0] + S[1] * sh.b[k][1];
+        const double sb1 = S[1] * sh.b[k][0] + S[2] * sh.b[k][1];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            rec[(12 + 2 * a) * n + e] = Fy[a][0];
-            rec[(13 + 2 * a) * n + e] = Fy[a][1];
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) rec[(9 + q) * n + e] = S[q];
+        for (int a = 0; a < 3; ++a) rec[(27 + 3 * k + a) * n + e] = -a0 * (F[a][0] * sb0 + F[a][1] * sb1);
     }
 }
 
@@ -785,36 +808,24 @@ __device__ __forceinline__ void store_block_inverse(float *out, double a, double
 __device__ __forceinline__ void add_stiffness(const AsmArgs &A, unsigned code, int l, double acc[9]) {
     const int e = inc_elem(code), k = inc_corner(code);
     const unsigned type = inc_type(code);
-    const DevParams &P = A.prm;
     if (type == INC_TRI) {
+        // the record holds K_kl for k < l; K_lk = K_kl^T
+        const int lo = k < l ? k : l, hi = k < l ? l : k;
+        const int p = lo + hi - 1;   // (0,1) -> 0, (0,2) -> 1, (1,2) -> 2
         const int64_t n = A.nt;
-        const double B0 = A.Bm[e], B1 = A.Bm[n + e], B2 = A.Bm[2 * n + e], B3 = A.Bm[3 * n + e];
-        double bk0, bk1, bl0, bl1;
-        if (k == 0) { bk0 = -B0 - B2; bk1 = -B1 - B3; }
-        else if (k == 1) { bk0 = B0; bk1 = B1; }
-        else { bk0 = B2; bk1 = B3; }
-        if (l == 0) { bl0 = -B0 - B2; bl1 = -B1 - B3; }
-        else if (l == 1) { bl0 = B0; bl1 = B1; }
-        else { bl0 = B2; bl1 = B3; }
-        const double a0 = A.A0[e];
-        const double *R = A.trec;
-        const double F00 = R[e], F01 = R[n + e], F10 = R[2 * n + e], F11 = R[3 * n + e], F20 = R[4 * n + e],
-                     F21 = R[5 * n + e];
-        const double S0 = R[6 * n + e], S1 = R[7 * n + e], S2 = R[8 * n + e];
-        const double uk[3] = {F00 * bk0 + F01 * bk1, F10 * bk0 + F11 * bk1, F20 * bk0 + F21 * bk1};
-        const double ul[3] = {F00 * bl0 + F01 * bl1, F10 * bl0 + F11 * bl1, F20 * bl0 + F21 * bl1};
-        const double Fr[3][2] = {{F00, F01}, {F10, F11}, {F20, F21}};
-        const double bb = bk0 * bl0 + bk1 * bl1;
-        const double bSb = bk0 * (S0 * bl0 + S1 * bl1) + bk1 * (S1 * bl0 + S2 * bl1);
+        const double *R = A.trec + (int64_t)(9 * p) * n + e;
+        double K[9];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < 9; ++q) K[q] = R[q * n];
+        if (k < l) {
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const double fft = Fr[a][0] * Fr[b][0] + Fr[a][1] * Fr[b][1];
-                double val = P.mu * bb * fft + P.mu * ul[a] * uk[b] + P.lam * uk[a] * ul[b];
-                if (a == b) val += bSb;
-                acc[3 * a + b] += a0 * val;
-            }
+            for (int q = 0; q < 9; ++q) acc[q] += K[q];
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) acc[3 * a + b] += K[3 * b + a];
+        }
     } else if (type == INC_HINGE) {
         const int64_t n = A.nh;
         const double *R = A.hrec;
@@ -825,12 +836,13 @@ __device__ __forceinline__ void add_stiffness(const AsmArgs &A, unsigned code, i
 #pragma unroll
             for (int b = 0; b < 3; ++b) acc[3 * a + b] += gk[a] * gl[b];
     } else {
+        // written so that the (l, k) block is the exact transpose of (k, l)
         const double nr[3] = {A.cn[3 * e], A.cn[3 * e + 1], A.cn[3 * e + 2]};
-        const double sc = A.crec[e] * A.cw[4 * e + k] * A.cw[4 * e + l];
+        const double sc = A.crec[e] * (A.cw[4 * e + k] * A.cw[4 * e + l]);
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int b = 0; b < 3; ++b) acc[3 * a + b] += sc * nr[a] * nr[b];
+            for (int b = 0; b < 3; ++b) acc[3 * a + b] += sc * (nr[a] * nr[b]);
     }
 }
 
@@ -840,20 +852,9 @@ __device__ __forceinline__ void add_force(const AsmArgs &A, unsigned code, doubl
     const unsigned type = inc_type(code);
     const bool look = A.prm.s_look != 0.0;
     if (type == INC_TRI) {
-        // f_k = -A0 F S beta_k
         const int64_t n = A.nt;
-        const double B0 = A.Bm[e], B1 = A.Bm[n + e], B2 = A.Bm[2 * n + e], B3 = A.Bm[3 * n + e];
-        const double bk0 = k == 0 ? -B0 - B2 : (k == 1 ? B0 : B2);
-        const double bk1 = k == 0 ? -B1 - B3 : (k == 1 ? B1 : B3);
-        const double a0 = A.A0[e];
-        const double *R = A.trec;
-        const int fb = look ? 12 : 0;
-        const double S0 = R[9 * n + e], S1 = R[10 * n + e], S2 = R[11 * n + e];
-        const double sb0 = S0 * bk0 + S1 * bk1;
-        const double sb1 = S1 * bk0 + S2 * bk1;
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            f[a] += -a0 * (R[(fb + 2 * a) * n + e] * sb0 + R[(fb + 2 * a + 1) * n + e] * sb1);
+        for (int a = 0; a < 3; ++a) f[a] += A.trec[(27 + 3 * k + a) * n + e];
     } else if (type == INC_HINGE) {
         const int64_t n = A.nh;
         const double *R = A.hrec;
@@ -1103,7 +1104,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     const bool look = ctx->prm.s_look != 0.0;
     const int nc = ctx->nc;
     struct Need { double **p; size_t *have; size_t n; } recs[3] = {
-        {&ctx->trec, &ctx->trec_elems, (size_t)(look ? TREC_LOOK : TREC) * nt},
+        {&ctx->trec, &ctx->trec_elems, (size_t)TREC * nt},
         {&ctx->hrec, &ctx->hrec_elems, (size_t)(look ? HREC_LOOK : HREC) * nh},
         {&ctx->crec, &ctx->crec_elems, (size_t)CREC * nc}};
     for (auto &r : recs)
@@ -1121,8 +1122,8 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     const int slot_all = ctx->prof.begin(PK_ASM_ALL, s);
     // 1. elements, each evaluated once
     int slot = ctx->prof.begin(PK_ELEMENTS, s);
-    hipLaunchKernelGGL(k_tri_eval, dim3((nt + TB - 1) / TB), dim3(TB), 0, s, nt, ctx->tri, ctx->Bm, x, v, ctx->prm,
-                       ctx->trec);
+    hipLaunchKernelGGL(k_tri_eval, dim3((nt + TB - 1) / TB), dim3(TB), 0, s, nt, ctx->tri, ctx->Bm, ctx->A0, x, v,
+                       ctx->prm, ctx->trec);
     if (nh > 0)
         hipLaunchKernelGGL(k_hinge_eval, dim3((nh + TB - 1) / TB), dim3(TB), 0, s, nh, ctx->hinge, ctx->hcoef,
                            ctx->htbar, x, v, ctx->prm, ctx->hrec);
