@@ -206,6 +206,12 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
         ctx->err = "more than 2^28 triangles or hinges";
         return fail(PC_ERR_ARG);
     }
+    // element records are indexed with 32-bit plane offsets (36 planes per
+    // triangle, up to 25 per hinge)
+    if ((int64_t)36 * nt >= ((int64_t)1 << 31) || (int64_t)25 * nh >= ((int64_t)1 << 31)) {
+        ctx->err = "more than 59,652,323 triangles or 85,899,345 hinges";
+        return fail(PC_ERR_ARG);
+    }
     ctx->ninc = 3 * (int64_t)nt + 4 * (int64_t)nh;
     ctx->ninc_cap = ctx->ninc;
     // block capacity: diagonal + both directions of every triangle edge (6

@@ -812,8 +812,8 @@ __device__ __forceinline__ void add_stiffness(const AsmArgs &A, unsigned code, i
         // the record holds K_kl for k < l; K_lk = K_kl^T
         const int lo = k < l ? k : l, hi = k < l ? l : k;
         const int p = lo + hi - 1;   // (0,1) -> 0, (0,2) -> 1, (1,2) -> 2
-        const int64_t n = A.nt;
-        const double *R = A.trec + (int64_t)(9 * p) * n + e;
+        const int n = A.nt;          // 36 n < 2^31 (checked at pc_create)
+        const double *R = A.trec + 9 * p * n + e;
         double K[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) K[q] = R[q * n];
@@ -827,10 +827,10 @@ __device__ __forceinline__ void add_stiffness(const AsmArgs &A, unsigned code, i
                 for (int b = 0; b < 3; ++b) acc[3 * a + b] += K[3 * b + a];
         }
     } else if (type == INC_HINGE) {
-        const int64_t n = A.nh;
-        const double *R = A.hrec;
-        const double gk[3] = {R[(3 * k) * n + e], R[(3 * k + 1) * n + e], R[(3 * k + 2) * n + e]};
-        const double gl[3] = {R[(3 * l) * n + e], R[(3 * l + 1) * n + e], R[(3 * l + 2) * n + e]};
+        const int n = A.nh;          // 25 n < 2^31 (checked at pc_create)
+        const double *Rk = A.hrec + 3 * k * n + e, *Rl = A.hrec + 3 * l * n + e;
+        const double gk[3] = {Rk[0], Rk[n], Rk[2 * n]};
+        const double gl[3] = {Rl[0], Rl[n], Rl[2 * n]};
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -852,16 +852,16 @@ __device__ __forceinline__ void add_force(const AsmArgs &A, unsigned code, doubl
     const unsigned type = inc_type(code);
     const bool look = A.prm.s_look != 0.0;
     if (type == INC_TRI) {
-        const int64_t n = A.nt;
+        const int n = A.nt;
+        const double *R = A.trec + (27 + 3 * k) * n + e;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) f[a] += A.trec[(27 + 3 * k + a) * n + e];
+        for (int a = 0; a < 3; ++a) f[a] += R[a * n];
     } else if (type == INC_HINGE) {
-        const int64_t n = A.nh;
-        const double *R = A.hrec;
-        const double phi = R[12 * n + e];
-        const int gb = look ? 13 + 3 * k : 3 * k;
+        const int n = A.nh;
+        const double phi = A.hrec[12 * n + e];
+        const double *R = A.hrec + (look ? 13 + 3 * k : 3 * k) * n + e;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) f[a] += phi * R[(gb + a) * n + e];
+        for (int a = 0; a < 3; ++a) f[a] += phi * R[a * n];
     } else {
         const double m = A.crec[(int64_t)A.nc + e] * A.cw[4 * e + k];
 #pragma unroll
@@ -906,11 +906,11 @@ __device__ __forceinline__ void row_values_g(RowGroupLDS<NI> &L, const AsmArgs &
     __syncthreads();
     const int len = row_columns_g<G, NI>(L, A, i, n, act, t);
     const DevParams &P = A.prm;
-    double red[18];
+    double red[9];   // K v (3), diagonal of sum_j K_ij (3), its symmetrised off-diagonal entries (3)
 #pragma unroll
-    for (int q = 0; q < 18; ++q) red[q] = 0.0;
+    for (int q = 0; q < 9; ++q) red[q] = 0.0;
     double f[3] = {0.0, 0.0, 0.0};
-    int dslot = -1;
+    int dslot = -1, npin = 0;
     bool rowpin = false;
     if (act) {
         rowpin = A.pinned[i] != 0;
@@ -930,6 +930,7 @@ __device__ __forceinline__ void row_values_g(RowGroupLDS<NI> &L, const AsmArgs &
                 if (l >= 0) add_stiffness(A, L.code[m], l, acc);
             }
             const bool colpin = A.pinned[col] != 0;
+            npin += colpin ? 1 : 0;
             const d3 dvv = ld3(A.v, col) - vi;
             red[0] += acc[0] * dvv.x + acc[1] * dvv.y + acc[2] * dvv.z;
             red[1] += acc[3] * dvv.x + acc[4] * dvv.y + acc[5] * dvv.z;
@@ -937,14 +938,11 @@ __device__ __forceinline__ void row_values_g(RowGroupLDS<NI> &L, const AsmArgs &
             red[3] += acc[0];
             red[4] += acc[4];
             red[5] += acc[8];
-            if (colpin)
-#pragma unroll
-                for (int q = 0; q < 9; ++q) red[6 + q] += acc[q];
             // off-diagonal entries of sum_j K_ij (symmetrised): the diagonal block is
             // A_ii = m_i I - c sum_{j != i} K_ij since every element's block rows sum to zero
-            red[15] += 0.5 * (acc[1] + acc[3]);
-            red[16] += 0.5 * (acc[2] + acc[6]);
-            red[17] += 0.5 * (acc[5] + acc[7]);
+            red[6] += 0.5 * (acc[1] + acc[3]);
+            red[7] += 0.5 * (acc[2] + acc[6]);
+            red[8] += 0.5 * (acc[5] + acc[7]);
             double blk[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) blk[q] = (rowpin || colpin) ? 0.0 : P.c * acc[q];
@@ -953,15 +951,31 @@ __device__ __forceinline__ void row_values_g(RowGroupLDS<NI> &L, const AsmArgs &
         for (int m = t; m < n; m += G) add_force(A, L.code[m], f);
     }
 #pragma unroll
-    for (int q = 0; q < 18; ++q) red[q] = group_sum<G>(red[q]);
+    for (int q = 0; q < 9; ++q) red[q] = group_sum<G>(red[q]);
+    npin = group_sum_int<G>(npin);
 #pragma unroll
     for (int a = 0; a < 3; ++a) f[a] = group_sum<G>(f[a]);
     if (dslot < 0) return;
-    // D_i = -c sum_{j pinned} K_ij for a free row, 0 for a pinned row
+    // D_i = -c sum_{j pinned} K_ij for a free row, 0 for a pinned row: the
+    // blocks of pinned columns, summed in incidence order (rows next to a pin only)
     const double mi = A.mass[i];
+    double pin[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) pin[q] = 0.0;
+    if (!rowpin && npin > 0)
+        for (int m = 0; m < n; ++m) {
+            const unsigned code = L.code[m];
+            const int4 ev = L.ev[m];
+            const int k = inc_corner(code);
+            const int nq = inc_type(code) == INC_TRI ? 3 : 4;
+            for (int l = 0; l < nq; ++l) {
+                const int vl = l == 0 ? ev.x : (l == 1 ? ev.y : (l == 2 ? ev.z : ev.w));
+                if (l != k && A.pinned[vl]) add_stiffness(A, code, l, pin);
+            }
+        }
     double blk[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) blk[q] = rowpin ? 0.0 : -P.c * red[6 + q];
+    for (int q = 0; q < 9; ++q) blk[q] = rowpin ? 0.0 : -P.c * pin[q];
     // force: gravity plus the element forces
     const double f0 = mi * P.g[0] + f[0], f1 = mi * P.g[1] + f[1], f2 = mi * P.g[2] + f[2];
     double bi0 = P.h * (f0 - P.kv_coef * red[0]);
@@ -978,9 +992,9 @@ __device__ __forceinline__ void row_values_g(RowGroupLDS<NI> &L, const AsmArgs &
     A.dinv[3 * i] = (float)(1.0 / d0);
     A.dinv[3 * i + 1] = (float)(1.0 / d1);
     A.dinv[3 * i + 2] = (float)(1.0 / d2);
-    const double o01 = rowpin ? 0.0 : -P.c * red[15];
-    const double o02 = rowpin ? 0.0 : -P.c * red[16];
-    const double o12 = rowpin ? 0.0 : -P.c * red[17];
+    const double o01 = rowpin ? 0.0 : -P.c * red[6];
+    const double o02 = rowpin ? 0.0 : -P.c * red[7];
+    const double o12 = rowpin ? 0.0 : -P.c * red[8];
     store_block_inverse(A.binv + 6 * (int64_t)i, d0, o01, o02, d1, o12, d2);
     store_row_block<TB>(A, i, dslot, i, blk);
 }

@@ -1,7 +1,8 @@
 """Fixed-work kernel driver for hardware-counter runs.
 
 Runs a bounded amount of the solver's work on one workload through the C ABI
-(one assembly, then a CG solve capped at ``--iters`` iterations) plus a
+(``--assemblies`` assemblies of the initial state, then a CG solve capped
+at ``--iters`` iterations) plus a
 plain device copy of known size, so that a counter profiler can take the
 bytes each kernel fetches and writes per dispatch and scale them against the
 copy, whose traffic is exactly 2 x its size.
@@ -28,6 +29,7 @@ def main(argv=None):
     ap.add_argument("--narrow", type=int, default=1, help="1: 16-bit column offsets when they fit")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy")
     ap.add_argument("--copies", type=int, default=5)
+    ap.add_argument("--assemblies", type=int, default=1, help="assemblies of the initial state before the solve")
     a = ap.parse_args(argv)
 
     import torch
@@ -50,7 +52,8 @@ def main(argv=None):
     v = torch.from_numpy(c.v0.copy()).cuda()
     print(f"# kernel_bench {c.name}: nv={c.nv} nt={c.nt} blocks={a.blocks} precond={a.precond} iters={a.iters}",
           flush=True)
-    b = ctx.cloth_assemble(x, v, a.blocks)
+    for _ in range(max(1, a.assemblies)):
+        b = ctx.cloth_assemble(x, v, a.blocks)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dv, info = ctx.cloth_pcg_solve(b, tol=1e-30, maxit=a.iters, raise_on_error=False, max_sweeps=1,

@@ -10,6 +10,10 @@ Markdown tables.
         full dispatches), scaled by what the same counters read for a plain
         copy kernel that moves N bytes each way; prints the scale factors and
         the HBM bytes per launch
+
+    python -m paper_2008_00409_amd.profile_summary counters <results.db> [...] --kernel NAME [--kernel NAME ...]
+        every counter the databases hold, median over each kernel's
+        dispatches (several databases: one counter pass each)
 """
 from __future__ import annotations
 
@@ -111,6 +115,26 @@ def pmc_table(fetch_db, write_db, kernel, copy_kernel, copy_bytes):
     return "\n".join(lines)
 
 
+def counter_names(db):
+    con = sqlite3.connect(db)
+    return [r[0] for r in con.execute("select distinct counter_name from counters_collection").fetchall()]
+
+
+def counters_table(dbs, kernels):
+    """One row per kernel, one column per counter: the median per dispatch."""
+    cols, vals = [], {}
+    for db in dbs:
+        for cn in counter_names(db):
+            cols.append(cn)
+            for k in kernels:
+                v = counter_values(db, k, cn)
+                vals[(k, cn)] = statistics.median(v) if v else float("nan")
+    out = ["| kernel | " + " | ".join(cols) + " |", "|---|" + "---|" * len(cols)]
+    for k in kernels:
+        out.append(f"| `{k}` | " + " | ".join(f"{vals[(k, c)]:.6g}" for c in cols) + " |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -124,9 +148,14 @@ def main(argv=None):
     p.add_argument("--kernel", required=True)
     p.add_argument("--copy-kernel", required=True)
     p.add_argument("--copy-bytes", type=float, required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("dbs", nargs="+")
+    c.add_argument("--kernel", action="append", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(trace_table(a.db, a.top, a.by_grid))
+    elif a.cmd == "counters":
+        print(counters_table(a.dbs, a.kernel))
     else:
         print(pmc_table(a.fetch_db, a.write_db, a.kernel, a.copy_kernel, a.copy_bytes))
 
