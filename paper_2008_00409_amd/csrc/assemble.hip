@@ -522,10 +522,18 @@ struct AsmArgs {
     DevParams prm;
     int *rowlen, *rowptr, *colidx, *jcol;
     int16_t *jdel;
-    const int *row_lane, *row_slice, *slice_row0, *slice_vbase, *slot_off;
+    const int *row_lane, *lane_row, *row_slice, *slice_row0, *slice_vbase, *slot_off;
     const uint8_t *slot_cnt;
     uint8_t *row_state;          // ROW_GROUP, ROW_WIDE, ROW_OVERFLOW or ROW_WIDE_OVERFLOW
     int *wide_rows, *wide_count; // rows of the wide-row pass (list and its length)
+    int nslices;
+    // per row of the row group pass, from the pattern pass to the value pass:
+    // its columns at cols_tmp[3 p0 + i ..] (p0 = inc_ptr[i]; at most 3 n + 1),
+    // its (incidence, corner) pairs sorted by column slot then incidence at
+    // pairs_tmp[3 p0 ..] (key slot << 7 | m << 2 | l), and their number
+    int *cols_tmp;
+    int *pairs_tmp;
+    int *row_npairs;
     void *jval;
     double *jval_hi;   // FP64 copy (nullptr when the solver copy is FP64)
     double *b, *diag;
@@ -633,11 +641,13 @@ __device__ __forceinline__ int row_columns_g(RowGroupLDS<NI> &L, const AsmArgs &
     for (int p = t; p < nc; p += G) {
         const int c = L.cand[p];
         bool f = true;
+#pragma unroll 4
         for (int q = 0; q < p; ++q) f = f && L.cand[q] != c;
         L.first[p] = f ? 1 : 0;
     }
     __syncthreads();
     int nd = 0, below = 0;
+#pragma unroll 4
     for (int p = 0; p < nc; ++p) {
         const int f = L.first[p];
         nd += f;
@@ -647,6 +657,7 @@ __device__ __forceinline__ int row_columns_g(RowGroupLDS<NI> &L, const AsmArgs &
         if (!L.first[p]) continue;
         const int c = L.cand[p];
         int r = 0;
+#pragma unroll 4
         for (int q = 0; q < nc; ++q) r += L.first[q] && L.cand[q] < c;
         L.cols[r + (c > i ? 1 : 0)] = c;
     }
@@ -673,6 +684,7 @@ __device__ __forceinline__ int row_pattern_g(RowGroupLDS<NI> &L, const AsmArgs &
         for (int m = t; m < n; m += G) {
             const unsigned key = (unsigned)L.cols[m];
             int r = 0;
+#pragma unroll 4
             for (int q = 0; q < n; ++q) r += (unsigned)L.cols[q] < key;
             L.code[r] = key;
         }
@@ -699,6 +711,55 @@ __device__ __forceinline__ void row_record(const AsmArgs &A, int i, int len, boo
     }
 }
 
+// For the value pass of a row group row: its columns, and every (incidence
+// m, corner l != k) pair grouped by the column slot of corner l's vertex,
+// slots ascending and each slot's pairs in incidence order.  Lane t takes
+// the slots s = t, t + 16, ...: it counts the pairs of each slot by scanning
+// the row's incidences, the counts give each slot's first position, and a
+// second scan writes the pairs.  Called by every lane.
+__device__ __forceinline__ int slot_pairs(const RowGroupLDS<RG_NI> &L, int n, int c, int q0, int *out, int s) {
+    int cnt = 0;
+#pragma unroll 4
+    for (int m = 0; m < n; ++m) {
+        const int4 ev = L.ev[m];
+        const int k = inc_corner(L.code[m]);
+        const int l = ev.x == c ? 0 : (ev.y == c ? 1 : (ev.z == c ? 2 : (ev.w == c ? 3 : -1)));
+        if (l >= 0 && l != k) {
+            if (out) out[q0 + cnt] = (s << 7) | (m << 2) | l;
+            ++cnt;
+        }
+    }
+    return cnt;
+}
+
+__device__ __forceinline__ void row_pairs_g(RowGroupLDS<RG_NI> &L, const AsmArgs &A, int i, int len, bool act,
+                                            int t) {
+    int p0 = 0, n = 0;
+    if (act) {
+        p0 = A.inc_ptr[i];
+        n = A.inc_ptr[i + 1] - p0;
+        for (int s = t; s < len; s += RG) {
+            const int c = L.cols[s];
+            A.cols_tmp[3 * p0 + i + s] = c;
+            L.cand[s] = c == i ? 0 : slot_pairs(L, n, c, 0, nullptr, s);   // pairs per slot
+        }
+    }
+    __syncthreads();
+    if (act) {
+        for (int s = t; s < len; s += RG) {
+            int q0 = 0;
+            for (int r = 0; r < s; ++r) q0 += L.cand[r];
+            const int c = L.cols[s];
+            if (c != i) slot_pairs(L, n, c, q0, A.pairs_tmp + 3 * (int64_t)p0, s);
+        }
+        if (t == 0) {
+            int np = 0;
+            for (int r = 0; r < len; ++r) np += L.cand[r];
+            A.row_npairs[i] = np;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(64) k_row_pattern(AsmArgs A) {
     __shared__ RowGroupLDS<RG_NI> Ls[RG_ROWS];
     const int g = threadIdx.x / RG, t = threadIdx.x % RG;
@@ -706,6 +767,7 @@ __global__ void __launch_bounds__(64) k_row_pattern(AsmArgs A) {
     const bool act = i < A.nv;
     const int len = row_pattern_g<RG, RG_NI>(Ls[g], A, i, act, t);
     if (act && t == 0) row_record(A, i, len, false);
+    row_pairs_g(Ls[g], A, i, len, act && len > 0 && len <= MAX_COLS, t);
 }
 
 // Wide rows: one workgroup per row, a grid-stride loop over the list the
@@ -886,6 +948,43 @@ __device__ __forceinline__ void store_row_block(const AsmArgs &A, int i, int s, 
     if (A.jval_hi) BlockIO<double>::store(A.jval_hi + 9 * seg, w, lane, blk);
 }
 
+// The row's own outputs: the diagonal slot's block D_i = -c sum_{j pinned}
+// K_ij (0 for a pinned row), b_i = h (f_i + m_i g - kv K v), diag(A)_i,
+// 1 / diag(A)_i and the inverse of the diagonal block A_ii = m_i I - c sum_j
+// K_ij (every element's block rows sum to zero).  red: K v, the diagonal of
+// sum_{j != i} K_ij, its symmetrised off-diagonal entries; pin: sum_{j
+// pinned} K_ij; f: the element forces.
+template <typename TB>
+__device__ __forceinline__ void write_row_diagonal(const AsmArgs &A, int i, int dslot, bool rowpin,
+                                                   const double red[9], const double pin[9], const double f[3]) {
+    const DevParams &P = A.prm;
+    const double mi = A.mass[i];
+    double blk[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) blk[q] = rowpin ? 0.0 : -P.c * pin[q];
+    // force: gravity plus the element forces
+    const double f0 = mi * P.g[0] + f[0], f1 = mi * P.g[1] + f[1], f2 = mi * P.g[2] + f[2];
+    double bi0 = P.h * (f0 - P.kv_coef * red[0]);
+    double bi1 = P.h * (f1 - P.kv_coef * red[1]);
+    double bi2 = P.h * (f2 - P.kv_coef * red[2]);
+    double d0 = mi - P.c * red[3], d1 = mi - P.c * red[4], d2 = mi - P.c * red[5];
+    if (rowpin) {
+        bi0 = bi1 = bi2 = 0.0;
+        d0 = d1 = d2 = mi;
+    }
+    if (!isfinite(bi0) || !isfinite(bi1) || !isfinite(bi2)) atomicOr(A.status, ST_NONFINITE);
+    A.b[3 * i] = bi0; A.b[3 * i + 1] = bi1; A.b[3 * i + 2] = bi2;
+    A.diag[3 * i] = d0; A.diag[3 * i + 1] = d1; A.diag[3 * i + 2] = d2;
+    A.dinv[3 * i] = (float)(1.0 / d0);
+    A.dinv[3 * i + 1] = (float)(1.0 / d1);
+    A.dinv[3 * i + 2] = (float)(1.0 / d2);
+    const double o01 = rowpin ? 0.0 : -P.c * red[6];
+    const double o02 = rowpin ? 0.0 : -P.c * red[7];
+    const double o12 = rowpin ? 0.0 : -P.c * red[8];
+    store_block_inverse(A.binv + 6 * (int64_t)i, d0, o01, o02, d1, o12, d2);
+    store_row_block<TB>(A, i, dslot, i, blk);
+}
+
 // Values of one row.  Lane t of the group owns the column slots s = t, t + G,
 // ...; for each it sums, in the row's incidence order, the stiffness blocks
 // of every incident element containing the column's vertex (a deterministic
@@ -958,7 +1057,6 @@ __device__ __forceinline__ void row_values_g(RowGroupLDS<NI> &L, const AsmArgs &
     if (dslot < 0) return;
     // D_i = -c sum_{j pinned} K_ij for a free row, 0 for a pinned row: the
     // blocks of pinned columns, summed in incidence order (rows next to a pin only)
-    const double mi = A.mass[i];
     double pin[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) pin[q] = 0.0;
@@ -973,40 +1071,110 @@ __device__ __forceinline__ void row_values_g(RowGroupLDS<NI> &L, const AsmArgs &
                 if (l != k && A.pinned[vl]) add_stiffness(A, code, l, pin);
             }
         }
-    double blk[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) blk[q] = rowpin ? 0.0 : -P.c * pin[q];
-    // force: gravity plus the element forces
-    const double f0 = mi * P.g[0] + f[0], f1 = mi * P.g[1] + f[1], f2 = mi * P.g[2] + f[2];
-    double bi0 = P.h * (f0 - P.kv_coef * red[0]);
-    double bi1 = P.h * (f1 - P.kv_coef * red[1]);
-    double bi2 = P.h * (f2 - P.kv_coef * red[2]);
-    double d0 = mi - P.c * red[3], d1 = mi - P.c * red[4], d2 = mi - P.c * red[5];
-    if (rowpin) {
-        bi0 = bi1 = bi2 = 0.0;
-        d0 = d1 = d2 = mi;
-    }
-    if (!isfinite(bi0) || !isfinite(bi1) || !isfinite(bi2)) atomicOr(A.status, ST_NONFINITE);
-    A.b[3 * i] = bi0; A.b[3 * i + 1] = bi1; A.b[3 * i + 2] = bi2;
-    A.diag[3 * i] = d0; A.diag[3 * i + 1] = d1; A.diag[3 * i + 2] = d2;
-    A.dinv[3 * i] = (float)(1.0 / d0);
-    A.dinv[3 * i + 1] = (float)(1.0 / d1);
-    A.dinv[3 * i + 2] = (float)(1.0 / d2);
-    const double o01 = rowpin ? 0.0 : -P.c * red[6];
-    const double o02 = rowpin ? 0.0 : -P.c * red[7];
-    const double o12 = rowpin ? 0.0 : -P.c * red[8];
-    store_block_inverse(A.binv + 6 * (int64_t)i, d0, o01, o02, d1, o12, d2);
-    store_row_block<TB>(A, i, dslot, i, blk);
+    write_row_diagonal<TB>(A, i, dslot, rowpin, red, pin, f);
 }
+
+// Value pass of the row group rows, four rows per 64-lane workgroup, 16
+// lanes per row (the pattern pass has left each row's columns and its
+// (incidence, corner) pairs sorted by column slot).  Lane t of a row owns
+// the column slots s = t, t + 16, ...; for each it sums, in incidence order,
+// the stiffness blocks of the pairs of that slot (a contiguous range of the
+// sorted pairs) from the element records: a deterministic segmented reduce
+// with no floating-point atomics.  Row totals and the forces are summed per
+// lane, then over the 16 lanes in a fixed butterfly order; the lane holding
+// the diagonal slot writes the row's own outputs.
+struct RowPairsLDS {
+    unsigned code[RG_NI];
+    int pair[3 * RG_NI];
+    int cols[MAX_COLS];
+};
 
 template <typename TB>
 __global__ void __launch_bounds__(64) k_row_values(AsmArgs A) {
-    __shared__ RowGroupLDS<RG_NI> Ls[RG_ROWS];
+    __shared__ RowPairsLDS Ls[RG_ROWS];
     const int g = threadIdx.x / RG, t = threadIdx.x % RG;
     const int i = xcd_remap(blockIdx.x, gridDim.x) * RG_ROWS + g;
     const int st = i < A.nv ? (int)A.row_state[i] : -1;
     if (st == ROW_OVERFLOW && t == 0) write_overflow_row<TB>(A, i);
-    row_values_g<TB, RG, RG_NI>(Ls[g], A, i, st == ROW_GROUP, t);
+    const bool act = st == ROW_GROUP;
+    RowPairsLDS &L = Ls[g];
+    int p0 = 0, n = 0, np = 0, len = 0;
+    if (act) {
+        p0 = A.inc_ptr[i];
+        n = A.inc_ptr[i + 1] - p0;
+        np = A.row_npairs[i];
+        len = A.rowlen[i];
+        for (int m = t; m < n; m += RG) L.code[m] = (unsigned)A.inc[p0 + m];
+        for (int q = t; q < np; q += RG) L.pair[q] = A.pairs_tmp[3 * p0 + q];
+        for (int q = t; q < len; q += RG) L.cols[q] = A.cols_tmp[3 * p0 + i + q];
+    }
+    __syncthreads();
+    const DevParams &P = A.prm;
+    double red[9];   // K v (3), diagonal of sum_j K_ij (3), its symmetrised off-diagonal entries (3)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) red[q] = 0.0;
+    double f[3] = {0.0, 0.0, 0.0};
+    int dslot = -1, npin = 0;
+    bool rowpin = false;
+    if (act) {
+        rowpin = A.pinned[i] != 0;
+        const d3 vi = ld3(A.v, i);
+        for (int s = t; s < len; s += RG) {
+            const int col = L.cols[s];
+            if (col == i) {
+                dslot = s;
+                continue;
+            }
+            // first pair of slot s (pairs are sorted by slot)
+            int lo = 0, hi = np;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((L.pair[mid] >> 7) < s) lo = mid + 1; else hi = mid;
+            }
+            double acc[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+            for (int q = lo; q < np; ++q) {
+                const int key = L.pair[q];
+                if ((key >> 7) != s) break;
+                add_stiffness(A, L.code[(key >> 2) & 31], key & 3, acc);
+            }
+            const bool colpin = A.pinned[col] != 0;
+            npin += colpin ? 1 : 0;
+            const d3 dvv = ld3(A.v, col) - vi;
+            red[0] += acc[0] * dvv.x + acc[1] * dvv.y + acc[2] * dvv.z;
+            red[1] += acc[3] * dvv.x + acc[4] * dvv.y + acc[5] * dvv.z;
+            red[2] += acc[6] * dvv.x + acc[7] * dvv.y + acc[8] * dvv.z;
+            red[3] += acc[0];
+            red[4] += acc[4];
+            red[5] += acc[8];
+            red[6] += 0.5 * (acc[1] + acc[3]);
+            red[7] += 0.5 * (acc[2] + acc[6]);
+            red[8] += 0.5 * (acc[5] + acc[7]);
+            double blk[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) blk[q] = (rowpin || colpin) ? 0.0 : P.c * acc[q];
+            store_row_block<TB>(A, i, s, col, blk);
+        }
+        for (int m = t; m < n; m += RG) add_force(A, L.code[m], f);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) red[q] = group_sum<RG>(red[q]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f[a] = group_sum<RG>(f[a]);
+    npin = group_sum_int<RG>(npin);
+    if (dslot < 0) return;
+    // pinned-column sums for D_i, pair by pair in (slot, incidence) order
+    // (rows next to a pin only)
+    double pin[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) pin[q] = 0.0;
+    if (!rowpin && npin > 0)
+        for (int q = 0; q < np; ++q) {
+            const int key = L.pair[q];
+            if (A.pinned[L.cols[key >> 7]]) add_stiffness(A, L.code[(key >> 2) & 31], key & 3, pin);
+        }
+    write_row_diagonal<TB>(A, i, dslot, rowpin, red, pin, f);
 }
 
 template <typename TB>
@@ -1132,6 +1300,18 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     if (!ctx->row_state) {
         if ((st = dev_alloc(ctx, (void **)&ctx->row_state, (size_t)nv))) return st;
         if ((st = dev_alloc(ctx, (void **)&ctx->wide_rows, sizeof(int) * (size_t)nv))) return st;
+        if ((st = dev_alloc(ctx, (void **)&ctx->row_npairs, sizeof(int) * (size_t)nv))) return st;
+    }
+    // per-row columns and pair lists between the two passes: 3 per incidence (+1 column per row)
+    if (ctx->pair_incs < ctx->ninc) {
+        dev_free(ctx, ctx->cols_tmp);
+        dev_free(ctx, ctx->pairs_tmp);
+        ctx->cols_tmp = nullptr;
+        ctx->pairs_tmp = nullptr;
+        ctx->pair_incs = 0;
+        if ((st = dev_alloc(ctx, (void **)&ctx->cols_tmp, sizeof(int) * (3 * (size_t)ctx->ninc + nv)))) return st;
+        if ((st = dev_alloc(ctx, (void **)&ctx->pairs_tmp, sizeof(int) * 3 * (size_t)ctx->ninc))) return st;
+        ctx->pair_incs = ctx->ninc;
     }
     const int slot_all = ctx->prof.begin(PK_ASM_ALL, s);
     // 1. elements, each evaluated once
@@ -1163,9 +1343,11 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     a.trec = ctx->trec; a.hrec = ctx->hrec; a.crec = ctx->crec;
     a.pinned = ctx->pinned; a.v = v; a.prm = ctx->prm;
     a.rowlen = ctx->rowlen; a.rowptr = ctx->rowptr; a.colidx = ctx->colidx; a.jcol = ctx->jcol; a.jdel = ctx->jdel;
-    a.row_lane = ctx->row_lane; a.slot_cnt = ctx->slot_cnt; a.slot_off = ctx->slot_off; a.jval = ctx->jval;
+    a.row_lane = ctx->row_lane; a.lane_row = ctx->lane_row; a.slot_cnt = ctx->slot_cnt; a.slot_off = ctx->slot_off; a.jval = ctx->jval;
     a.row_slice = ctx->row_slice; a.slice_row0 = ctx->slice_row0; a.slice_vbase = ctx->slice_vbase;
     a.row_state = ctx->row_state; a.wide_rows = ctx->wide_rows; a.wide_count = (int *)ctx->counter + 1;
+    a.nslices = ctx->nslices;
+    a.cols_tmp = ctx->cols_tmp; a.pairs_tmp = ctx->pairs_tmp; a.row_npairs = ctx->row_npairs;
     a.jval_hi = dtype != PC_F64 ? ctx->jval_hi : nullptr;
     a.b = b; a.diag = diag_out ? diag_out : ctx->diag; a.dinv = ctx->dinv; a.binv = ctx->binv; a.status = ctx->status;
     // four rows per workgroup; a multiple of 8 workgroups for the XCD mapping

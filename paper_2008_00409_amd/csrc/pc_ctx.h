@@ -190,6 +190,10 @@ struct Ctx {
     int *slot_off = nullptr;      // nslices * 64: first stored block of each slot, from the slice's first
     uint8_t *row_state = nullptr; // nv: which assembly pass handles each row
     int *wide_rows = nullptr;     // nv: rows of the wide-row passes
+    int *row_npairs = nullptr;    // nv: (incidence, corner) pairs of each row
+    int *cols_tmp = nullptr;      // 3 ninc + nv: each row's columns, pattern pass -> value pass
+    int *pairs_tmp = nullptr;     // 3 ninc: each row's pairs grouped by column slot
+    int64_t pair_incs = 0;        // incidences the two buffers above can hold
     // element records of the last assembly (FP64 SoA planes; sizes in doubles)
     double *trec = nullptr, *hrec = nullptr, *crec = nullptr;
     size_t trec_elems = 0, hrec_elems = 0, crec_elems = 0;
