@@ -11,6 +11,12 @@ Markdown tables.
         copy kernel that moves N bytes each way; prints the scale factors and
         the HBM bytes per launch
 
+    python -m paper_2008_00409_amd.profile_summary kernels <fetch.db> <write.db> <trace.db> [--sq <sq.db>]
+            --kernel NAME [--kernel NAME ...] --copy-kernel NAME --copy-bytes N
+        per kernel: mean duration, HBM bytes fetched and written per
+        dispatch (copy-scaled as above), their rate, and with --sq the
+        VALU instructions per wave
+
     python -m paper_2008_00409_amd.profile_summary counters <results.db> [...] --kernel NAME [--kernel NAME ...]
         every counter the databases hold, median over each kernel's
         dispatches (several databases: one counter pass each)
@@ -135,6 +141,33 @@ def counters_table(dbs, kernels):
     return "\n".join(out)
 
 
+def kernels_table(fetch_db, write_db, trace_db, kernels, copy_kernel, copy_bytes, sq_db=None):
+    kib = copy_bytes / 1024.0
+    sf = kib / full_median(counter_values(fetch_db, copy_kernel, "FETCH_SIZE"))
+    sw = kib / full_median(counter_values(write_db, copy_kernel, "WRITE_SIZE"))
+    rows = kernel_rows(trace_db)
+    out = [f"FETCH_SIZE scale {sf:.3f}, WRITE_SIZE scale {sw:.3f} (from `{copy_kernel}` moving {copy_bytes:.0f} B each way)",
+           "",
+           "| kernel | mean us | fetched MB | written MB | GB/s | VALU instructions per wave |",
+           "|---|---|---|---|---|---|"]
+    tb = tt = 0.0
+    for k in kernels:
+        f = statistics.median(counter_values(fetch_db, k, "FETCH_SIZE")) * sf * 1024.0
+        w = statistics.median(counter_values(write_db, k, "WRITE_SIZE")) * sw * 1024.0
+        t = statistics.mean([(e - s) / 1e3 for n, s, e, g in rows if k in n])
+        va = "-"
+        if sq_db:
+            v = counter_values(sq_db, k, "SQ_INSTS_VALU")
+            wv = counter_values(sq_db, k, "SQ_WAVES")
+            if v and wv:
+                va = f"{statistics.median(v) / statistics.median(wv):.0f}"
+        tb += f + w
+        tt += t
+        out.append(f"| `{k}` | {t:.1f} | {f / 1e6:.1f} | {w / 1e6:.1f} | {(f + w) / (t * 1e-6) / 1e9:.0f} | {va} |")
+    out.append(f"| all listed | {tt:.1f} | | {tb / 1e6:.1f} (total) | {tb / (tt * 1e-6) / 1e9:.0f} | |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -148,12 +181,22 @@ def main(argv=None):
     p.add_argument("--kernel", required=True)
     p.add_argument("--copy-kernel", required=True)
     p.add_argument("--copy-bytes", type=float, required=True)
+    kk = sub.add_parser("kernels")
+    kk.add_argument("fetch_db")
+    kk.add_argument("write_db")
+    kk.add_argument("trace_db")
+    kk.add_argument("--sq", default=None)
+    kk.add_argument("--kernel", action="append", required=True)
+    kk.add_argument("--copy-kernel", required=True)
+    kk.add_argument("--copy-bytes", type=float, required=True)
     c = sub.add_parser("counters")
     c.add_argument("dbs", nargs="+")
     c.add_argument("--kernel", action="append", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(trace_table(a.db, a.top, a.by_grid))
+    elif a.cmd == "kernels":
+        print(kernels_table(a.fetch_db, a.write_db, a.trace_db, a.kernel, a.copy_kernel, a.copy_bytes, a.sq))
     elif a.cmd == "counters":
         print(counters_table(a.dbs, a.kernel))
     else:
