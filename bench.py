@@ -10,7 +10,9 @@ resident in HBM.  Two configurations run on the same workload:
           timed again with the previous-step start, and the speedup is
           taken against the faster of the two
   value   the project configuration: BF16 blocks with FP64 refinement sweeps,
-          block-Jacobi, learned warm start (network trained online first);
+          block-Jacobi, learned warm start (the network trained offline on
+          the 512 x 512 solver's trajectories, paper_2008_00409_amd/
+          ws_params_512.npy, or online first when that file is absent);
           timed again with the previous-step start, so that the learned
           start's own share of the speedup is a number of its own
 
@@ -246,7 +248,10 @@ def main():
     ap.add_argument("--no-paired", action="store_true",
                     help="skip the untimed replay that solves every timed step's system from each start")
     ap.add_argument("--prof-every", type=int, default=8)
-    ap.add_argument("--train-steps", type=int, default=30)
+    ap.add_argument("--train-steps", type=int, default=30,
+                    help="online training steps when no trained parameters are given")
+    ap.add_argument("--ws-params", default=os.path.join(ROOT, "paper_2008_00409_amd", "ws_params_512.npy"),
+                    help="trained warm-start parameters (train_ws.py); '' trains online instead")
     ap.add_argument("--autotune", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -303,7 +308,19 @@ def main():
     train_info = None
     params = None
     if args.warm == "learned":
-        params, train_info = train_warm_start(binding, meshgen, args.train_steps, 3, 1e-3, log)
+        if args.ws_params and os.path.exists(args.ws_params):
+            # the network trained offline on the 512 x 512 solver's trajectories
+            params = np.load(args.ws_params).astype(np.float32)
+            train_info = {"source": os.path.relpath(args.ws_params, ROOT)}
+            meta = os.path.splitext(args.ws_params)[0] + ".json"
+            if os.path.exists(meta):
+                with open(meta) as fh:
+                    m = json.load(fh)
+                train_info.update({k: m[k] for k in ("workload", "solver", "episodes_total", "steps_total",
+                                                     "adam_steps_total", "adam_per_step", "lr") if k in m})
+            log(f"# warm-start network: {train_info}")
+        else:
+            params, train_info = train_warm_start(binding, meshgen, args.train_steps, 3, 1e-3, log)
     ctx = new_context(binding, cloth, contacts)
     if params is not None:
         ctx.ws_set_params(params)

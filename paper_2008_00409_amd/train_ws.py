@@ -69,6 +69,7 @@ def main(argv=None):
         pin = torch.from_numpy(c.pinned.astype(bool)).cuda()
         x_pin = x[pin].clone()
         losses, iters = [], []
+        failed = None
         t0 = time.perf_counter()
         for k in range(a.steps):
             b = ctx.cloth_assemble(x, v, a.blocks)
@@ -76,7 +77,13 @@ def main(argv=None):
                 L = ctx.ws_train_step(x, v, b, dvp, lr=a.lr, want_loss=(it == 0))
                 if it == 0:
                     losses.append(L)
-            dv, info = ctx.cloth_pcg_solve(b, dv=dvp.clone(), tol=c.tol, warm="learned", precond="block")
+            dv, info = ctx.cloth_pcg_solve(b, dv=dvp.clone(), tol=c.tol, warm="learned", precond="block",
+                                           raise_on_error=False)
+            if info["status"] != binding.PC_OK:
+                # the trajectory cannot go on from an unconverged step: end the episode here
+                failed = {"step": k, "status": binding.STATUS_NAMES.get(info["status"], info["status"]),
+                          "iters": info["iters"], "rel_res_true": info["rel_res_true"]}
+                break
             iters.append(info["iters"])
             v += dv
             v[pin] = 0
@@ -85,9 +92,11 @@ def main(argv=None):
             dvp = dv
         params = ctx.ws_get_params()
         ctx.close()
-        rec = {"episode": ep, "seed": 4000 + ep, "steps": a.steps, "seconds": time.perf_counter() - t0,
+        rec = {"episode": ep, "seed": 4000 + ep, "steps": len(iters), "seconds": time.perf_counter() - t0,
                "loss_first": losses[0], "loss_last": losses[-1], "loss_mean_last_20": float(np.mean(losses[-20:])),
-               "cg_iters_mean": float(np.mean(iters))}
+               "cg_iters_mean": float(np.mean(iters)) if iters else None}
+        if failed:
+            rec["ended_early"] = failed
         episodes.append(rec)
         print(json.dumps(rec), flush=True)
         np.save(a.out, params)
