@@ -432,9 +432,12 @@ static int cmp_i64(const void *pa, const void *pb) {
  * too small); rowptr has nv+1 entries. */
 int or_pattern2(int nv, int nt, const int32_t *tris, int H, const int32_t *hinges, int nc, const int32_t *cverts,
                 int32_t *rowptr, int32_t *colidx, int cap) {
-    size_t nkeys = (size_t)9 * nt + (size_t)16 * H + (size_t)16 * nc;
+    size_t nkeys = (size_t)9 * nt + (size_t)16 * H + (size_t)16 * nc + (size_t)nv;
     int64_t *keys = (int64_t *)malloc(sizeof(int64_t) * (nkeys ? nkeys : 1));
     size_t m = 0;
+    /* M is diagonal with positive masses (Eq. 3): every row holds its
+       diagonal block, also a vertex that no element touches */
+    for (int i = 0; i < nv; ++i) keys[m++] = (int64_t)i * nv + i;
     for (int t = 0; t < nt; ++t)
         for (int k = 0; k < 3; ++k)
             for (int l = 0; l < 3; ++l) keys[m++] = (int64_t)tris[3 * t + k] * nv + tris[3 * t + l];

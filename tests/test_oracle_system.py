@@ -291,6 +291,37 @@ def test_pcg_edge_cases(oracle_mod):
     assert not info["converged"] and info["iters"] == 1
 
 
+def test_isolated_vertices_hold_only_the_mass_term(oracle_mod):
+    """A vertex that no element touches: K has nothing in its row, so its
+    row of A (Eq. 3) is the diagonal block m_i I alone, b_i = h m_i g when
+    free and 0 when pinned, and the solve gives dv_i = h g (0 when pinned)."""
+    rest, tris, mass, pinned, x0 = small_sheet(4, seed=5)
+    n0, n_iso = rest.shape[0], 5
+    rng = np.random.default_rng(2)
+    extra = rng.uniform(-0.5, 0.5, size=(n_iso, 3))
+    rest2 = np.vstack([rest, extra])
+    x2 = np.vstack([x0, extra + 0.01])
+    m2 = np.concatenate([mass, rng.uniform(0.5, 2.0, n_iso) * mass.mean()])
+    p2 = np.concatenate([pinned, np.array([0, 0, 0, 0, 1], np.uint8)])
+    h = 0.01
+    P = oracle_mod.Problem(rest2, tris, m2, p2, h)
+    A = P.assemble(x2, np.zeros_like(x2))
+    g = np.array(mg.GRAVITY)
+    for i in range(n0, n0 + n_iso):
+        assert P.rowptr[i + 1] - P.rowptr[i] == 1 and P.colidx[P.rowptr[i]] == i
+        np.testing.assert_array_equal(A.vals[P.rowptr[i]].reshape(3, 3), m2[i] * np.eye(3))
+        np.testing.assert_array_equal(A.diag[i], m2[i])
+        want_b = np.zeros(3) if p2[i] else h * m2[i] * g
+        np.testing.assert_allclose(A.b[i], want_b, rtol=1e-15, atol=0)
+    # no other row has a block in an isolated vertex's column
+    assert not np.isin(P.colidx, np.arange(n0, n0 + n_iso)).sum() > n_iso
+    dv, info = P.pcg(A, tol=1e-12)
+    assert info["converged"]
+    for i in range(n0, n0 + n_iso):
+        want = np.zeros(3) if p2[i] else h * g
+        np.testing.assert_allclose(dv[i], want, rtol=1e-9, atol=1e-14)
+
+
 def test_update_and_pins(oracle_mod):
     c = mg.config_tiny()
     P = oracle_mod.Problem.from_cloth(c)
