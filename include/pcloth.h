@@ -374,8 +374,11 @@ pc_status pc_ws_gradient(pc_ctx *ctx, const double *x, const double *v, const do
 pc_status pc_ws_train_step(pc_ctx *ctx, const double *x, const double *v, const double *b, const double *dv_prev,
                            double lr, double *loss_host, void *stream);
 /* Matrix-core lane-layout self test: D = A*B for two known 16x16 BF16 pairs
- * (A[i][k] = 16i+k, B = I; then A = I, B[k][j] = 16k+j); out_host receives
- * the two 16x16 FP32 results, row-major (512 floats). */
+ * (A[i][k] = 16i+k, B = I; then A = I, B[k][j] = 16k+j) with the 16x16x16
+ * instruction, then the 16x16x32 instruction on the concatenated tile pairs
+ * (A0, A1) with A0[i][k] = 16i+k, A1[i][k] = 256-16i-k, and (B0, B1) = (I, 0),
+ * then (0, I); out_host receives the four 16x16 FP32 results, row-major
+ * (1024 floats: A, B, A0, A1 when the layout is the one the kernels use). */
 pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
 
 /* Context options.  The schedule options (graph chunk, slices and rows per

@@ -509,9 +509,9 @@ class Context:
         return loss.value if want_loss else None
 
     def mfma_probe(self):
-        out = np.zeros(512, dtype=np.float32)
+        out = np.zeros(1024, dtype=np.float32)
         self._check(lib().pc_mfma_probe(self.h, out.ctypes.data_as(ctypes.c_void_p)))
-        return out.reshape(2, 16, 16)
+        return out.reshape(4, 16, 16)
 
     def set_option(self, option, value):
         self._check(lib().pc_set_option(self.h, int(option), int(value)))

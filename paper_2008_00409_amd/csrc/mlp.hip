@@ -1,5 +1,5 @@
 // Learned CG warm start: per-vertex features, a 27-64-64-64-3 ReLU MLP on
-// BF16 matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation), its
+// BF16 matrix cores (gfx950's v_mfma_f32_16x16x32_bf16, FP32 accumulation), its
 // backward pass, split-K weight gradients and Adam.  The prediction is a
 // correction to the previous step's velocity increment and starts the CG
 // solve of Eq. 3 (paper Sec. 2.5).
@@ -21,10 +21,24 @@
 namespace pc {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// gfx950's 16 x 16 x 32 product on two K tiles at once: lane l holds rows /
+// columns l % 16 and K values 8 (l / 16) .. + 7 of A and B, so two 16 x 16 x 16
+// operand pairs (K 4 (l / 16) .. + 3 of tiles 0 and 1) concatenated in the
+// same order on both sides give the sum of both tile products (the order of
+// the K terms does not change the product).  D has the 16 x 16 x 16 layout.
+__device__ __forceinline__ f32x4 mfma32(bf16x4 a0, bf16x4 a1, bf16x4 b0, bf16x4 b1, f32x4 c) {
+    const s16x8 a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    const s16x8 b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
 }
 
 __device__ __forceinline__ short f2bf(float f) {
@@ -49,7 +63,11 @@ static_assert(OFF_B4 + 16 == MLP_PADDED, "padded parameter count");
 // ---------------------------------------------------------------- layout probe
 // D = A * B with A[i][k] = i * 16 + k and B = I (then D must equal A), and
 // with A = I and B[k][j] = k * 16 + j (then D must equal B): checks the lane
-// layout the kernels assume for A, B and D.
+// layout the kernels assume for A, B and D of the 16 x 16 x 16 product.  Then
+// the 16 x 16 x 32 product through mfma32 on the tile pairs (A0, A1), (B0,
+// B1) with A0[i][k] = 16 i + k, A1[i][k] = 256 - 16 i - k: with B0 = I, B1 =
+// 0 it must return A0, with B0 = 0, B1 = I it must return A1 (all values are
+// integers of at most 256, exact in BF16).
 __global__ void __launch_bounds__(64) k_mfma_probe(float *out) {
     const int l = threadIdx.x;
     for (int t = 0; t < 2; ++t) {
@@ -65,6 +83,20 @@ __global__ void __launch_bounds__(64) k_mfma_probe(float *out) {
         f32x4 c = {0.f, 0.f, 0.f, 0.f};
         c = mfma16(a, b, c);
         for (int i = 0; i < 4; ++i) out[t * 256 + (4 * (l / 16) + i) * 16 + (l % 16)] = c[i];
+    }
+    for (int t = 0; t < 2; ++t) {
+        bf16x4 a0, a1, b0, b1;
+        for (int i = 0; i < 4; ++i) {
+            const int row = l % 16, k = 4 * (l / 16) + i, col = l % 16;
+            a0[i] = f2bf((float)(16 * row + k));
+            a1[i] = f2bf((float)(256 - 16 * row - k));
+            const float id = k == col ? 1.0f : 0.0f;
+            b0[i] = f2bf(t == 0 ? id : 0.0f);
+            b1[i] = f2bf(t == 0 ? 0.0f : id);
+        }
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        c = mfma32(a0, a1, b0, b1, c);
+        for (int i = 0; i < 4; ++i) out[(2 + t) * 256 + (4 * (l / 16) + i) * 16 + (l % 16)] = c[i];
     }
 }
 
@@ -196,27 +228,26 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(FwdArgs F) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             f32x4 c = {0.f, 0.f, 0.f, 0.f};
-            c = mfma16(A1[m][0], X0, c);
-            c = mfma16(A1[m][1], X1, c);
+            c = mfma32(A1[m][0], A1[m][1], X0, X1, c);
             H1[m] = act_relu(c, b1, 16 * m);
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) c = mfma16(A2[m][k], H1[k], c);
+            c = mfma32(A2[m][0], A2[m][1], H1[0], H1[1], c);
+            c = mfma32(A2[m][2], A2[m][3], H1[2], H1[3], c);
             H2[m] = act_relu(c, b2, 16 * m);
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) c = mfma16(A3[m][k], H2[k], c);
+            c = mfma32(A3[m][0], A3[m][1], H2[0], H2[1], c);
+            c = mfma32(A3[m][2], A3[m][3], H2[2], H2[3], c);
             H3[m] = act_relu(c, b3, 16 * m);
         }
         f32x4 y = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) y = mfma16(A4[k], H3[k], y);
+        y = mfma32(A4[0], A4[1], H3[0], H3[1], y);
+        y = mfma32(A4[2], A4[3], H3[2], H3[3], y);
         if (F.H1) {
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -296,8 +327,8 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(BwdArgs B) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) c = mfma16(A3[m][k], G3[k], c);
+            c = mfma32(A3[m][0], A3[m][1], G3[0], G3[1], c);
+            c = mfma32(A3[m][2], A3[m][3], G3[2], G3[3], c);
             const bf16x4 h = load_act(B.H2, 64, v0, 16 * m);
             bf16x4 r;
 #pragma unroll
@@ -308,8 +339,8 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(BwdArgs B) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             f32x4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) c = mfma16(A2[m][k], G2[k], c);
+            c = mfma32(A2[m][0], A2[m][1], G2[0], G2[1], c);
+            c = mfma32(A2[m][2], A2[m][3], G2[2], G2[3], c);
             const bf16x4 h = load_act(B.H1, 64, v0, 16 * m);
             bf16x4 r;
 #pragma unroll
@@ -342,8 +373,11 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(int ntiles, const short *X, c
     f32x4 acc[MAXT];
 #pragma unroll
     for (int q = 0; q < MAXT; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int t = t0; t < t1; ++t) {
+    // two vertex tiles (32 vertices) per product; a missing second tile of
+    // the range contributes zeros
+    for (int t = t0; t < t1; t += 2) {
         const int v0 = 16 * t;
+        const bool two = t + 1 < t1;
 #pragma unroll
         for (int q = 0; q < MAXT; ++q) {
             const int tile = w + 4 * q;
@@ -353,15 +387,18 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(int ntiles, const short *X, c
             const int win = T.layer == 0 ? 32 : 64;
             const short *Gout = T.layer == 0 ? G1 : (T.layer == 1 ? G2 : (T.layer == 2 ? G3 : G4));
             const int wout = T.layer == 3 ? 16 : 64;
-            bf16x4 a, bb;
+            bf16x4 a[2], bb[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int vtx = v0 + 4 * (l / 16) + i;
-                a[i] = T.bias ? (short)((l % 16) == 0 ? 0x3F80 : 0)
-                              : Hin[(int64_t)vtx * win + 16 * T.mb + l % 16];
-                bb[i] = Gout[(int64_t)vtx * wout + 16 * T.nb + l % 16];
-            }
-            acc[q] = mfma16(a, bb, acc[q]);
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int vtx = v0 + 16 * h + 4 * (l / 16) + i;
+                    const bool in = h == 0 || two;
+                    a[h][i] = T.bias ? (short)((l % 16) == 0 && in ? 0x3F80 : 0)
+                                     : (in ? Hin[(int64_t)vtx * win + 16 * T.mb + l % 16] : (short)0);
+                    bb[h][i] = in ? Gout[(int64_t)vtx * wout + 16 * T.nb + l % 16] : (short)0;
+                }
+            acc[q] = mfma32(a[0], a[1], bb[0], bb[1], acc[q]);
         }
     }
 #pragma unroll
@@ -374,14 +411,31 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(int ntiles, const short *X, c
     }
 }
 
-// Sum the per-block partial tiles in block order and scatter them to the
-// padded parameter layout.
-__global__ void k_mlp_grad_reduce(int nblocks, const float *part, float *grad) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= MLP_GRAD_TILES * 256) return;
-    const int tile = e / 256, rc = e % 256, r = rc / 16, c = rc % 16;
+// Sum the per-block partial tiles and scatter them to the padded parameter
+// layout.  Workgroup (tile, quarter) owns 64 of the tile's 256 entries: lane
+// group g (16 lanes, one float4 each) adds the partials of blocks g, g + 16,
+// g + 32, ... and the 16 group sums are then added in group order through
+// LDS, so the result is the same on every run.
+__global__ void __launch_bounds__(256) k_mlp_grad_reduce(int nblocks, const float *part, float *grad) {
+    __shared__ float4 red[16][16];
+    const int tile = blockIdx.x, quarter = blockIdx.y;
+    const int j = threadIdx.x % 16, g = threadIdx.x / 16;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int b = g; b < nblocks; b += 16) {
+        const float4 p =
+            *reinterpret_cast<const float4 *>(part + ((int64_t)b * MLP_GRAD_TILES + tile) * 256 + 64 * quarter + 4 * j);
+        acc.x += p.x; acc.y += p.y; acc.z += p.z; acc.w += p.w;
+    }
+    red[g][j] = acc;
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const int e = threadIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += part[((int64_t)b * MLP_GRAD_TILES + tile) * 256 + rc];
+    for (int q = 0; q < 16; ++q) {
+        const float4 v = red[q][e / 4];
+        s += (e % 4) == 0 ? v.x : ((e % 4) == 1 ? v.y : ((e % 4) == 2 ? v.z : v.w));
+    }
+    const int rc = 64 * quarter + e, r = rc / 16, c = rc % 16;
     const GradTile T = c_tiles[tile];
     const int offW[4] = {OFF_W1, OFF_W2, OFF_W3, OFF_W4}, offB[4] = {OFF_B1, OFF_B2, OFF_B3, OFF_B4};
     const int wout = T.layer == 3 ? 16 : 64;
@@ -656,8 +710,8 @@ pc_status mlp_gradient(Ctx *ctx, MlpState *M, const double *x, const double *v, 
     hipLaunchKernelGGL(k_mlp_bwd, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, Bw);
     hipLaunchKernelGGL(k_mlp_wgrad, dim3(MLP_WGRAD_BLOCKS), dim3(256), 0, s, M->nv_pad / 16, M->X, M->H1, M->H2,
                        M->H3, M->G1, M->G2, M->G3, M->G4, M->part);
-    hipLaunchKernelGGL(k_mlp_grad_reduce, dim3((MLP_GRAD_TILES * 256 + 255) / 256), dim3(256), 0, s,
-                       MLP_WGRAD_BLOCKS, M->part, M->g);
+    hipLaunchKernelGGL(k_mlp_grad_reduce, dim3(MLP_GRAD_TILES, 4), dim3(256), 0, s, MLP_WGRAD_BLOCKS, M->part,
+                       M->g);
     PC_HIP(hipGetLastError());
     if (loss) {
         double d[3];
@@ -796,11 +850,11 @@ pc_status mlp_predict_noalloc(Ctx *ctx, const double *x, const double *v, const 
 
 pc_status mlp_probe(Ctx *ctx, float *host_out) {
     float *d = nullptr;
-    pc_status st = dev_alloc(ctx, (void **)&d, sizeof(float) * 512);
+    pc_status st = dev_alloc(ctx, (void **)&d, sizeof(float) * 1024);
     if (st) return st;
     hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, 0, d);
     PC_HIP(hipGetLastError());
-    PC_HIP(hipMemcpy(host_out, d, sizeof(float) * 512, hipMemcpyDeviceToHost));
+    PC_HIP(hipMemcpy(host_out, d, sizeof(float) * 1024, hipMemcpyDeviceToHost));
     dev_free(ctx, d);
     return PC_OK;
 }

@@ -70,8 +70,12 @@ def test_mfma_lane_layout(torch, B):
     try:
         out = ctx.mfma_probe()
         idx = np.arange(16)
-        np.testing.assert_array_equal(out[0], idx[:, None] * 16 + idx[None, :])
-        np.testing.assert_array_equal(out[1], idx[:, None] * 16 + idx[None, :])
+        a = idx[:, None] * 16 + idx[None, :]
+        np.testing.assert_array_equal(out[0], a)
+        np.testing.assert_array_equal(out[1], a)
+        # 16 x 16 x 32: the two K tiles of A come back apart
+        np.testing.assert_array_equal(out[2], a)
+        np.testing.assert_array_equal(out[3], 256 - a)
     finally:
         ctx.close()
 
