@@ -48,13 +48,29 @@ TRAFFIC_FILES = {"k_pcg_spmv<pc::bf16_t, true, float>": "k_pcg_spmv_bf16_stacked
                  "k_pcg_spmv<float, true, double>": "k_pcg_spmv_f32_stacked-3x501x551_traffic.md"}
 
 
-def spmv_bytes(nv, nnzb, blocks, col_bytes=4, q_bytes=24):
+def spmv_bytes(nv, nblk, blocks, col_bytes=4, q_bytes=24):
     """Algorithmic bytes of one difference-form SpMV in the CG loop: every
-    stored block and its column index once (16-bit offsets when the SpMV
-    runs with them, else 32-bit columns), the input vector once per row
-    (float4), the output (FP64, or FP32 inside the BF16 refinement sweeps),
-    the FP64 mass, and the row pointers."""
-    return nnzb * (BLOCK_BYTES[blocks] + col_bytes) + nv * (16 + q_bytes + 8) + 4 * (nv + 1)
+    block the solver layout stores (nblk: the pattern's blocks less the
+    diagonal blocks it leaves out because they are zero) and its column index
+    (16-bit offsets when the SpMV runs with them, else 32-bit columns), the
+    input vector once per row (float4), the output (FP64, or FP32 inside the
+    BF16 refinement sweeps), the FP64 mass, and the row pointers."""
+    return nblk * (BLOCK_BYTES[blocks] + col_bytes) + nv * (16 + q_bytes + 8) + 4 * (nv + 1)
+
+
+def solver_blocks(rowptr, colidx, pinned):
+    """Blocks the solver layout stores: every block of the pattern except
+    the diagonal of rows whose remainder D_i is zero, i.e. of pinned rows and
+    of free rows without a pinned column."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    colidx = np.asarray(colidx)
+    pinned = np.asarray(pinned)
+    nv = rowptr.size - 1
+    rows = np.repeat(np.arange(nv), np.diff(rowptr))
+    offd_pinned = (colidx != rows) & (pinned[colidx] != 0)
+    has_pin = np.bincount(rows[offd_pinned], minlength=nv) > 0
+    keep = has_pin & (pinned == 0)
+    return int(colidx.size - (nv - int(keep.sum())))
 
 
 def assembly_bytes(nv, nt, nh, nnzb, blocks):
@@ -286,13 +302,14 @@ def main():
         el, infos, prof = time_steps(ctx, x, v, args.steps, args.warmup, "f32", tol, "zero", args.prof_every)
         rowptr, colidx = ctx.pattern()
         nnzb = int(colidx.numel())
+        nblk = solver_blocks(rowptr.cpu().numpy(), colidx.cpu().numpy(), cloth.pinned)
         sp = prof.get("spmv", {}).get("median_ms", float("nan"))
         cb = 2 if ctx.get_option(binding.PC_OPT_SPMV_NARROW_ACTIVE) else 4
         rec_plain = {"steps_per_s": args.steps / el, "block_storage": "f32", "warm_start": "zero",
                      "preconditioner": "jacobi", "schedule": tune_plain,
                      "cg_iters_per_step": [i["iters"] for i in infos],
                      "rel_res_true_max": max(i["rel_res_true"] for i in infos),
-                     "spmv_median_ms": sp, "spmv_GBs": spmv_bytes(ctx.nv, nnzb, "f32", cb) / (sp * 1e-3) / 1e9}
+                     "spmv_median_ms": sp, "spmv_GBs": spmv_bytes(ctx.nv, nblk, "f32", cb) / (sp * 1e-3) / 1e9}
         log(f"# plain: {rec_plain['steps_per_s']:.3f} steps/s, iters {rec_plain['cg_iters_per_step']}")
         # the same solver with the previous-step start, from the same initial
         # state on the same schedule; the speedup is taken against the faster
@@ -335,6 +352,7 @@ def main():
                                  args.precond, args.inner_rho, args.method)
     rowptr, colidx = ctx.pattern()
     nnzb = int(colidx.numel())
+    nblk = solver_blocks(rowptr.cpu().numpy(), colidx.cpu().numpy(), cloth.pinned)
     nv, nt, nh = ctx.nv, ctx.nt, ctx.nh
     iters = [i["iters"] for i in infos]
     log(f"# timed: {args.steps} steps in {el:.3f} s, iters {iters}, sweeps {[i['sweeps'] for i in infos]}, "
@@ -411,7 +429,7 @@ def main():
     narrow = bool(ctx.get_option(binding.PC_OPT_SPMV_NARROW_ACTIVE))
     inner32 = args.blocks == "bf16" and args.method == "cg" and bool(ctx.get_option(binding.PC_OPT_INNER_FP32))
     kname = f"k_pcg_spmv<{KERNEL_TB[args.blocks]}, {'true' if narrow else 'false'}, {'float' if inner32 else 'double'}>"
-    alg = spmv_bytes(nv, nnzb, args.blocks, 2 if narrow else 4, 12 if inner32 else 24)
+    alg = spmv_bytes(nv, nblk, args.blocks, 2 if narrow else 4, 12 if inner32 else 24)
     ach = alg / (spmv_ms * 1e-3) / 1e9 if spmv_ms == spmv_ms and spmv_ms > 0 else None
     asm = prof.get("assemble_all", {})
     asm_ms = asm.get("median_ms", float("nan"))
@@ -462,7 +480,7 @@ def main():
             "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (ach / HBM_PEAK_GBS) if ach else None, "traffic": read_traffic(kname),
             "median_launch_ms": spmv_ms, "samples": spmv.get("samples", 0),
-            "algorithmic_bytes_per_launch": alg,
+            "algorithmic_bytes_per_launch": alg, "solver_blocks": nblk, "pattern_blocks": nnzb,
         },
         "kernels": {k: {"median_ms": round(vv["median_ms"], 5), "mean_ms": round(vv["mean_ms"], 5),
                         "samples": vv["samples"]} for k, vv in prof.items()},

@@ -104,7 +104,7 @@ static void free_all(Ctx *c) {
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
                     c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn, c->jdel, c->cg_pd, c->cg_s, c->e32, c->r32, c->q32,
                     c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d,
-                    c->slot_off, c->row_state, c->wide_rows, c->trec, c->hrec, c->crec, c->row_npairs,
+                    c->slot_off, c->rowlen_s, c->row_state, c->wide_rows, c->trec, c->hrec, c->crec, c->row_npairs,
                     c->cols_tmp, c->pairs_tmp};
     for (void *p : ptrs) dev_free(c, p);
     if (c->st_host) (void)hipHostFree(c->st_host);

@@ -521,6 +521,10 @@ struct AsmArgs {
     const double *v;
     DevParams prm;
     int *rowlen, *rowptr, *colidx, *jcol;
+    // blocks of each row in the solver layout: rowlen, less the diagonal
+    // block when it is zero (D_i = 0 unless the row is free and has a pinned
+    // column; the SpMV applies the mass term apart)
+    int *rowlen_s;
     int16_t *jdel;
     const int *row_lane, *lane_row, *row_slice, *slice_row0, *slice_vbase, *slot_off;
     const uint8_t *slot_cnt;
@@ -670,7 +674,8 @@ __device__ __forceinline__ int row_columns_g(RowGroupLDS<NI> &L, const AsmArgs &
 // row are distinct) and write them back in place, then count its distinct
 // columns.  Returns the row length, 0 when n > NI (not handled here).
 template <int G, int NI>
-__device__ __forceinline__ int row_pattern_g(RowGroupLDS<NI> &L, const AsmArgs &A, int i, bool act, int t) {
+__device__ __forceinline__ int row_pattern_g(RowGroupLDS<NI> &L, const AsmArgs &A, int i, bool act, int t,
+                                             bool &keep) {
     int p0 = 0, n = 0;
     if (act) {
         p0 = A.inc_ptr[i];
@@ -692,21 +697,32 @@ __device__ __forceinline__ int row_pattern_g(RowGroupLDS<NI> &L, const AsmArgs &
     if (fits)
         for (int m = t; m < n; m += G) A.inc[p0 + m] = (int)L.code[m];
     const int len = row_columns_g<G, NI>(L, A, i, n, fits, t);
+    // does the row keep its diagonal block: free, with a pinned column
+    int anyp = 0;
+    if (fits)
+        for (int q = t; q < len; q += G) {
+            const int c = L.cols[q];
+            anyp |= (c != i && A.pinned[c]) ? 1 : 0;
+        }
+    anyp = group_sum_int<G>(anyp);
+    keep = fits && anyp > 0 && !A.pinned[i];
     return fits ? len : 0;
 }
 
 // Lane-level: rows a group passes on to the wide-row pass, and rows beyond
 // every capacity (length 1, reported through the status word).
-__device__ __forceinline__ void row_record(const AsmArgs &A, int i, int len, bool wide_pass) {
+__device__ __forceinline__ void row_record(const AsmArgs &A, int i, int len, bool keep, bool wide_pass) {
     if (len > MAX_COLS || (len == 0 && wide_pass)) {
         atomicOr(A.status, len > MAX_COLS ? ST_COL_OVERFLOW : ST_INC_OVERFLOW);
         A.rowlen[i] = 1;
+        A.rowlen_s[i] = 1;
         A.row_state[i] = wide_pass ? ROW_WIDE_OVERFLOW : ROW_OVERFLOW;
     } else if (len == 0) {
         A.row_state[i] = ROW_WIDE;
         A.wide_rows[atomicAdd(A.wide_count, 1)] = i;
     } else {
         A.rowlen[i] = len;
+        A.rowlen_s[i] = keep ? len : len - 1;
         A.row_state[i] = wide_pass ? ROW_WIDE : ROW_GROUP;
     }
 }
@@ -765,8 +781,9 @@ __global__ void __launch_bounds__(64) k_row_pattern(AsmArgs A) {
     const int g = threadIdx.x / RG, t = threadIdx.x % RG;
     const int i = xcd_remap(blockIdx.x, gridDim.x) * RG_ROWS + g;
     const bool act = i < A.nv;
-    const int len = row_pattern_g<RG, RG_NI>(Ls[g], A, i, act, t);
-    if (act && t == 0) row_record(A, i, len, false);
+    bool keep = false;
+    const int len = row_pattern_g<RG, RG_NI>(Ls[g], A, i, act, t, keep);
+    if (act && t == 0) row_record(A, i, len, keep, false);
     row_pairs_g(Ls[g], A, i, len, act && len > 0 && len <= MAX_COLS, t);
 }
 
@@ -777,8 +794,9 @@ __global__ void __launch_bounds__(64) k_row_pattern_wide(AsmArgs A) {
     const int nw = *A.wide_count;
     for (int idx = blockIdx.x; idx < nw; idx += gridDim.x) {
         const int i = A.wide_rows[idx];
-        const int len = row_pattern_g<WAVE, WIDE_NI>(L, A, i, true, threadIdx.x);
-        if (threadIdx.x == 0) row_record(A, i, len, true);
+        bool keep = false;
+        const int len = row_pattern_g<WAVE, WIDE_NI>(L, A, i, true, threadIdx.x, keep);
+        if (threadIdx.x == 0) row_record(A, i, len, keep, true);
         __syncthreads();
     }
 }
@@ -933,13 +951,23 @@ __device__ __forceinline__ void add_force(const AsmArgs &A, unsigned code, doubl
 
 // Block s of row i (column col) into the block-CSR column list and the
 // solver layout, in the solver's type and, when kept, in FP64.
+// The solver slot of the row's s-th column (dpos: the diagonal's position;
+// -1 for a diagonal block the solver layout leaves out).
+__device__ __forceinline__ int solver_slot(const AsmArgs &A, int i, int s, int dpos) {
+    const bool keep = A.rowlen_s[i] == A.rowlen[i];
+    return keep || s < dpos ? s : (s == dpos ? -1 : s - 1);
+}
+
 template <typename TB>
-__device__ __forceinline__ void store_row_block(const AsmArgs &A, int i, int s, int col, const double blk[9]) {
+__device__ __forceinline__ void store_row_block(const AsmArgs &A, int i, int s, int dpos, int col,
+                                                const double blk[9]) {
+    A.colidx[A.rowptr[i] + s] = col;
+    s = solver_slot(A, i, s, dpos);
+    if (s < 0) return;
     const int si = A.row_slice[i];
     const int w = slot_width((int)A.slot_cnt[si * WAVE + s]);
     const int64_t seg = (int64_t)A.slice_vbase[si] + A.slot_off[si * WAVE + s];
     const int lane = A.row_lane[i];
-    A.colidx[A.rowptr[i] + s] = col;
     A.jcol[seg + lane] = col;
     // offset from the slice's first row; meaningful only when it fits (the
     // solver checks every slice before using it)
@@ -982,7 +1010,7 @@ __device__ __forceinline__ void write_row_diagonal(const AsmArgs &A, int i, int 
     const double o02 = rowpin ? 0.0 : -P.c * red[7];
     const double o12 = rowpin ? 0.0 : -P.c * red[8];
     store_block_inverse(A.binv + 6 * (int64_t)i, d0, o01, o02, d1, o12, d2);
-    store_row_block<TB>(A, i, dslot, i, blk);
+    store_row_block<TB>(A, i, dslot, dslot, i, blk);
 }
 
 // Values of one row.  Lane t of the group owns the column slots s = t, t + G,
@@ -1014,6 +1042,8 @@ __device__ __forceinline__ void row_values_g(RowGroupLDS<NI> &L, const AsmArgs &
     if (act) {
         rowpin = A.pinned[i] != 0;
         const d3 vi = ld3(A.v, i);
+        int dpos = 0;
+        for (int q = 0; q < len; ++q) dpos += L.cols[q] < i ? 1 : 0;
         for (int s = t; s < len; s += G) {
             const int col = L.cols[s];
             if (col == i) {
@@ -1045,7 +1075,7 @@ __device__ __forceinline__ void row_values_g(RowGroupLDS<NI> &L, const AsmArgs &
             double blk[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) blk[q] = (rowpin || colpin) ? 0.0 : P.c * acc[q];
-            store_row_block<TB>(A, i, s, col, blk);
+            store_row_block<TB>(A, i, s, dpos, col, blk);
         }
         for (int m = t; m < n; m += G) add_force(A, L.code[m], f);
     }
@@ -1119,6 +1149,8 @@ __global__ void __launch_bounds__(64) k_row_values(AsmArgs A) {
     if (act) {
         rowpin = A.pinned[i] != 0;
         const d3 vi = ld3(A.v, i);
+        int dpos = 0;
+        for (int q = 0; q < len; ++q) dpos += L.cols[q] < i ? 1 : 0;
         for (int s = t; s < len; s += RG) {
             const int col = L.cols[s];
             if (col == i) {
@@ -1154,7 +1186,7 @@ __global__ void __launch_bounds__(64) k_row_values(AsmArgs A) {
             double blk[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) blk[q] = (rowpin || colpin) ? 0.0 : P.c * acc[q];
-            store_row_block<TB>(A, i, s, col, blk);
+            store_row_block<TB>(A, i, s, dpos, col, blk);
         }
         for (int m = t; m < n; m += RG) add_force(A, L.code[m], f);
     }
@@ -1193,28 +1225,36 @@ __global__ void __launch_bounds__(64) k_row_values_wide(AsmArgs A) {
 // Export: solver layout -> block-CSR FP64 with the true diagonal block
 // A_ii = m_i I + D_i - sum_{j != i} A_ij; optionally D_i.
 template <typename TB>
-__global__ void __launch_bounds__(64) k_export(int nv, const int *rowptr, const int *row_lane, const int *row_slice,
-                                               const int *slice_vbase, const uint8_t *slot_cnt, const int *jcol,
-                                               const void *jval, const double *mass, double *out, double *Dout) {
+__global__ void __launch_bounds__(64) k_export(int nv, const int *rowptr, const int *colidx, const int *rowlen_s,
+                                               const int *row_lane, const int *row_slice, const int *slice_vbase,
+                                               const uint8_t *slot_cnt, const void *jval, const double *mass,
+                                               double *out, double *Dout) {
     const int i = blockIdx.x;
     if (i >= nv) return;
     const int t = threadIdx.x;
     const int s = row_slice[i];
+    // solver slot t of the slice: width and offset
     const int w = slot_width((int)slot_cnt[s * WAVE + t]);
     const int off = wave_excl_scan(w);
     const int len = rowptr[i + 1] - rowptr[i];
     const bool active = t < len;
+    const int col = active ? colidx[rowptr[i] + t] : -1;
+    // CSR position t -> solver slot (the diagonal may be left out when zero)
+    const unsigned long long dmask = __ballot(col == i);
+    const int dpos = dmask ? __ffsll((long long)dmask) - 1 : len;
+    const bool keep = rowlen_s[i] == len;
+    const int ss = keep || t < dpos ? t : (t == dpos ? -1 : t - 1);
+    const int w_ss = __shfl(w, ss < 0 ? 0 : ss, WAVE);
+    const int off_ss = __shfl(off, ss < 0 ? 0 : ss, WAVE);
     double blk[9];
-    int col = -1;
-    if (active) {
+    if (active && ss >= 0) {
         // element-wise reads through val_index (the solver reads whole blocks
         // through BlockIO; the two must agree)
-        const int64_t seg = (int64_t)slice_vbase[s] + off;
+        const int64_t seg = (int64_t)slice_vbase[s] + off_ss;
         const int lane = row_lane[i];
-        col = jcol[seg + lane];
         const TB *val = (const TB *)jval + 9 * seg;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) blk[q] = to_f64(val[val_index<TB>(q, w, lane)]);
+        for (int q = 0; q < 9; ++q) blk[q] = to_f64(val[val_index<TB>(q, w_ss, lane)]);
     } else {
 #pragma unroll
         for (int q = 0; q < 9; ++q) blk[q] = 0.0;
@@ -1298,6 +1338,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
             *r.have = r.n;
         }
     if (!ctx->row_state) {
+        if ((st = dev_alloc(ctx, (void **)&ctx->rowlen_s, sizeof(int) * (size_t)nv))) return st;
         if ((st = dev_alloc(ctx, (void **)&ctx->row_state, (size_t)nv))) return st;
         if ((st = dev_alloc(ctx, (void **)&ctx->wide_rows, sizeof(int) * (size_t)nv))) return st;
         if ((st = dev_alloc(ctx, (void **)&ctx->row_npairs, sizeof(int) * (size_t)nv))) return st;
@@ -1342,7 +1383,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     a.Bm = ctx->Bm; a.A0 = ctx->A0; a.mass = ctx->mass;
     a.trec = ctx->trec; a.hrec = ctx->hrec; a.crec = ctx->crec;
     a.pinned = ctx->pinned; a.v = v; a.prm = ctx->prm;
-    a.rowlen = ctx->rowlen; a.rowptr = ctx->rowptr; a.colidx = ctx->colidx; a.jcol = ctx->jcol; a.jdel = ctx->jdel;
+    a.rowlen = ctx->rowlen; a.rowlen_s = ctx->rowlen_s; a.rowptr = ctx->rowptr; a.colidx = ctx->colidx; a.jcol = ctx->jcol; a.jdel = ctx->jdel;
     a.row_lane = ctx->row_lane; a.lane_row = ctx->lane_row; a.slot_cnt = ctx->slot_cnt; a.slot_off = ctx->slot_off; a.jval = ctx->jval;
     a.row_slice = ctx->row_slice; a.slice_row0 = ctx->slice_row0; a.slice_vbase = ctx->slice_vbase;
     a.row_state = ctx->row_state; a.wide_rows = ctx->wide_rows; a.wide_count = (int *)ctx->counter + 1;
@@ -1360,7 +1401,7 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     if ((st = scan_excl(ctx, ctx->rowlen, ctx->rowptr, nv, s))) return st;
     // 4. solver layout
     hipLaunchKernelGGL(k_slice_layout, dim3(ctx->nslices), dim3(64), 0, s, ctx->nslices, ctx->slice_row0,
-                       ctx->rowlen, ctx->lane_row, ctx->row_lane, ctx->slot_cnt, ctx->slot_off, ctx->slice_psize);
+                       ctx->rowlen_s, ctx->lane_row, ctx->row_lane, ctx->slot_cnt, ctx->slot_off, ctx->slice_psize);
     if ((st = scan_excl(ctx, ctx->slice_psize, ctx->slice_vbase, ctx->nslices, s))) return st;
     // 5. values
     slot = ctx->prof.begin(PK_ROW_ASM, s);
@@ -1396,16 +1437,19 @@ pc_status export_blocks(Ctx *ctx, double *vals, double *D, bool solver, hipStrea
     const void *src = (solver || !ctx->hi_valid) ? ctx->jval : (const void *)ctx->jval_hi;
     switch (dt) {
         case PC_F64:
-            hipLaunchKernelGGL(k_export<double>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->row_lane,
-                               ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
+            hipLaunchKernelGGL(k_export<double>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->colidx,
+                               ctx->rowlen_s, ctx->row_lane, ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, src,
+                               ctx->mass, vals, D);
             break;
         case PC_F32:
-            hipLaunchKernelGGL(k_export<float>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->row_lane,
-                               ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
+            hipLaunchKernelGGL(k_export<float>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->colidx,
+                               ctx->rowlen_s, ctx->row_lane, ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, src,
+                               ctx->mass, vals, D);
             break;
         case PC_BF16:
-            hipLaunchKernelGGL(k_export<bf16_t>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->row_lane,
-                               ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, ctx->jcol, src, ctx->mass, vals, D);
+            hipLaunchKernelGGL(k_export<bf16_t>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->colidx,
+                               ctx->rowlen_s, ctx->row_lane, ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, src,
+                               ctx->mass, vals, D);
             break;
     }
     PC_HIP(hipGetLastError());

@@ -189,6 +189,7 @@ struct Ctx {
     uint8_t *slot_cnt = nullptr;  // nslices * 64
     int *slot_off = nullptr;      // nslices * 64: first stored block of each slot, from the slice's first
     uint8_t *row_state = nullptr; // nv: which assembly pass handles each row
+    int *rowlen_s = nullptr;      // nv: blocks of each row in the solver layout (a zero diagonal left out)
     int *wide_rows = nullptr;     // nv: rows of the wide-row passes
     int *row_npairs = nullptr;    // nv: (incidence, corner) pairs of each row
     int *cols_tmp = nullptr;      // 3 ninc + nv: each row's columns, pattern pass -> value pass

@@ -141,13 +141,17 @@ __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, 
     if (row >= 0) x.load(row, x0, x1, x2);
     A a0 = 0, a1 = 0, a2 = 0;
 #if PC_SPMV_PIPE
-    SlotGroup<TB, UNROLL, NARROW> cur;
-    cur.load(M, 0, nslots, lane, my_cnt, my_off, r0);
-    for (int k = 0; k < nslots; k += UNROLL) {
-        SlotGroup<TB, UNROLL, NARROW> nxt;
-        nxt.load(M, k + UNROLL, nslots, lane, my_cnt, my_off, r0);
-        cur.apply(x, row, x0, x1, x2, a0, a1, a2);
-        cur = nxt;
+    // a slice may store no block at all (rows whose only block, a zero
+    // diagonal, is left out): then there is nothing to prefetch
+    if (nslots > 0) {
+        SlotGroup<TB, UNROLL, NARROW> cur;
+        cur.load(M, 0, nslots, lane, my_cnt, my_off, r0);
+        for (int k = 0; k < nslots; k += UNROLL) {
+            SlotGroup<TB, UNROLL, NARROW> nxt;
+            nxt.load(M, k + UNROLL, nslots, lane, my_cnt, my_off, r0);
+            cur.apply(x, row, x0, x1, x2, a0, a1, a2);
+            cur = nxt;
+        }
     }
 #else
     for (int k = 0; k < nslots; k += UNROLL) {

@@ -25,11 +25,30 @@ def B():
     return binding
 
 
+def with_isolated(c, n_iso=70, n_pin=3, seed=11):
+    """c plus n_iso vertices that no element touches, numbered last (the
+    last n_pin of them pinned): their rows hold only the mass term, so whole
+    64-row slices of the solver layout store no block."""
+    rng = np.random.default_rng(seed)
+    extra = rng.uniform(-0.1, 0.1, size=(n_iso, 3))
+    rest = np.vstack([c.rest, extra])
+    x0 = np.vstack([c.x0, extra + 1e-3 * rng.normal(size=extra.shape)])
+    mass = np.concatenate([c.mass, rng.uniform(0.5, 2.0, n_iso) * c.mass.mean()])
+    pinned = np.concatenate([c.pinned, np.zeros(n_iso, np.uint8)])
+    pinned[-n_pin:] = 1
+    nv = rest.shape[0]
+    return mg.Cloth(f"{c.name}+{n_iso}-isolated", rest, c.tris, mass, pinned, x0, np.zeros_like(rest), c.h,
+                    c.tol, 1, [(0, nv)], [(0, c.nt)])
+
+
 def problems():
     yield "tiny", mg.config_tiny(), 0
     yield "ragged-7x9", sheet(7, 9, seed=1), 0            # 63 vertices: one partial slice
     yield "ragged-13x5-flipped", sheet(13, 5, seed=2, flips=0.2), 1   # 65 vertices: 2 slices
     yield "flipped-40x37", sheet(40, 37, seed=3, flips=0.1), 1
+    # 63 sheet rows + 70 isolated: slice 1 (rows 64..127) and the ragged
+    # slice 2 store no block at all
+    yield "isolated-7x9+70", with_isolated(sheet(7, 9, seed=1)), 0
 
 
 PROBS = list(problems())
@@ -206,3 +225,31 @@ def test_medium_full_size_pattern_and_sampled_values(torch, B, oracle_mod):
     assert err.max() <= 1e-5
     np.testing.assert_allclose(b, A.b, rtol=0, atol=1e-10 * np.abs(A.b).max())
     np.testing.assert_allclose(diag, A.diag, rtol=1e-10)
+
+
+@pytest.mark.parametrize("dtype,rtol", [("f64", 1e-13), ("f32", 1e-6), ("bf16", 4e-3)])
+def test_isolated_rows_product_and_solve(torch, B, oracle_mod, dtype, rtol):
+    """Rows without off-diagonal blocks (vertices no element touches) have
+    nothing in the solver layout: the product is the mass term there, and
+    the solve matches the oracle's.  Whole slices without blocks included."""
+    c = with_isolated(sheet(7, 9, seed=1))
+    P = oracle_mod.Problem.from_cloth(c)
+    v = random_velocity(c, 0.05)
+    A = P.assemble(c.x0, v)
+    ctx = B.Context.from_cloth(c)
+    try:
+        b = ctx.cloth_assemble(to_dev(torch, c.x0), to_dev(torch, v), dtype)
+        rng = np.random.default_rng(5)
+        xin = rng.normal(size=c.rest.shape)
+        want = P.spmv(A, xin)
+        y = ctx.cloth_spmv(to_dev(torch, xin), solver_blocks=True).cpu().numpy()
+        assert np.linalg.norm(y - want) / np.linalg.norm(want) <= rtol
+        iso = slice(63, c.nv)
+        np.testing.assert_allclose(y[iso], c.mass[iso, None] * xin[iso], rtol=1e-15, atol=0)
+        dv, info = ctx.cloth_pcg_solve(b, tol=1e-8)
+        want_dv, oinfo = P.pcg(A, tol=1e-8)
+        assert oinfo["converged"] and info["rel_res_true"] <= 1e-8
+        assert np.linalg.norm(dv.cpu().numpy() - want_dv) <= 1e-6 * np.linalg.norm(want_dv)
+        assert P.residual(A, dv.cpu().numpy()) <= 1e-7
+    finally:
+        ctx.close()
