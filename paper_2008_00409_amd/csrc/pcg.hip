@@ -1052,7 +1052,16 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
     std::vector<int> iters(ninst, 0), sweeps(ninst, 0), fallback(ninst, 0), wused(ninst, 0);
     std::vector<uint8_t> active(ninst, 1);
     std::vector<double> res2(2 * ninst, 0.0);
-    std::vector<int> maxit_h(ninst, maxit);
+    // Refinement sweeps on the low-precision copy (inner reduction rho > 0)
+    // have an iteration budget: half of maxit for the first, three times the
+    // instance's longest earlier sweep (at least 256) for the others.  For
+    // some states the copy's rounding leaves CG on it diverging or stalled,
+    // which no per-iteration test sees while p.Ap stays positive; a sweep
+    // that reaches its budget ends like any other, and the contraction check
+    // below then moves the instance to the FP64 blocks.
+    const bool sweep_budget = rho > 0.0 && ctx->hi_valid;
+    std::vector<int> longest(ninst, 0);
+    std::vector<int> maxit_h(ninst, sweep_budget ? std::max(1, maxit / 2) : maxit);
     pc_status st;
 
     ctx->cg_par = 0;
@@ -1136,7 +1145,10 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
             ctx->prof.harvest();
         }
         for (int i = 0; i < ninst; ++i)
-            if (active[i]) iters[i] += ctx->st_host[i].iters;
+            if (active[i]) {
+                iters[i] += ctx->st_host[i].iters;
+                longest[i] = std::max(longest[i], ctx->st_host[i].iters);
+            }
         launch_fold(ctx, s);
         // true residual of every instance
         launch_residual(ctx, Mhi, S, g, nullptr, b, ctx->x, 1, ctx->res2, s);
@@ -1178,6 +1190,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
             if (again[i]) {
                 sweeps[i] += 1;
                 maxit_h[i] = maxit - iters[i];
+                if (sweep_budget && !inner_hi) maxit_h[i] = std::min(maxit_h[i], std::max(256, 3 * longest[i]));
             }
         }
         PC_HIP(hipMemcpyAsync(ctx->maxit_d, maxit_h.data(), sizeof(int) * ninst, hipMemcpyHostToDevice, s));
