@@ -64,8 +64,10 @@ typedef enum {
 typedef enum { PC_F64 = 0, PC_F32 = 1, PC_BF16 = 2 } pc_dtype;
 
 /* Device memory allocator of a context (pc_set_allocator): alloc returns
- * `bytes` of device memory on the current device (NULL on failure), free
- * releases a block that alloc returned.  `user` is passed through. */
+ * `bytes` of device memory on the current device, 256-byte aligned as
+ * hipMalloc's blocks are (NULL on failure; a misaligned block is returned to
+ * free and the call fails with PC_ERR_ARG), free releases a block that alloc
+ * returned.  `user` is passed through. */
 typedef void *(*pc_alloc_fn)(size_t bytes, void *user);
 typedef void (*pc_free_fn)(void *ptr, void *user);
 

@@ -38,6 +38,13 @@ pc_status dev_alloc(Ctx *ctx, void **p, size_t bytes) {
             ctx->err = "allocator returned NULL for " + std::to_string(bytes) + " bytes";
             return PC_ERR_OOM;
         }
+        if ((reinterpret_cast<uintptr_t>(q) & 255u) != 0) {
+            // kernels read every buffer with 16-byte vector loads and rely on
+            // the alignment hipMalloc gives
+            ctx->free_fn(q, ctx->alloc_user);
+            ctx->err = "allocator returned a block that is not 256-byte aligned";
+            return PC_ERR_ARG;
+        }
         ctx->blocks[q] = AllocRec{ctx->free_fn, ctx->alloc_user};
         *p = q;
         return PC_OK;

@@ -82,6 +82,34 @@ def test_set_allocator_rejects_half_a_pair(torch, B):
     assert st == B.PC_ERR_ARG
 
 
+def test_misaligned_allocator_is_refused(torch, B):
+    """Blocks must be 256-byte aligned (the kernels' 16-byte vector loads rely
+    on it): a block 16 bytes off is handed back and creation fails cleanly."""
+
+    class Misaligned(B.TorchAllocator):
+        def _alloc(self, nbytes, user):
+            ptr = super()._alloc(int(nbytes) + 256, user)
+            return None if ptr is None else ptr + 16
+
+        def _free(self, ptr, user):
+            super()._free(ptr - 16, user)
+
+    bad = Misaligned()
+    c = sheet(9, 8, seed=2)
+    with pytest.raises(B.PclothError, match="PC_ERR_ARG"):
+        B.Context.from_cloth(c, allocator=bad)
+    assert bad.n_alloc >= 1 and bad.n_free == bad.n_alloc and not bad.live
+    # a context created afterwards with torch's allocator works normally
+    ctx = B.Context.from_cloth(c)
+    try:
+        x = to_dev(torch, c.x0)
+        b = ctx.cloth_assemble(x, torch.zeros_like(x), "f32")
+        _, info = ctx.cloth_pcg_solve(b, tol=1e-6)
+        assert info["rel_res_true"] <= 1e-6
+    finally:
+        ctx.close()
+
+
 def test_failed_step_is_not_committed(torch, B):
     c = sheet(29, 23, seed=4, flips=0.1)
     ctx = B.Context.from_cloth(c)
