@@ -394,8 +394,12 @@ def main():
             ctx.cloth_step(x, v, nsteps=1, dtype=args.blocks, warm=args.warm, **kw)
             dv_prev = v - v_before
         pin = torch.from_numpy(cloth.pinned.astype(bool)).cuda()
-        paired = {m: {"iters": [], "sweeps": [], "start_used": []} for m in modes}
+        paired = {m: {"iters": [], "sweeps": [], "start_used": [], "a_err2": []} for m in modes}
         paired["missed"] = 0     # solves that ended above the tolerance (none expected)
+
+        def energy(s, b):
+            # 1/2 s.A s - b.s through the FP64 blocks
+            return 0.5 * float((s * ctx.cloth_spmv(s, solver_blocks=False)).sum()) - float((b * s).sum())
         t_rep = time.perf_counter()
         for k in range(args.steps):
             b = ctx.cloth_assemble(x, v, args.blocks)
@@ -410,6 +414,13 @@ def main():
                 paired[mode]["start_used"].append(pinfo["warm_used"])
                 if mode == args.warm:
                     keep = dv
+            # squared A-norm error of each start relative to the solution's:
+            # (E(s) - E(dv*)) / -E(dv*), 1 for the zero start
+            e_star = energy(keep, b)
+            for mode in modes:
+                s0 = (torch.zeros_like(x) if mode == "zero" else
+                      dv_prev if mode == "prev" else ctx.ws_start(x, v, b, dv_prev)[0])
+                paired[mode]["a_err2"].append((energy(s0, b) - e_star) / -e_star if e_star < 0 else None)
             v.add_(keep)
             v[pin] = 0.0
             x.add_(cloth.h * v)
@@ -417,6 +428,8 @@ def main():
         for m in modes:
             it = paired[m]["iters"]
             paired[m].update({"mean": float(np.mean(it)), "median": float(np.median(it)), "total": int(sum(it))})
+            ae = [e for e in paired[m]["a_err2"] if e is not None]
+            paired[m]["a_err2_mean"] = float(np.mean(ae)) if ae else None
         if "learned" in paired:
             paired["learned_over_prev_iters"] = paired["learned"]["total"] / paired["prev"]["total"]
             paired["learned_over_zero_iters"] = paired["learned"]["total"] / paired["zero"]["total"]
@@ -424,6 +437,8 @@ def main():
                 1 for a, b_ in zip(paired["learned"]["iters"], paired["prev"]["iters"]) if a < b_))
         paired["seconds"] = time.perf_counter() - t_rep
         log(f"# paired starts per step: " + ", ".join(f"{m} mean {paired[m]['mean']:.0f}" for m in modes))
+        log(f"# paired starts, squared A-norm error / solution's: "
+            + ", ".join(f"{m} {paired[m]['a_err2_mean']:.3g}" for m in modes if paired[m]["a_err2_mean"] is not None))
     spmv = prof.get("spmv", {})
     spmv_ms = spmv.get("median_ms", float("nan"))
     narrow = bool(ctx.get_option(binding.PC_OPT_SPMV_NARROW_ACTIVE))
