@@ -360,46 +360,106 @@ struct GradTile {
 __constant__ GradTile c_tiles[MLP_GRAD_TILES];
 
 // Split-K over vertex tiles: block b handles tiles [t0, t1) of the vertex
-// dimension; its 4 wavefronts share the output tiles round-robin.  Partial
-// tiles go to part[block][tile][16 x 16] (row-major).
-__global__ void __launch_bounds__(256) k_mlp_wgrad(int ntiles, const short *X, const short *H1, const short *H2,
+// dimension, 32 vertices (two tiles, the K of one 16 x 16 x 32 product) at a
+// time; its 4 wavefronts share the output tiles round-robin.  Registers are
+// capped for 3 waves per SIMD (the accumulators then live in VGPRs), and the
+// grid is three blocks per CU.  Partial tiles
+// go to part[block][tile][16 x 16] (row-major).
+//
+// A lane's K values are 8 vertices of one feature, 128 bytes apart in the
+// vertex-major activations, so each 32-vertex chunk of all eight arrays
+// (X, H1..H3, G1..G4: 27 KiB) is first copied to LDS with 16-byte loads, in
+// the same vertex-major order.  Every array gets rows of WG_P = 68 values
+// (64 + 4 padding, whatever its width): the 2-byte operand reads of the four
+// lane groups (rows 4 apart) then fall on distinct banks, and a read's offset
+// from its tile's base is a constant.  Vertices past the block's range are
+// staged as zeros.
+// Arrays k = 0..7: X (32 features), H1, H2, H3, G1, G2, G3 (64), G4 (16).
+constexpr int WG_V = 32, WG_P = 68;
+__host__ __device__ constexpr int wg_width(int k) { return k == 0 ? 32 : (k == 7 ? 16 : 64); }
+__host__ __device__ constexpr int wg_off(int k) { return k * WG_V * WG_P; }
+// first 16-byte unit of array k in a chunk
+__host__ __device__ constexpr int wg_units(int k) {
+    return k == 0 ? 0 : (k <= 7 ? WG_V * 32 / 8 + (k - 1) * WG_V * 64 / 8 : WG_V * (32 + 6 * 64 + 16) / 8);
+}
+constexpr int WG_LDS = wg_off(8);       // 17,408 values
+constexpr int WG_UNITS = wg_units(8);   // 1,728 16-byte units per chunk
+static_assert(wg_units(7) + WG_V * wg_width(7) / 8 == WG_UNITS, "unit count");
+static_assert(WG_P % 4 == 0, "LDS rows must stay 8-byte aligned");
+
+__global__ void __launch_bounds__(256, 3) k_mlp_wgrad(int ntiles, const short *X, const short *H1, const short *H2,
                                                    const short *H3, const short *G1, const short *G2,
                                                    const short *G3, const short *G4, float *part) {
+    __shared__ __align__(16) short L[WG_LDS];
     const int l = threadIdx.x & 63;
     const int w = threadIdx.x / 64;
     const int per = (ntiles + gridDim.x - 1) / gridDim.x;
     const int t0 = blockIdx.x * per, t1 = min(ntiles, t0 + per);
+    const short *const src[8] = {X, H1, H2, H3, G1, G2, G3, G4};
     constexpr int MAXT = (MLP_GRAD_TILES + 3) / 4;
     f32x4 acc[MAXT];
 #pragma unroll
     for (int q = 0; q < MAXT; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // two vertex tiles (32 vertices) per product; a missing second tile of
-    // the range contributes zeros
-    for (int t = t0; t < t1; t += 2) {
+    // this thread's 16-byte units of a chunk: unit u = threadIdx.x + 256 j
+    // lies in array j (threads 0..127) or j + 1 (threads 128..255) for
+    // j < 6; for j = 6 in G3 (0..127) or G4 (128..191).  The next chunk's
+    // units are loaded into registers while the current chunk's products run.
+    constexpr int UPT = (WG_UNITS + 255) / 256;
+    static_assert(UPT == 7 && WG_UNITS == 6 * 256 + 192, "unit split");
+    const bool hi = threadIdx.x >= 128;
+    const int uidx = hi ? (int)threadIdx.x - 128 : (int)threadIdx.x + 128;   // unit within its array (k >= 1)
+    uint4 pre[UPT];
+    auto load_chunk = [&](int t) {
         const int v0 = 16 * t;
-        const bool two = t + 1 < t1;
+        const int nvalid = min(WG_V, 16 * (t1 - t));
+#pragma unroll
+        for (int j = 0; j < UPT; ++j) {
+            const int k = hi ? j + 1 : j;
+            const int W = wg_width(k);
+            const int e = 8 * (k == 0 ? (int)threadIdx.x : uidx);
+            const short *p = hi ? src[j + 1] : src[j];
+            pre[j] = make_uint4(0u, 0u, 0u, 0u);
+            if ((j < 6 || threadIdx.x < 192) && e / W < nvalid)
+                pre[j] = *reinterpret_cast<const uint4 *>(p + (int64_t)v0 * W + e);
+        }
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int j = 0; j < UPT; ++j) {
+            if (j == 6 && threadIdx.x >= 192) continue;
+            const int k = hi ? j + 1 : j;
+            const int W = wg_width(k);
+            const int e = 8 * (k == 0 ? (int)threadIdx.x : uidx);
+            uint2 *dst = reinterpret_cast<uint2 *>(L + wg_off(k) + (e / W) * WG_P + e % W);
+            dst[0] = make_uint2(pre[j].x, pre[j].y);
+            dst[1] = make_uint2(pre[j].z, pre[j].w);
+        }
+    };
+    if (t0 < t1) load_chunk(t0);
+    for (int t = t0; t < t1; t += 2) {
+        store_chunk();
+        __syncthreads();
+        if (t + 2 < t1) load_chunk(t + 2);
 #pragma unroll
         for (int q = 0; q < MAXT; ++q) {
             const int tile = w + 4 * q;
             if (tile >= MLP_GRAD_TILES) continue;       // uniform per wavefront
             const GradTile T = c_tiles[tile];
-            const short *Hin = T.layer == 0 ? X : (T.layer == 1 ? H1 : (T.layer == 2 ? H2 : H3));
-            const int win = T.layer == 0 ? 32 : 64;
-            const short *Gout = T.layer == 0 ? G1 : (T.layer == 1 ? G2 : (T.layer == 2 ? G3 : G4));
-            const int wout = T.layer == 3 ? 16 : 64;
+            const int kin = T.layer, kout = 4 + T.layer;
+            const short *Lin = L + wg_off(kin) + 4 * (l / 16) * WG_P + 16 * T.mb + l % 16;
+            const short *Lout = L + wg_off(kout) + 4 * (l / 16) * WG_P + 16 * T.nb + l % 16;
             bf16x4 a[2], bb[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int vtx = v0 + 16 * h + 4 * (l / 16) + i;
-                    const bool in = h == 0 || two;
-                    a[h][i] = T.bias ? (short)((l % 16) == 0 && in ? 0x3F80 : 0)
-                                     : (in ? Hin[(int64_t)vtx * win + 16 * T.mb + l % 16] : (short)0);
-                    bb[h][i] = in ? Gout[(int64_t)vtx * wout + 16 * T.nb + l % 16] : (short)0;
+                    // vertex 16 h + 4 (l / 16) + i of the chunk
+                    a[h][i] = T.bias ? (short)((l % 16) == 0 ? 0x3F80 : 0) : Lin[(16 * h + i) * WG_P];
+                    bb[h][i] = Lout[(16 * h + i) * WG_P];
                 }
             acc[q] = mfma32(a[0], a[1], bb[0], bb[1], acc[q]);
         }
+        __syncthreads();
     }
 #pragma unroll
     for (int q = 0; q < MAXT; ++q) {
