@@ -9,7 +9,8 @@ resident in HBM.  Two configurations run on the same workload:
   plain   the paper's solver: FP32 blocks, FP64 vectors, Jacobi, zero start;
           timed again with the previous-step start, and the speedup is
           taken against the faster of the two
-  value   the project configuration: BF16 blocks with FP64 refinement sweeps,
+  value   the project configuration: FP16 blocks (a power-of-two scale per
+          instance and assembly) with FP64 refinement sweeps,
           block-Jacobi, learned warm start (the network trained offline on
           the 512 x 512 solver's trajectories, paper_2008_00409_amd/
           ws_params_512.npy, or online first when that file is absent);
@@ -23,7 +24,7 @@ same tolerance and reports the iterations per step (paired evaluation).
 Both use the autotuned launch schedule.  Prints one JSON line (stdout);
 progress goes to stderr.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--blocks f32|bf16|f64]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--blocks f32|bf16|f16|f64]
        [--precond jacobi|block] [--warm zero|prev|learned] [--workload large|medium|batch]
        [--no-plain] [--no-cpu-baseline]
 """
@@ -41,10 +42,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BLOCK_BYTES = {"f64": 72, "f32": 36, "bf16": 18}
-KERNEL_TB = {"f64": "double", "f32": "float", "bf16": "pc::bf16_t"}
+BLOCK_BYTES = {"f64": 72, "f32": 36, "bf16": 18, "f16": 18}
+KERNEL_TB = {"f64": "double", "f32": "float", "bf16": "pc::bf16_t", "f16": "pc::f16_t"}
 # committed counter summaries (profiles/) giving HBM bytes per launch
 TRAFFIC_FILES = {"k_pcg_spmv<pc::bf16_t, true, float>": "k_pcg_spmv_bf16_stacked-3x501x551_traffic.md",
+                 "k_pcg_spmv<pc::f16_t, true, float>": "k_pcg_spmv_f16_stacked-3x501x551_traffic.md",
                  "k_pcg_spmv<float, true, double>": "k_pcg_spmv_f32_stacked-3x501x551_traffic.md"}
 
 
@@ -54,7 +56,7 @@ def spmv_bytes(nv, nblk, blocks, col_bytes=4, q_bytes=24):
     diagonal blocks it leaves out because they are zero) and its column index
     (16-bit offsets when the SpMV runs with them, else 32-bit columns), the
     input vector once per row (float4), the output (FP64, or FP32 inside the
-    BF16 refinement sweeps), the FP64 mass, and the row pointers."""
+    BF16 and FP16 refinement sweeps), the FP64 mass, and the row pointers."""
     return nblk * (BLOCK_BYTES[blocks] + col_bytes) + nv * (16 + q_bytes + 8) + 4 * (nv + 1)
 
 
@@ -243,8 +245,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--blocks", default=None, choices=["f32", "bf16", "f64"],
-                    help="block storage of the project configuration (default: bf16; f32 for the batch)")
+    ap.add_argument("--blocks", default=None, choices=["f32", "bf16", "f16", "f64"],
+                    help="block storage of the project configuration (default: f16; f32 for the batch)")
     ap.add_argument("--warm", default="learned", choices=["zero", "prev", "learned"],
                     help="CG start of the project configuration")
     ap.add_argument("--precond", default="block", choices=["jacobi", "block"],
@@ -275,7 +277,7 @@ def main():
               f"and nothing is sharded (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
     if args.blocks is None:
-        args.blocks = "f32" if args.workload == "batch" else "bf16"
+        args.blocks = "f32" if args.workload == "batch" else "f16"
 
     import torch
 
@@ -442,7 +444,8 @@ def main():
     spmv = prof.get("spmv", {})
     spmv_ms = spmv.get("median_ms", float("nan"))
     narrow = bool(ctx.get_option(binding.PC_OPT_SPMV_NARROW_ACTIVE))
-    inner32 = args.blocks == "bf16" and args.method == "cg" and bool(ctx.get_option(binding.PC_OPT_INNER_FP32))
+    inner32 = (args.blocks in ("bf16", "f16") and args.method == "cg"
+               and bool(ctx.get_option(binding.PC_OPT_INNER_FP32)))
     kname = f"k_pcg_spmv<{KERNEL_TB[args.blocks]}, {'true' if narrow else 'false'}, {'float' if inner32 else 'double'}>"
     alg = spmv_bytes(nv, nblk, args.blocks, 2 if narrow else 4, 12 if inner32 else 24)
     ach = alg / (spmv_ms * 1e-3) / 1e9 if spmv_ms == spmv_ms and spmv_ms > 0 else None
@@ -460,7 +463,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         # arithmetic of the CG inner loop: FP32 row sums and inner vectors with
-        # BF16 blocks (textbook form), FP64 otherwise; dots, the refinement
+        # BF16 or FP16 blocks (textbook form), FP64 otherwise; dots, the refinement
         # residual and the state are FP64 in every case
         "dtype": "f32" if inner32 else "f64",
         "precision": (f"{args.blocks} blocks; " + ("FP32 SpMV row sums and inner vectors; " if inner32 else

@@ -57,11 +57,15 @@ typedef enum {
  * and sums every block in FP64 and then rounds to this type.  The state,
  * b, the dots of the CG recurrences and the refinement residual b - A dv
  * (through the FP64 copy of the blocks) stay FP64 for every type.  With FP32
- * or FP64 blocks the CG product accumulates in FP64.  With BF16 blocks the
- * CG product's row sums are FP32, and (PC_OPT_INNER_FP32, the default) each
- * refinement sweep keeps its correction, residual and product in FP32; the
- * sweep's start residual and the final convergence test are FP64. */
-typedef enum { PC_F64 = 0, PC_F32 = 1, PC_BF16 = 2 } pc_dtype;
+ * or FP64 blocks the CG product accumulates in FP64.  With BF16 or FP16
+ * blocks the CG product's row sums are FP32, and (PC_OPT_INNER_FP32, the
+ * default) each refinement sweep keeps its correction, residual and product
+ * in FP32; the sweep's start residual and the final convergence test are
+ * FP64.  FP16 blocks (IEEE binary16, 11 significant bits against BF16's 8)
+ * are stored multiplied by a power of two S chosen at each assembly so that
+ * the largest stored magnitude lies in [2^13, 2^14); the product divides S
+ * out of its row sums, and cloth_export_blocks returns the unscaled values. */
+typedef enum { PC_F64 = 0, PC_F32 = 1, PC_BF16 = 2, PC_F16 = 3 } pc_dtype;
 
 /* Device memory allocator of a context (pc_set_allocator): alloc returns
  * `bytes` of device memory on the current device, 256-byte aligned as
@@ -110,14 +114,14 @@ typedef struct {
 typedef struct {
     double tol;            /* stop when ||b - A dv||_2 <= tol * ||b||_2, A with FP64 blocks */
     double inner_rho;      /* each refinement sweep's CG stops once its residual has fallen by
-                              this factor (or reached tol); 0: default (BF16 blocks 1e-2,
-                              FP32/FP64 blocks: run each sweep to tol) */
+                              this factor (or reached tol); 0: default (BF16 and FP16
+                              blocks 1e-2, FP32/FP64 blocks: run each sweep to tol) */
     int32_t maxit;         /* total CG iterations over all sweeps; default 20000 when <= 0 */
     int32_t warm;          /* 0: zero start, 1: caller's dv as start, 2: learned start predicted
                               from the caller's dv taken as the previous step's increment
                               (needs pc_ws_set_params; see pc_ws_predict for the safeguard) */
     int32_t check_every;   /* iterations between host convergence checks (0: auto) */
-    int32_t max_sweeps;    /* refinement sweeps; 0: default (BF16 40, otherwise 4) */
+    int32_t max_sweeps;    /* refinement sweeps; 0: default (BF16 and FP16 40, otherwise 4) */
     int32_t precond;       /* 0: Jacobi, P = diag(A) (the paper's preconditioner, Sec. 2.5);
                               1: block Jacobi, P = the 3x3 diagonal blocks A_ii, inverted in
                               FP64 at assembly and applied in FP32 x FP64 */
@@ -209,10 +213,13 @@ pc_status cloth_assemble(pc_ctx *ctx, const double *x, const double *v, pc_dtype
  * residual b - A dv computed with the FP64 copy, and sweeps repeat (iterative
  * refinement) until that FP64 residual meets tol.  Dots accumulate in
  * FP64.  The product accumulates in FP64 for FP32 and FP64 blocks and in
- * FP32 for BF16 blocks (whose values carry 8 significant bits).  Vectors
- * are FP64 except the search direction (FP32) and, with BF16 blocks and
- * PC_OPT_INNER_FP32, the sweep's correction, residual and product (FP32;
- * x stays FP64).  The sweep's start residual and the final test use FP64
+ * FP32 for BF16 and FP16 blocks (whose values carry 8 and 11 significant
+ * bits).  Vectors are FP64 except the search direction (FP32) and, with BF16
+ * or FP16 blocks and PC_OPT_INNER_FP32, the sweep's correction, residual and
+ * product (FP32; x stays FP64).  A low-precision sweep runs at most half of
+ * maxit iterations if it is the first and three times the instance's longest
+ * earlier sweep (at least 256) otherwise; a sweep that does not halve the
+ * FP64 residual it started from moves the instance to the FP64 blocks.  The sweep's start residual and the final test use FP64
  * vectors and the FP64 blocks, so the returned dv meets tol through an FP64
  * matrix whatever the storage.
  * dv: device nv*3 doubles, the start when opts->warm = 1, the solution on
@@ -234,7 +241,7 @@ pc_status cloth_step(pc_ctx *ctx, double *x, double *v, int32_t nsteps, pc_dtype
                      const pc_solve_opts *opts, pc_solve_info *infos, void *stream);
 
 /* y = A x with the assembled matrix (difference form; FP64 accumulation,
- * FP32 row sums of the BF16 copy),
+ * FP32 row sums of a BF16 or FP16 copy),
  * using the FP64 blocks (solver_blocks = 0) or the solver copy in the
  * assembled dtype (solver_blocks = 1).  x, y: device nv*3 doubles. */
 pc_status cloth_spmv(pc_ctx *ctx, const double *x, double *y, int32_t solver_blocks, void *stream);
@@ -409,7 +416,7 @@ pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
  *   columns; 0: always 32-bit.  Results do not change.
  * PC_OPT_SPMV_NARROW_ACTIVE (read only, pc_get_option): 1 when the CG SpMV
  *   of the last solve read 16-bit column offsets, else 0.
- * PC_OPT_INNER_FP32: 1 (default): with BF16 blocks and the textbook
+ * PC_OPT_INNER_FP32: 1 (default): with BF16 or FP16 blocks and the textbook
  *   recurrences, each refinement sweep solves for a correction e (x += e at
  *   the sweep's end) with the correction, residual and product vectors in
  *   FP32 (dots still accumulate in FP64; the sweep's start residual and the

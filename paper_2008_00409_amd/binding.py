@@ -23,8 +23,8 @@ PC_OK, PC_ERR_ARG, PC_ERR_MESH, PC_ERR_HIP, PC_ERR_OOM, PC_ERR_NONFINITE, PC_ERR
     PC_ERR_CAPACITY = range(8)
 STATUS_NAMES = {0: "PC_OK", 1: "PC_ERR_ARG", 2: "PC_ERR_MESH", 3: "PC_ERR_HIP", 4: "PC_ERR_OOM",
                 5: "PC_ERR_NONFINITE", 6: "PC_ERR_NOT_CONVERGED", 7: "PC_ERR_CAPACITY"}
-PC_F64, PC_F32, PC_BF16 = 0, 1, 2
-DTYPES = {"f64": PC_F64, "f32": PC_F32, "bf16": PC_BF16}
+PC_F64, PC_F32, PC_BF16, PC_F16 = 0, 1, 2, 3
+DTYPES = {"f64": PC_F64, "f32": PC_F32, "bf16": PC_BF16, "f16": PC_F16}
 
 # Names of every entry point declared in include/pcloth.h.
 ABI_SYMBOLS = ["pc_create", "pc_destroy", "pc_set_params", "pc_last_error", "pc_sizes", "pc_get_hinges",

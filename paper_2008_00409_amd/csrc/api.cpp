@@ -111,7 +111,7 @@ static void free_all(Ctx *c) {
                     c->row_lane, c->slot_cnt, c->jval, c->diag, c->dinv, c->binv, c->zb, c->x, c->r, c->q, c->tmp, c->bbuf,
                     c->p, c->partials, c->partials_u, c->res2, c->counter, c->st, c->scan_tmp, c->jval_hi, c->slice_row0, c->slice_psize, c->slice_vbase, c->sitem_win, c->cverts, c->cw, c->cn, c->jdel, c->cg_pd, c->cg_s, c->e32, c->r32, c->q32,
                     c->row_slice, c->sitem, c->vitem, c->inst_sitem0, c->inst_vitem0, c->restart, c->maxit_d,
-                    c->slot_off, c->rowlen_s, c->row_state, c->wide_rows, c->trec, c->hrec, c->crec, c->row_npairs,
+                    c->slot_off, c->rowlen_s, c->f16_scale, c->f16_part, c->inst_slice0, c->row_state, c->wide_rows, c->trec, c->hrec, c->crec, c->row_npairs,
                     c->cols_tmp, c->pairs_tmp};
     for (void *p : ptrs) dev_free(c, p);
     if (c->st_host) (void)hipHostFree(c->st_host);
@@ -620,12 +620,18 @@ pc_status pc_get_hinges(pc_ctx *h, int32_t *hinges_host, double *coef_host) {
     return PC_OK;
 }
 
+static bool dtype_ok(Ctx *ctx, pc_dtype dtype) {
+    if (dtype == PC_F64 || dtype == PC_F32 || dtype == PC_BF16 || dtype == PC_F16) return true;
+    ctx->err = "bad dtype " + std::to_string((int)dtype);
+    return false;
+}
+
 pc_status cloth_assemble(pc_ctx *h, const double *x, const double *v, pc_dtype dtype, pc_bsr3 *A_out, double *b,
                          double *diag_out, void *stream) {
     if (!h) return PC_ERR_ARG;
     Ctx *ctx = &h->c;
     if (!x || !v || !b) { ctx->err = "cloth_assemble: x, v and b must be device pointers"; return PC_ERR_ARG; }
-    if (dtype != PC_F64 && dtype != PC_F32 && dtype != PC_BF16) { ctx->err = "bad dtype"; return PC_ERR_ARG; }
+    if (!dtype_ok(ctx, dtype)) return PC_ERR_ARG;
     pc_status st = assemble_run(ctx, x, v, dtype, b, diag_out, (hipStream_t)stream);
     if (st) return st;
     if (A_out) {
@@ -831,7 +837,7 @@ pc_status cloth_step(pc_ctx *h, double *x, double *v, int32_t nsteps, pc_dtype d
     if (!h) return PC_ERR_ARG;
     Ctx *ctx = &h->c;
     if (!x || !v || nsteps < 0) { ctx->err = "cloth_step: bad arguments"; return PC_ERR_ARG; }
-    if (!opts_ok(ctx, opts)) return PC_ERR_ARG;
+    if (!opts_ok(ctx, opts) || !dtype_ok(ctx, dtype)) return PC_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     pc_solve_opts o = opts ? *opts : pc_solve_opts{1e-6, 0.0, 20000, 0, 0, 0, 0, 0};
     // dv lives in ctx->tmp between steps (previous-step start when warm = 1)

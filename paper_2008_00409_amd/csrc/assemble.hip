@@ -1228,7 +1228,7 @@ template <typename TB>
 __global__ void __launch_bounds__(64) k_export(int nv, const int *rowptr, const int *colidx, const int *rowlen_s,
                                                const int *row_lane, const int *row_slice, const int *slice_vbase,
                                                const uint8_t *slot_cnt, const void *jval, const double *mass,
-                                               double *out, double *Dout) {
+                                               const double *vscale, double *out, double *Dout) {
     const int i = blockIdx.x;
     if (i >= nv) return;
     const int t = threadIdx.x;
@@ -1255,6 +1255,10 @@ __global__ void __launch_bounds__(64) k_export(int nv, const int *rowptr, const 
         const TB *val = (const TB *)jval + 9 * seg;
 #pragma unroll
         for (int q = 0; q < 9; ++q) blk[q] = to_f64(val[val_index<TB>(q, w_ss, lane)]);
+        if constexpr (BlockIO<TB>::SCALED) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) blk[q] *= vscale[2 * s + 1];
+        }
     } else {
 #pragma unroll
         for (int q = 0; q < 9; ++q) blk[q] = 0.0;
@@ -1277,6 +1281,91 @@ __global__ void __launch_bounds__(64) k_export(int nv, const int *rowptr, const 
     } else {
 #pragma unroll
         for (int q = 0; q < 9; ++q) o[q] = blk[q];
+    }
+}
+
+// ---------------------------------------------------------------- FP16 blocks
+// With FP16 storage the value pass writes the FP64 copy only.  The largest
+// magnitude over every stored block then fixes a power-of-two scale S with
+// max |S a| in [2^13, 2^14) (FP16's largest finite value is 65504, its
+// smallest normal 2^-14), and the FP16 copy holds S a rounded to nearest.
+// One wavefront per slice walks the slice's slots; lanes past a slot's row
+// count hold padding and are skipped.
+__global__ void __launch_bounds__(64) k_f16_absmax(int nslices, const int *slice_vbase, const uint8_t *slot_cnt,
+                                                   const int *slot_off, const double *hi, double *part) {
+    const int si = blockIdx.x;
+    if (si >= nslices) return;
+    const int lane = threadIdx.x;
+    const int my_cnt = (int)slot_cnt[si * WAVE + lane];
+    const int nslots = __popcll(__ballot(my_cnt > 0));
+    double m = 0.0;
+    for (int k = 0; k < nslots; ++k) {
+        const int c = __shfl(my_cnt, k, WAVE);
+        if (lane < c) {
+            const int64_t off = (int64_t)slice_vbase[si] + slot_off[si * WAVE + k];
+            double v[9];
+            BlockIO<double>::load(hi + 9 * off, slot_width(c), lane, v);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) m = fmax(m, fabs(v[q]));
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = fmax(m, __shfl_xor(m, d, WAVE));
+    if (lane == 0) part[si] = m;
+}
+
+// One workgroup per instance: S of the instance's slices [inst_slice0[i],
+// inst_slice0[i + 1]) from their maxima (S = 1 for all-zero or non-finite
+// blocks; the solver's own checks report the latter), written to each of
+// those slices as (S, 1 / S).  Instances are scaled apart, so an instance
+// solved in a batch gives the same bits as solved alone.
+__global__ void __launch_bounds__(1024) k_f16_scale(const int *inst_slice0, const double *part, double *scale) {
+    __shared__ double sh[16];
+    const int s0 = inst_slice0[blockIdx.x], s1 = inst_slice0[blockIdx.x + 1];
+    double m = 0.0;
+    for (int i = s0 + (int)threadIdx.x; i < s1; i += blockDim.x) m = fmax(m, part[i]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = fmax(m, __shfl_xor(m, d, WAVE));
+    if (lane_id() == 0) sh[threadIdx.x / WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / WAVE); ++w) m = fmax(m, sh[w]);
+        sh[0] = m;
+    }
+    __syncthreads();
+    m = sh[0];
+    double S = 1.0;
+    if (m > 0.0 && isfinite(m)) {
+        int e = 0;
+        (void)frexp(m, &e);                 // m < 2^e
+        e = max(-960, min(960, e));
+        S = ldexp(1.0, 14 - e);
+    }
+    for (int i = s0 + (int)threadIdx.x; i < s1; i += blockDim.x) {
+        scale[2 * i] = S;
+        scale[2 * i + 1] = 1.0 / S;
+    }
+}
+
+__global__ void __launch_bounds__(64) k_f16_store(int nslices, const int *slice_vbase, const uint8_t *slot_cnt,
+                                                  const int *slot_off, const double *hi, const double *scale,
+                                                  f16_t *out) {
+    const int si = blockIdx.x;
+    if (si >= nslices) return;
+    const int lane = threadIdx.x;
+    const int my_cnt = (int)slot_cnt[si * WAVE + lane];
+    const int nslots = __popcll(__ballot(my_cnt > 0));
+    const double S = scale[2 * si];
+    for (int k = 0; k < nslots; ++k) {
+        const int c = __shfl(my_cnt, k, WAVE);
+        if (lane < c) {
+            const int64_t off = (int64_t)slice_vbase[si] + slot_off[si * WAVE + k];
+            double v[9];
+            BlockIO<double>::load(hi + 9 * off, slot_width(c), lane, v);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) v[q] *= S;
+            BlockIO<f16_t>::store(out + 9 * off, slot_width(c), lane, v);
+        }
     }
 }
 
@@ -1337,6 +1426,15 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
             if ((st = dev_alloc(ctx, (void **)r.p, sizeof(double) * r.n))) return st;
             *r.have = r.n;
         }
+    if (dtype == PC_F16 && ctx->f16_cap < ctx->nslices) {
+        dev_free(ctx, ctx->f16_part);
+        dev_free(ctx, ctx->f16_scale);
+        ctx->f16_part = ctx->f16_scale = nullptr;
+        ctx->f16_cap = 0;
+        if ((st = dev_alloc(ctx, (void **)&ctx->f16_part, sizeof(double) * (size_t)ctx->nslices))) return st;
+        if ((st = dev_alloc(ctx, (void **)&ctx->f16_scale, sizeof(double) * 2 * (size_t)ctx->nslices))) return st;
+        ctx->f16_cap = ctx->nslices;
+    }
     if (!ctx->row_state) {
         if ((st = dev_alloc(ctx, (void **)&ctx->rowlen_s, sizeof(int) * (size_t)nv))) return st;
         if ((st = dev_alloc(ctx, (void **)&ctx->row_state, (size_t)nv))) return st;
@@ -1390,6 +1488,11 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
     a.nslices = ctx->nslices;
     a.cols_tmp = ctx->cols_tmp; a.pairs_tmp = ctx->pairs_tmp; a.row_npairs = ctx->row_npairs;
     a.jval_hi = dtype != PC_F64 ? ctx->jval_hi : nullptr;
+    if (dtype == PC_F16) {
+        // the value pass writes the FP64 copy; the FP16 copy is converted from it
+        a.jval = ctx->jval_hi;
+        a.jval_hi = nullptr;
+    }
     a.b = b; a.diag = diag_out ? diag_out : ctx->diag; a.dinv = ctx->dinv; a.binv = ctx->binv; a.status = ctx->status;
     // four rows per workgroup; a multiple of 8 workgroups for the XCD mapping
     const int ng = (((nv + RG_ROWS - 1) / RG_ROWS + 7) / 8) * 8;
@@ -1418,6 +1521,16 @@ pc_status assemble_run(Ctx *ctx, const double *x, const double *v, pc_dtype dtyp
             hipLaunchKernelGGL(k_row_values<bf16_t>, dim3(ng), dim3(64), 0, s, a);
             hipLaunchKernelGGL(k_row_values_wide<bf16_t>, dim3(nwide), dim3(64), 0, s, a);
             break;
+        case PC_F16:
+            hipLaunchKernelGGL(k_row_values<double>, dim3(ng), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(k_row_values_wide<double>, dim3(nwide), dim3(64), 0, s, a);
+            hipLaunchKernelGGL(k_f16_absmax, dim3(ctx->nslices), dim3(64), 0, s, ctx->nslices, ctx->slice_vbase,
+                               ctx->slot_cnt, ctx->slot_off, ctx->jval_hi, ctx->f16_part);
+            hipLaunchKernelGGL(k_f16_scale, dim3(ctx->ninst), dim3(1024), 0, s, ctx->inst_slice0, ctx->f16_part,
+                               ctx->f16_scale);
+            hipLaunchKernelGGL(k_f16_store, dim3(ctx->nslices), dim3(64), 0, s, ctx->nslices, ctx->slice_vbase,
+                               ctx->slot_cnt, ctx->slot_off, ctx->jval_hi, ctx->f16_scale, (f16_t *)ctx->jval);
+            break;
     }
     ctx->prof.end(slot, s);
     ctx->prof.end(slot_all, s);
@@ -1439,17 +1552,22 @@ pc_status export_blocks(Ctx *ctx, double *vals, double *D, bool solver, hipStrea
         case PC_F64:
             hipLaunchKernelGGL(k_export<double>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->colidx,
                                ctx->rowlen_s, ctx->row_lane, ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, src,
-                               ctx->mass, vals, D);
+                               ctx->mass, ctx->f16_scale, vals, D);
             break;
         case PC_F32:
             hipLaunchKernelGGL(k_export<float>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->colidx,
                                ctx->rowlen_s, ctx->row_lane, ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, src,
-                               ctx->mass, vals, D);
+                               ctx->mass, ctx->f16_scale, vals, D);
             break;
         case PC_BF16:
             hipLaunchKernelGGL(k_export<bf16_t>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->colidx,
                                ctx->rowlen_s, ctx->row_lane, ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, src,
-                               ctx->mass, vals, D);
+                               ctx->mass, ctx->f16_scale, vals, D);
+            break;
+        case PC_F16:
+            hipLaunchKernelGGL(k_export<f16_t>, dim3(ctx->nv), dim3(64), 0, s, ctx->nv, ctx->rowptr, ctx->colidx,
+                               ctx->rowlen_s, ctx->row_lane, ctx->row_slice, ctx->slice_vbase, ctx->slot_cnt, src,
+                               ctx->mass, ctx->f16_scale, vals, D);
             break;
     }
     PC_HIP(hipGetLastError());

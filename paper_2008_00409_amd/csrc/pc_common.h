@@ -104,8 +104,13 @@ __device__ __forceinline__ void bitonic_lds(K *keys) {
 }
 
 // Block value storage types.  bf16 is stored as the upper half of an fp32
-// (round to nearest even on the way in).
+// (round to nearest even on the way in).  f16 is IEEE binary16; f16 blocks
+// are stored multiplied by a power-of-two scale chosen at each assembly
+// (BlockIO<f16_t>::SCALED), which the SpMV divides out of its row sums.
 struct bf16_t {
+    uint16_t bits;
+};
+struct f16_t {
     uint16_t bits;
 };
 
@@ -114,6 +119,10 @@ __device__ __forceinline__ double to_f64(float v) { return (double)v; }
 __device__ __forceinline__ double to_f64(bf16_t v) {
     return (double)__uint_as_float(((unsigned)v.bits) << 16);
 }
+__device__ __forceinline__ float f16_to_f32(unsigned bits) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)bits);
+}
+__device__ __forceinline__ double to_f64(f16_t v) { return (double)f16_to_f32(v.bits); }
 
 template <typename T> __device__ __forceinline__ T from_f64(double v);
 template <> __device__ __forceinline__ double from_f64<double>(double v) { return v; }
@@ -128,6 +137,11 @@ template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double v) {
     }
     unsigned rounding = 0x7fffu + ((u >> 16) & 1u);
     return bf16_t{(uint16_t)((u + rounding) >> 16)};
+}
+// FP64 -> FP32 -> FP16, each step rounding to nearest even (values beyond
+// the FP16 range become infinities, which the scale choice rules out)
+template <> __device__ __forceinline__ f16_t from_f64<f16_t>(double v) {
+    return f16_t{__builtin_bit_cast(uint16_t, (_Float16)(float)v)};
 }
 
 // ---------------------------------------------------------------- solver block storage
@@ -155,6 +169,7 @@ template <typename TB> struct BlockIO;
 
 template <> struct BlockIO<float> {
     typedef float R;
+    static constexpr bool SCALED = false;
     __device__ __forceinline__ static void load(const float *seg, int w, int l, float v[9]) {
         const float4 a = reinterpret_cast<const float4 *>(seg)[l];
         const float4 b = reinterpret_cast<const float4 *>(seg + 4 * (int64_t)w)[l];
@@ -172,6 +187,7 @@ template <> struct BlockIO<float> {
 
 template <> struct BlockIO<bf16_t> {
     typedef float R;
+    static constexpr bool SCALED = false;
     __device__ __forceinline__ static void load(const bf16_t *seg, int w, int l, float v[9]) {
         const uint4 a = reinterpret_cast<const uint4 *>(seg)[l];
         v[0] = __uint_as_float(a.x << 16); v[1] = __uint_as_float(a.x & 0xffff0000u);
@@ -190,8 +206,31 @@ template <> struct BlockIO<bf16_t> {
     }
 };
 
+template <> struct BlockIO<f16_t> {
+    typedef float R;
+    static constexpr bool SCALED = true;
+    __device__ __forceinline__ static void load(const f16_t *seg, int w, int l, float v[9]) {
+        const uint4 a = reinterpret_cast<const uint4 *>(seg)[l];
+        v[0] = f16_to_f32(a.x & 0xffffu); v[1] = f16_to_f32(a.x >> 16);
+        v[2] = f16_to_f32(a.y & 0xffffu); v[3] = f16_to_f32(a.y >> 16);
+        v[4] = f16_to_f32(a.z & 0xffffu); v[5] = f16_to_f32(a.z >> 16);
+        v[6] = f16_to_f32(a.w & 0xffffu); v[7] = f16_to_f32(a.w >> 16);
+        v[8] = f16_to_f32(seg[8 * (int64_t)w + l].bits);
+    }
+    // b: values already multiplied by the scale
+    __device__ __forceinline__ static void store(f16_t *seg, int w, int l, const double b[9]) {
+        unsigned u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            u[q] = (unsigned)from_f64<f16_t>(b[2 * q]).bits | ((unsigned)from_f64<f16_t>(b[2 * q + 1]).bits << 16);
+        reinterpret_cast<uint4 *>(seg)[l] = make_uint4(u[0], u[1], u[2], u[3]);
+        seg[8 * (int64_t)w + l] = from_f64<f16_t>(b[8]);
+    }
+};
+
 template <> struct BlockIO<double> {
     typedef double R;
+    static constexpr bool SCALED = false;
     __device__ __forceinline__ static void load(const double *seg, int w, int l, double v[9]) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {

@@ -189,7 +189,14 @@ struct Ctx {
     uint8_t *slot_cnt = nullptr;  // nslices * 64
     int *slot_off = nullptr;      // nslices * 64: first stored block of each slot, from the slice's first
     uint8_t *row_state = nullptr; // nv: which assembly pass handles each row
-    int *rowlen_s = nullptr;      // nv: blocks of each row in the solver layout (a zero diagonal left out)
+    int *rowlen_s = nullptr;
+    // FP16 storage: per slice, f16_scale[2 s] = S of the slice's instance
+    // (its blocks are stored as S a) and f16_scale[2 s + 1] = 1 / S;
+    // f16_part: per-slice maxima of |a|
+    double *f16_scale = nullptr;
+    double *f16_part = nullptr;
+    int f16_cap = 0;                  // slices the two arrays can hold
+    int *inst_slice0 = nullptr;       // ninst + 1 instance slice ranges (device)      // nv: blocks of each row in the solver layout (a zero diagonal left out)
     int *wide_rows = nullptr;     // nv: rows of the wide-row passes
     int *row_npairs = nullptr;    // nv: (incidence, corner) pairs of each row
     int *cols_tmp = nullptr;      // 3 ninc + nv: each row's columns, pattern pass -> value pass

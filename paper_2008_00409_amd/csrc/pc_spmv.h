@@ -23,6 +23,9 @@ struct SpmvArgs {
     const int16_t *jdel;   // block columns as offsets from the slice's first row
     const void *jval;
     const double *mass;
+    // f16 blocks: per slice, the storage scale S of its instance and 1 / S
+    // (vscale[2 s], vscale[2 s + 1]); unused for the other types
+    const double *vscale;
 };
 
 // Tuning knobs of the SpMV row loop (compile time):
@@ -63,14 +66,15 @@ struct VecD3 {
     }
 };
 
-// Arithmetic type of the row sums: FP64, except for BF16 blocks applied to
-// the FP32 search direction, whose products and differences are taken in
-// FP32 (the stored values carry 8 significant bits; FP32 rounding adds about
-// 6e-8 of the row's terms, the blocks' own rounding 4e-3; differences of two
-// FP32 values within a factor 2 of each other are exact).  The mass term is
-// always FP64.
+// Arithmetic type of the row sums: FP64, except for BF16 and FP16 blocks
+// applied to the FP32 search direction, whose products and differences are
+// taken in FP32 (the stored values carry 8 or 11 significant bits; FP32
+// rounding adds about 6e-8 of the row's terms, the blocks' own rounding 4e-3
+// or 5e-4; differences of two FP32 values within a factor 2 of each other are
+// exact).  The mass term is always FP64.
 template <typename TB> struct SpmvAcc { typedef double T; };
 template <> struct SpmvAcc<bf16_t> { typedef float T; };
+template <> struct SpmvAcc<f16_t> { typedef float T; };
 
 // One row of the difference-form product for the lane's row of `slice`.
 // Lane k of the wavefront holds slot k's row count and start offset, so the
@@ -162,9 +166,14 @@ __device__ __forceinline__ int spmv_row(const SpmvArgs &M, int slice, int lane, 
 #endif
     if (row >= 0) {
         const double m = M.mass[row];
-        y[0] = (double)a0 + m * (double)x0;
-        y[1] = (double)a1 + m * (double)x1;
-        y[2] = (double)a2 + m * (double)x2;
+        double s0 = (double)a0, s1 = (double)a1, s2 = (double)a2;
+        if constexpr (BlockIO<TB>::SCALED) {
+            const double vi = M.vscale[2 * slice + 1];   // a power of two: exact
+            s0 *= vi; s1 *= vi; s2 *= vi;
+        }
+        y[0] = s0 + m * (double)x0;
+        y[1] = s1 + m * (double)x1;
+        y[2] = s2 + m * (double)x2;
     } else {
         y[0] = y[1] = y[2] = 0.0;
     }

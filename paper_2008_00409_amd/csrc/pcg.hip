@@ -628,6 +628,7 @@ static SpmvArgs spmv_args(Ctx *ctx, bool hi) {
     M.jdel = ctx->use_narrow ? ctx->jdel : nullptr;
     M.jval = (hi && ctx->hi_valid) ? (const void *)ctx->jval_hi : ctx->jval;
     M.mass = ctx->mass;
+    M.vscale = ctx->f16_scale;
     return M;
 }
 
@@ -660,10 +661,11 @@ pc_status build_schedule(Ctx *ctx) {
     const int ninst = (int)ctx->inst_row0_h.size() - 1;
     std::vector<int> slice_row0, row_slice(ctx->nv);
     std::vector<int4> sitems, vitems;
-    std::vector<int> isit(ninst + 1), ivit(ninst + 1);
+    std::vector<int> isit(ninst + 1), ivit(ninst + 1), islc(ninst + 1);
     for (int i = 0; i < ninst; ++i) {
         const int r0 = ctx->inst_row0_h[i], r1 = ctx->inst_row0_h[i + 1];
         const int s0 = (int)slice_row0.size();
+        islc[i] = s0;
         for (int r = r0; r < r1; r += WAVE) {
             for (int q = r; q < std::min(r + WAVE, r1); ++q) row_slice[q] = (int)slice_row0.size();
             slice_row0.push_back(r);
@@ -678,6 +680,7 @@ pc_status build_schedule(Ctx *ctx) {
     isit[ninst] = (int)sitems.size();
     ivit[ninst] = (int)vitems.size();
     const int nslices = (int)slice_row0.size() - 1;
+    islc[ninst] = nslices;
     pc_status st;
     auto realloc = [&](void **p, size_t bytes) -> pc_status {
         if (*p) dev_free(ctx, *p);
@@ -710,6 +713,7 @@ pc_status build_schedule(Ctx *ctx) {
     if ((st = realloc((void **)&ctx->vitem, sizeof(int4) * vitems.size()))) return st;
     if ((st = realloc((void **)&ctx->inst_sitem0, sizeof(int) * (ninst + 1)))) return st;
     if ((st = realloc((void **)&ctx->inst_vitem0, sizeof(int) * (ninst + 1)))) return st;
+    if ((st = realloc((void **)&ctx->inst_slice0, sizeof(int) * (ninst + 1)))) return st;
     const size_t nitems = std::max(sitems.size(), vitems.size()) + 16;
     if ((st = realloc((void **)&ctx->partials, sizeof(double) * 4 * nitems))) return st;
     if ((st = realloc((void **)&ctx->partials_u, sizeof(double) * 2 * nitems))) return st;
@@ -732,6 +736,7 @@ pc_status build_schedule(Ctx *ctx) {
     PC_HIP(hipMemcpy(ctx->vitem, vitems.data(), sizeof(int4) * vitems.size(), hipMemcpyHostToDevice));
     PC_HIP(hipMemcpy(ctx->inst_sitem0, isit.data(), sizeof(int) * isit.size(), hipMemcpyHostToDevice));
     PC_HIP(hipMemcpy(ctx->inst_vitem0, ivit.data(), sizeof(int) * ivit.size(), hipMemcpyHostToDevice));
+    PC_HIP(hipMemcpy(ctx->inst_slice0, islc.data(), sizeof(int) * islc.size(), hipMemcpyHostToDevice));
     ctx->nslices = nslices;
     ctx->ninst = ninst;
     ctx->n_sitems = (int)sitems.size();
@@ -916,10 +921,10 @@ static void launch_fold(Ctx *ctx, hipStream_t s) {
     hipLaunchKernelGGL(k_fold, dim3((n3 + 255) / 256), dim3(256), 0, s, n3, ctx->x, ctx->e32);
 }
 
-// FP32 inner vectors apply to BF16 blocks with the textbook recurrences
-// (the refinement sweeps only ask 1e-2 of each inner solve there).
+// FP32 inner vectors apply to BF16 and FP16 blocks with the textbook
+// recurrences (the refinement sweeps only ask 1e-2 of each inner solve there).
 pc_status set_inner_vectors(Ctx *ctx) {
-    ctx->inner32 = ctx->use_inner32 && ctx->dtype == PC_BF16 && ctx->method == 0;
+    ctx->inner32 = ctx->use_inner32 && (ctx->dtype == PC_BF16 || ctx->dtype == PC_F16) && ctx->method == 0;
     if (ctx->inner32 && !ctx->e32) {
         const size_t bytes = sizeof(float) * 3 * (size_t)ctx->nv;
         pc_status st;
@@ -931,8 +936,15 @@ pc_status set_inner_vectors(Ctx *ctx) {
     return PC_OK;
 }
 
-static bool graph_stale(const Ctx *ctx, int variant, const SpmvArgs &M, int elem_size) {
-    return !ctx->gexec[variant] || ctx->gkey[variant] != M.jval || ctx->gkey_dtype[variant] != elem_size ||
+// storage type of a block template, as its pc_dtype (graph keys)
+template <typename TB> constexpr int dtype_code();
+template <> constexpr int dtype_code<double>() { return PC_F64; }
+template <> constexpr int dtype_code<float>() { return PC_F32; }
+template <> constexpr int dtype_code<bf16_t>() { return PC_BF16; }
+template <> constexpr int dtype_code<f16_t>() { return PC_F16; }
+
+static bool graph_stale(const Ctx *ctx, int variant, const SpmvArgs &M, int code) {
+    return !ctx->gexec[variant] || ctx->gkey[variant] != M.jval || ctx->gkey_dtype[variant] != code ||
            ctx->gkey_chunk[variant] != ctx->graph_chunk || ctx->gkey_sched[variant] != ctx->sched_version ||
            ctx->gkey_pre[variant] != ctx->precond || ctx->gkey_win[variant] != ctx->win_cap ||
            ctx->gkey_narrow[variant] != (int)ctx->narrow || ctx->gkey_method[variant] != ctx->method ||
@@ -970,7 +982,7 @@ static pc_status capture_chunk(Ctx *ctx, const SpmvArgs &M, const Sched &S, cons
         return PC_ERR_HIP;
     }
     ctx->gkey[variant] = M.jval;
-    ctx->gkey_dtype[variant] = (int)sizeof(TB);
+    ctx->gkey_dtype[variant] = dtype_code<TB>();
     ctx->gkey_chunk[variant] = chunk;
     ctx->gkey_sched[variant] = ctx->sched_version;
     ctx->gkey_pre[variant] = ctx->precond;
@@ -998,6 +1010,9 @@ pc_status spmv_run(Ctx *ctx, const double *xin, double *y, bool solver, hipStrea
             break;
         case PC_BF16:
             hipLaunchKernelGGL(k_spmv_apply<bf16_t>, dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, xin, y);
+            break;
+        case PC_F16:
+            hipLaunchKernelGGL(k_spmv_apply<f16_t>, dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, xin, y);
             break;
     }
     PC_HIP(hipGetLastError());
@@ -1042,7 +1057,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
     const int maxit = (o && o->maxit > 0) ? o->maxit : 20000;
     int warm = o ? o->warm : 0;
     const int check = (o && o->check_every > 0) ? o->check_every : 0;
-    const bool lowp = ctx->dtype == PC_BF16;
+    const bool lowp = ctx->dtype == PC_BF16 || ctx->dtype == PC_F16;
     pc_status wst = ensure_windows(ctx, s);
     if (wst) return wst;
     const double rho = (o && o->inner_rho > 0.0) ? o->inner_rho : (lowp ? 1e-2 : 0.0);
@@ -1105,8 +1120,8 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
         const bool graph = ctx->graph_chunk > 0;
         if (graph) {
             const SpmvArgs &Mv = inner_hi ? Mhi : M;
-            const int want_size = inner_hi ? (int)sizeof(double) : (int)sizeof(TB);
-            if (graph_stale(ctx, variant, Mv, want_size)) {
+            const int want_code = inner_hi ? dtype_code<double>() : dtype_code<TB>();
+            if (graph_stale(ctx, variant, Mv, want_code)) {
                 st = inner_hi ? capture_chunk<double>(ctx, Mhi, S, g, ctx->graph_chunk, variant)
                               : capture_chunk<TB>(ctx, M, S, g, ctx->graph_chunk, variant);
                 if (st) return st;
@@ -1345,6 +1360,7 @@ pc_status autotune_run(Ctx *ctx, const double *b, int iters, int64_t *chosen, fl
                     case PC_F64: st = time_iters<double>(ctx, b, iters, &ms, s); break;
                     case PC_F32: st = time_iters<float>(ctx, b, iters, &ms, s); break;
                     case PC_BF16: st = time_iters<bf16_t>(ctx, b, iters, &ms, s); break;
+                    case PC_F16: st = time_iters<f16_t>(ctx, b, iters, &ms, s); break;
                 }
                 if (st) return st;
                 if (ms < best) {
@@ -1388,6 +1404,7 @@ pc_status pcg_run(Ctx *ctx, const double *b, double *dv, const pc_solve_opts *o,
         case PC_F64: return pcg_typed<double>(ctx, b, dv, o, info, s);
         case PC_F32: return pcg_typed<float>(ctx, b, dv, o, info, s);
         case PC_BF16: return pcg_typed<bf16_t>(ctx, b, dv, o, info, s);
+        case PC_F16: return pcg_typed<f16_t>(ctx, b, dv, o, info, s);
     }
     return PC_ERR_ARG;
 }

@@ -20,7 +20,7 @@ import time
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="large", choices=["large", "medium", "batch"])
-    ap.add_argument("--blocks", default="f32", choices=["f32", "bf16", "f64"])
+    ap.add_argument("--blocks", default="f32", choices=["f32", "bf16", "f16", "f64"])
     ap.add_argument("--iters", type=int, default=50, help="CG iterations (solve capped, tolerance unreachable)")
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "block"])
     ap.add_argument("--spb", type=int, default=0, help="slices per SpMV block (0: library default)")

@@ -39,7 +39,7 @@ def main(argv=None):
     ap.add_argument("--init", default=None, help="parameters to start from (.npy); default: seeded init")
     ap.add_argument("--out", required=True)
     ap.add_argument("--budget-s", type=float, default=0.0)
-    ap.add_argument("--blocks", default="bf16", choices=["f32", "bf16"])
+    ap.add_argument("--blocks", default="bf16", choices=["f32", "bf16", "f16"])
     a = ap.parse_args(argv)
 
     import torch

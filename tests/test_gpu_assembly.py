@@ -93,7 +93,7 @@ def test_hinges_and_pattern_bit_exact(torch, B, oracle_mod, name, c, _):
     np.testing.assert_array_equal(colidx, P.colidx)
 
 
-@pytest.mark.parametrize("dtype,rtol", [("f64", 1e-12), ("f32", 1e-5), ("bf16", 8e-3)])
+@pytest.mark.parametrize("dtype,rtol", [("f64", 1e-12), ("f32", 1e-5), ("bf16", 8e-3), ("f16", 2e-3)])
 @pytest.mark.parametrize("name,c,_", PROBS, ids=[p[0] for p in PROBS])
 def test_assembly_values(torch, B, oracle_mod, name, c, _, dtype, rtol):
     P, A, (rowptr, colidx, vals, D, b, diag, H, C) = compare(torch, B, oracle_mod, c, dtype, 0.05)
@@ -227,7 +227,7 @@ def test_medium_full_size_pattern_and_sampled_values(torch, B, oracle_mod):
     np.testing.assert_allclose(diag, A.diag, rtol=1e-10)
 
 
-@pytest.mark.parametrize("dtype,rtol", [("f64", 1e-13), ("f32", 1e-6), ("bf16", 4e-3)])
+@pytest.mark.parametrize("dtype,rtol", [("f64", 1e-13), ("f32", 1e-6), ("bf16", 4e-3), ("f16", 1e-3)])
 def test_isolated_rows_product_and_solve(torch, B, oracle_mod, dtype, rtol):
     """Rows without off-diagonal blocks (vertices no element touches) have
     nothing in the solver layout: the product is the mass term there, and
@@ -253,3 +253,38 @@ def test_isolated_rows_product_and_solve(torch, B, oracle_mod, dtype, rtol):
         assert P.residual(A, dv.cpu().numpy()) <= 1e-7
     finally:
         ctx.close()
+
+
+def test_f16_scale_follows_the_matrix(torch, B):
+    """FP16 blocks are stored times a power of two chosen at each assembly.
+    With masses and stiffnesses multiplied by 1e6 (entries far past FP16's
+    largest value, 65504) or by 1e-6 (entries in its subnormal range) the
+    stored blocks keep FP16's 11 significant bits, the system is the same up
+    to that factor, and the solve behaves as at factor 1."""
+    import dataclasses
+    c0 = sheet(30, 28, seed=8, flips=0.1)
+    v = random_velocity(c0, 0.05)
+    iters = {}
+    for factor in (1e-6, 1.0, 1e6):
+        c = dataclasses.replace(c0, mass=c0.mass * factor)
+        ctx = B.Context.from_cloth(c, mu=1000.0 * factor, lam=500.0 * factor, k_bend=1e-5 * factor)
+        try:
+            b = ctx.cloth_assemble(to_dev(torch, c.x0), to_dev(torch, v), "f16")
+            rowptr, colidx, vals, _ = ctx.cloth_export_blocks(solver_blocks=True)
+            _, _, hi, _ = ctx.cloth_export_blocks(solver_blocks=False)
+            rowptr, colidx = rowptr.cpu().numpy(), colidx.cpu().numpy()
+            vals, hi = vals.cpu().numpy().reshape(-1, 9), hi.cpu().numpy().reshape(-1, 9)
+            rows = np.repeat(np.arange(c.nv), np.diff(rowptr))
+            off = colidx != rows
+            big = np.abs(hi[off]).max()
+            assert big > 1e4 if factor > 1 else big < 1e-4 if factor < 1 else True, big
+            err = np.abs(vals[off] - hi[off])
+            # round to nearest in FP16 (via FP32) of S a with max |S a| in [2^13, 2^14)
+            bound = 1.001 * 2.0 ** -11 * np.abs(hi[off]) + 2.0 ** -37 * big
+            assert np.all(err <= bound), float((err / np.maximum(bound, 1e-300)).max())
+            dv, info = ctx.cloth_pcg_solve(b, tol=1e-6, precond="block")
+            assert info["rel_res_true"] <= 1e-6 and info["fallback"] == 0, info
+            iters[factor] = info["iters"]
+        finally:
+            ctx.close()
+    assert max(iters.values()) <= 1.1 * min(iters.values()), iters

@@ -36,7 +36,7 @@ def sub_cloth(c, k):
                     c.x0[v0:v1], c.v0[v0:v1], c.h, c.tol, 1, [(0, v1 - v0)], [(0, t1 - t0)])
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_batched_equals_solo_solves(torch, B, oracle_mod, dtype):
     c = batch()
     begins = [r[0] for r in c.sheet_ranges] + [c.nv]

@@ -75,7 +75,7 @@ def test_block_jacobi_fp64_matches_oracle_iterations(torch, B, oracle_mod):
         ctx.close()
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 def test_block_jacobi_residual_and_fewer_iterations(torch, B, oracle_mod, dtype):
     c = sheet(45, 41, seed=13, flips=0.1)
     P = oracle_mod.Problem.from_cloth(c)

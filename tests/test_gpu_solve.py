@@ -24,7 +24,7 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("dtype,rtol", [("f64", 1e-13), ("f32", 1e-6), ("bf16", 5e-2)])
+@pytest.mark.parametrize("dtype,rtol", [("f64", 1e-13), ("f32", 1e-6), ("bf16", 5e-2), ("f16", 1.5e-2)])
 def test_spmv_matches_oracle(torch, B, oracle_mod, dtype, rtol):
     c = sheet(33, 31, seed=11, flips=0.1)
     P = oracle_mod.Problem.from_cloth(c)
@@ -61,7 +61,7 @@ def solve_case(torch, B, oracle_mod, c, dtype, tol, v_scale=0.05):
         ctx.close()
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
 def test_solve_tiny_residual_through_oracle(torch, B, oracle_mod, dtype):
     """The refinement residual uses FP64 blocks, so for every storage type the
     solution meets the tolerance through the oracle's FP64 matrix."""
@@ -83,7 +83,7 @@ def test_solve_tiny_residual_through_oracle(torch, B, oracle_mod, dtype):
 @pytest.mark.parametrize("name,c", [("ragged-7x9", sheet(7, 9, seed=1)),
                                     ("flipped-40x37", sheet(40, 37, seed=3, flips=0.1)),
                                     ("grid-96", mg.config_grid(96, seed=21))])
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_solve_residual_through_oracle(torch, B, oracle_mod, name, c, dtype):
     P, A, dv, info = solve_case(torch, B, oracle_mod, c, dtype, 1e-6)
     res = P.residual(A, dv)
@@ -176,7 +176,7 @@ def test_solve_deterministic(torch, B):
         ctx.close()
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_graph_replay_matches_plain_launches(torch, B, dtype):
     """Iterations replayed from a captured HIP graph give the same iterate,
     bit for bit, as plain launches (same kernels, same order), on several

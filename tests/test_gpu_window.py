@@ -46,7 +46,8 @@ def solve(torch, B, c, v, window, dtype, precond, instances=None, narrow=1):
         ctx.close()
 
 
-@pytest.mark.parametrize("dtype,precond", [("f32", "jacobi"), ("bf16", "block"), ("f64", "block")])
+@pytest.mark.parametrize("dtype,precond", [("f32", "jacobi"), ("bf16", "block"), ("f64", "block"),
+                                           ("f16", "block")])
 def test_window_on_off_identical_grid_order(torch, B, dtype, precond):
     c = sheet(71, 53, seed=21, flips=0.1)       # 3763 rows, 59 slices
     v = random_velocity(c, 0.05, seed=2)
