@@ -246,7 +246,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--blocks", default=None, choices=["f32", "bf16", "f16", "f64"],
-                    help="block storage of the project configuration (default: f16; f32 for the batch)")
+                    help="block storage of the project configuration (default: f16)")
     ap.add_argument("--warm", default="learned", choices=["zero", "prev", "learned"],
                     help="CG start of the project configuration")
     ap.add_argument("--precond", default="block", choices=["jacobi", "block"],
@@ -277,7 +277,7 @@ def main():
               f"and nothing is sharded (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
     if args.blocks is None:
-        args.blocks = "f32" if args.workload == "batch" else "f16"
+        args.blocks = "f16"
 
     import torch
 
