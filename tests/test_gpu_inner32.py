@@ -118,3 +118,27 @@ def test_bf16_refinement_falls_back_when_not_contracting(torch, B):
     finally:
         ctx.close()
     assert fallbacks > 0
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_sweep_budget_ends_the_first_sweep_at_half_of_maxit(torch, B, dtype):
+    """A refinement sweep on the low-precision copy runs at most half of
+    maxit iterations if it is the first: with maxit = 40 (far too few for
+    the tolerance) the first sweep ends after 20 iterations, the FP64
+    residual is checked, and a second sweep (budget 20) uses the rest; the
+    solve reports 40 iterations in at least 2 sweeps and PC_ERR_NOT_CONVERGED.
+    Without the budget a single sweep would take all 40."""
+    c = sheet(40, 37, seed=3, flips=0.1)
+    v = random_velocity(c, 0.05, seed=2)
+    ctx = B.Context.from_cloth(c)
+    try:
+        b = ctx.cloth_assemble(to_dev(torch, c.x0), to_dev(torch, v), dtype)
+        _, info = ctx.cloth_pcg_solve(b, tol=1e-6, precond="block", maxit=40, raise_on_error=False)
+        assert info["status"] == B.PC_ERR_NOT_CONVERGED, info
+        assert info["iters"] == 40 and info["sweeps"] >= 2, info
+        # FP32 blocks run each sweep to the tolerance: no budget, one sweep
+        b = ctx.cloth_assemble(to_dev(torch, c.x0), to_dev(torch, v), "f32")
+        _, info = ctx.cloth_pcg_solve(b, tol=1e-6, precond="block", maxit=40, raise_on_error=False)
+        assert info["iters"] == 40 and info["sweeps"] == 1, info
+    finally:
+        ctx.close()
