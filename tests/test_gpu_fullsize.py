@@ -1,14 +1,17 @@
 """Parity at the benchmark's full size (three 501 x 551 sheets, 1.65M
-triangles, 828,153 rows) in the configuration the benchmark times (BF16
-solver blocks, block Jacobi, 16-bit columns, LDS windows, FP32 inner
-vectors, the schedule its autotuner picks), against the FP64 oracle's
-assembly of the same state:
+triangles, 828,153 rows) in the configuration the benchmark times (FP16
+solver blocks with per-instance power-of-two scales, block Jacobi, 16-bit
+columns, LDS windows, FP32 inner vectors, the schedule its autotuner picks),
+against the FP64 oracle's assembly of the same state:
 
 * the block pattern bit-exact (row pointers and columns of all rows);
 * the FP64 blocks, b and diag(A) on 20,000 sampled rows (1e-12 of the row
   scale, 1e-10 relative), and the FP32 solver copy of an FP32 assembly on
   the same rows to 1e-5 of the row scale (the project's bar for FP32 blocks;
   storage rounding is 6e-8 per block, the implicit diagonal sums about 13);
+* the FP16 solver copy's off-diagonal blocks on the same rows entry by
+  entry to FP16 rounding (2^-11 of the entry, plus 2^-36 of the largest
+  entry for FP16's subnormal range and the FP64 difference);
 * the solve meets the 1e-6 tolerance through the oracle's matrix, with the
   reported FP64 residual agreeing with the oracle's."""
 import numpy as np
@@ -61,7 +64,17 @@ def test_full_size_parity(torch, B, oracle_mod):
         del vals32
         # the benchmark's configuration
         diag = torch.empty_like(x_d)
-        b = ctx.cloth_assemble(x_d, v_d, "bf16", diag=diag)
+        b = ctx.cloth_assemble(x_d, v_d, "f16", diag=diag)
+        _rp, _ci, vals16, _D = ctx.cloth_export_blocks(with_D=False, solver_blocks=True)
+        v16 = vals16[torch.from_numpy(pos).cuda()].cpu().numpy().reshape(-1, 9)
+        del vals16
+        off = A.colidx[pos] != owner
+        ref = A.vals[pos].reshape(-1, 9)
+        big = np.abs(A.vals).max()
+        # (the second term also covers the 1e-12 of the row scale between the
+        # GPU's FP64 blocks and the oracle's)
+        bound = 1.001 * 2.0 ** -11 * np.abs(ref[off]) + 2.0 ** -36 * big
+        assert np.all(np.abs(v16[off] - ref[off]) <= bound)
         rowptr, colidx = ctx.pattern()
         np.testing.assert_array_equal(rowptr.cpu().numpy(), A.rowptr)
         np.testing.assert_array_equal(colidx.cpu().numpy(), A.colidx)
