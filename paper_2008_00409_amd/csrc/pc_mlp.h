@@ -7,7 +7,7 @@ namespace pc {
 constexpr int MLP_PARAMS = 27 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 * 3 + 3;  // 10,307
 constexpr int MLP_PADDED = 32 * 64 + 64 + 64 * 64 + 64 + 64 * 64 + 64 + 64 * 16 + 16;  // 11,472
 constexpr int MLP_GRAD_TILES = 57;
-constexpr int MLP_WGRAD_BLOCKS = 768;   // three per CU: one round at 3 waves per SIMD
+constexpr int MLP_WGRAD_BLOCKS = 768;   // three per CU, all resident at once at 3 waves per SIMD
 
 struct MlpState {
     bool ready = false, has_params = false;
