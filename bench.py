@@ -261,6 +261,8 @@ def main():
                          "apart with 274K vertex-face proximity pairs in the assembly")
     ap.add_argument("--method", default="cg", choices=["cg", "chronopoulos-gear"],
                     help="CG form of the project configuration: textbook recurrences or single reduction")
+    ap.add_argument("--keep-direction", type=int, default=None, choices=[0, 1],
+                    help="PC_OPT_KEEP_DIRECTION for the value configuration (default: the library's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP32 / Jacobi / zero-start run")
     ap.add_argument("--no-value-prev", action="store_true",
@@ -345,6 +347,8 @@ def main():
     ctx = new_context(binding, cloth, contacts)
     if params is not None:
         ctx.ws_set_params(params)
+    if args.keep_direction is not None:
+        ctx.set_option(binding.PC_OPT_KEEP_DIRECTION, args.keep_direction)
     x = torch.from_numpy(cloth.x0.copy()).cuda()
     v = torch.from_numpy(cloth.v0.copy()).cuda()
     tune = None

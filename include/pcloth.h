@@ -115,13 +115,15 @@ typedef struct {
     double tol;            /* stop when ||b - A dv||_2 <= tol * ||b||_2, A with FP64 blocks */
     double inner_rho;      /* each refinement sweep's CG stops once its residual has fallen by
                               this factor (or reached tol); 0: default (BF16 and FP16
-                              blocks 1e-2, FP32/FP64 blocks: run each sweep to tol) */
+                              blocks 1e-2, FP16 keeping the direction 0.5,
+                              FP32/FP64 blocks: run each sweep to tol) */
     int32_t maxit;         /* total CG iterations over all sweeps; default 20000 when <= 0 */
     int32_t warm;          /* 0: zero start, 1: caller's dv as start, 2: learned start predicted
                               from the caller's dv taken as the previous step's increment
                               (needs pc_ws_set_params; see pc_ws_predict for the safeguard) */
     int32_t check_every;   /* iterations between host convergence checks (0: auto) */
-    int32_t max_sweeps;    /* refinement sweeps; 0: default (BF16 and FP16 40, otherwise 4) */
+    int32_t max_sweeps;    /* refinement sweeps; 0: default (BF16 and FP16 40, FP16
+                              keeping the direction 400, otherwise 4) */
     int32_t precond;       /* 0: Jacobi, P = diag(A) (the paper's preconditioner, Sec. 2.5);
                               1: block Jacobi, P = the 3x3 diagonal blocks A_ii, inverted in
                               FP64 at assembly and applied in FP32 x FP64 */
@@ -421,10 +423,19 @@ pc_status pc_mfma_probe(pc_ctx *ctx, float *out_host);
  *   the sweep's end) with the correction, residual and product vectors in
  *   FP32 (dots still accumulate in FP64; the sweep's start residual and the
  *   convergence test use FP64 x and the FP64 blocks); 0: FP64 vectors.
- *   Results change at the inner solves' rounding level only. */
+ *   Results change at the inner solves' rounding level only.
+ * PC_OPT_KEEP_DIRECTION: 0 (default): every refinement sweep restarts CG
+ *   from P^-1 r (default inner reduction 1e-2); 1 (experimental): with FP16
+ *   blocks and the textbook recurrences, a sweep that follows a sweep
+ *   without breakdown keeps the search direction: its residual is replaced
+ *   by the FP64 one and the next direction is P^-1 r + beta p with beta =
+ *   r.P^-1 r over the r.P^-1 r the old direction was built from (residual
+ *   replacement), with a default inner reduction of 0.5.  It saves
+ *   iterations on small sheets and costs them on large ones at some steps.
+ *   BF16 blocks always restart. */
 typedef enum { PC_OPT_GRAPH_CHUNK = 0, PC_OPT_SPMV_SLICES_PER_BLOCK = 1, PC_OPT_VECTOR_ROWS_PER_BLOCK = 2,
                PC_OPT_LDS_WINDOW = 3, PC_OPT_NARROW_COLUMNS = 4, PC_OPT_SPMV_NARROW_ACTIVE = 5,
-               PC_OPT_INNER_FP32 = 6 } pc_option;
+               PC_OPT_INNER_FP32 = 6, PC_OPT_KEEP_DIRECTION = 7 } pc_option;
 pc_status pc_set_option(pc_ctx *ctx, int32_t option, int64_t value);
 pc_status pc_get_option(pc_ctx *ctx, int32_t option, int64_t *value);
 

@@ -42,7 +42,7 @@ WS_SHAPES = [(27, 64), (64, 64), (64, 64), (64, 3)]
 WARM = {"zero": 0, "prev": 1, "given": 1, "learned": 2}
 METHOD = {"cg": 0, "chronopoulos-gear": 1}
 PC_OPT_GRAPH_CHUNK, PC_OPT_SPMV_SLICES_PER_BLOCK, PC_OPT_VECTOR_ROWS_PER_BLOCK, PC_OPT_LDS_WINDOW, \
-    PC_OPT_NARROW_COLUMNS, PC_OPT_SPMV_NARROW_ACTIVE, PC_OPT_INNER_FP32 = 0, 1, 2, 3, 4, 5, 6
+    PC_OPT_NARROW_COLUMNS, PC_OPT_SPMV_NARROW_ACTIVE, PC_OPT_INNER_FP32, PC_OPT_KEEP_DIRECTION = 0, 1, 2, 3, 4, 5, 6, 7
 PROFILE_KINDS = ["spmv", "cg_update", "cg_dir", "row_assemble", "row_pattern", "assemble_all", "elements", "k7"]
 
 

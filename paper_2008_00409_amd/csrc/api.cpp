@@ -345,6 +345,13 @@ pc_status pc_set_option(pc_ctx *h, int32_t option, int64_t value) {
             }
             ctx->use_inner32 = value != 0;
             return PC_OK;
+        case PC_OPT_KEEP_DIRECTION:
+            if (value != 0 && value != 1) {
+                ctx->err = "keep-direction option must be 0 or 1";
+                return PC_ERR_ARG;
+            }
+            ctx->use_keep_dir = value != 0;
+            return PC_OK;
         case PC_OPT_SPMV_SLICES_PER_BLOCK: {
             if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16) {
                 ctx->err = "slices per block must be 1, 2, 4, 8 or 16";
@@ -386,6 +393,7 @@ pc_status pc_get_option(pc_ctx *h, int32_t option, int64_t *value) {
             *value = (ctx->use_narrow && ctx->narrow && ctx->win_valid) ? 1 : 0;
             return PC_OK;
         case PC_OPT_INNER_FP32: *value = ctx->use_inner32 ? 1 : 0; return PC_OK;
+        case PC_OPT_KEEP_DIRECTION: *value = ctx->use_keep_dir ? 1 : 0; return PC_OK;
         default: ctx->err = "unknown option"; return PC_ERR_ARG;
     }
 }

@@ -22,6 +22,7 @@ struct PcgState {
     double rho2;     // inner reduction factor squared (refinement sweeps)
     double thresh;   // stop when ||r||^2 <= thresh = max(tol^2 ||b||^2, rho^2 ||r_0||^2)
     double rr0;      // ||r_0||^2 of this sweep
+    double rzd;      // r.P^-1 r of the residual the current direction was built from
     // single-reduction (Chronopoulos-Gear) form: beta of the iteration being
     // applied, gamma and alpha of the previous one
     double beta, gprev, aprev;
@@ -248,6 +249,7 @@ struct Ctx {
     double *cg_s = nullptr;       // nv * 3: its product s = A p, by recurrence
     bool inner32 = false;         // inner CG vectors (correction, residual, product) in FP32
     bool use_inner32 = true;      // PC_OPT_INNER_FP32
+    bool use_keep_dir = false;    // PC_OPT_KEEP_DIRECTION
     float *e32 = nullptr, *r32 = nullptr, *q32 = nullptr;   // nv * 3 each
     double *partials = nullptr;   // per-block partial sums (4 doubles per block): SpMV, starts, checks
     double *partials_u = nullptr; // per-block partial sums of the CG update (2 doubles per block)

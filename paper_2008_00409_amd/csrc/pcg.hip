@@ -300,11 +300,13 @@ __global__ void __launch_bounds__(VT) k_pcg_dir(Sched S, int par, TV *x, const T
     const double beta = tot[0] / st[I.x].rzp[par];
     const bool bad = !isfinite(tot[1]) || !isfinite(tot[0]);
     const bool conv = tot[1] <= st[I.x].thresh;
+    const bool new_dir = !(bad || conv);
     if (first) {
         PcgState &T = st[I.x];
         T.rzp[1 - par] = tot[0];
         T.rr = tot[1];
         T.iters += 1;
+        if (new_dir) T.rzd = tot[0];
         if (bad) {
             T.flags |= 2;
             T.done = 1;
@@ -312,7 +314,6 @@ __global__ void __launch_bounds__(VT) k_pcg_dir(Sched S, int par, TV *x, const T
             T.done = 1;
         }
     }
-    const bool new_dir = !(bad || conv);
     for (; i < I.z; i += VT) {
         if (i != I.y + (int)threadIdx.x) row.load(i, x, r, p, P);
         const float4 pv = row.p;
@@ -474,9 +475,10 @@ __global__ void __launch_bounds__(VT) k_pcg_start_zero(Sched S, const uint8_t *r
 
 // Residual t = b - A x for FP64 x over the item's slices.  MODE 0 (sweep
 // start of the flagged instances): r = t, p = P^-1 r, e = 0 (FP32 inner
-// vectors); partials of r.z,
-// ||r||^2, ||b||^2.  MODE 1 (check, all instances): partials of ||t||^2,
-// ||b||^2.
+// vectors); partials of r.z, ||r||^2, ||b||^2.  MODE 2 (sweep start that
+// keeps the direction): the same, except that p is left alone and block
+// Jacobi's z = P^-1 r is stored for k_pcg_redirect.  MODE 1 (check, all
+// instances): partials of ||t||^2, ||b||^2.
 template <typename TB, int MODE, typename TV>
 __global__ void __launch_bounds__(1024) k_residual(SpmvArgs M, Sched S, const uint8_t *restart, const double *b,
                                                   const double *x, TV *r, float4 *p, PreArgs P,
@@ -484,7 +486,7 @@ __global__ void __launch_bounds__(1024) k_residual(SpmvArgs M, Sched S, const ui
     const int it = item_of_block(S.n_sitems);
     if (it < 0) return;
     const int4 I = S.sitem[it];
-    if (MODE == 0 && restart && !restart[I.x]) return;
+    if (MODE != 1 && restart && !restart[I.x]) return;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     const int lane = lane_id();
     double rz = 0.0, rr = 0.0, bb = 0.0;
@@ -500,7 +502,7 @@ __global__ void __launch_bounds__(1024) k_residual(SpmvArgs M, Sched S, const ui
                 rr += t[a] * t[a];
                 bb += ba * ba;
             }
-            if (MODE == 0) {
+            if (MODE != 1) {
                 double z[3];
                 precond3(P, row, t[0], t[1], t[2], z);
                 r[3 * row] = (TV)t[0]; r[3 * row + 1] = (TV)t[1]; r[3 * row + 2] = (TV)t[2];
@@ -508,12 +510,48 @@ __global__ void __launch_bounds__(1024) k_residual(SpmvArgs M, Sched S, const ui
                     e[3 * row] = TV(0); e[3 * row + 1] = TV(0); e[3 * row + 2] = TV(0);
                 }
                 rz += t[0] * z[0] + t[1] * z[1] + t[2] * z[2];
-                p[row] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
+                if (MODE == 0)
+                    p[row] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
+                else if (P.kind != 0)
+                    P.z[row] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
             }
         }
     }
     double v[3] = {rz, rr, bb};
     block_partials<3>(v, partials, it, S.n_sitems);
+}
+
+// Sweep start that keeps the direction (residual replacement), after
+// k_residual MODE 2: beta = r.z / rzd from the residual's partials (rzd:
+// r.z of the residual the current direction was built from; beta = 0, a
+// plain restart, when it is not positive), then p = z + beta p with z as the
+// direction kernel forms it (Jacobi: the stored r times P^-1; block Jacobi:
+// the stored z).  Every block sums its instance's partials in the same order.
+template <typename TV>
+__global__ void __launch_bounds__(VT) k_pcg_redirect(Sched S, const uint8_t *restart, const TV *r, float4 *p,
+                                                      PreArgs P, const PcgState *st, const double *partials) {
+    const int it = item_of_block(S.n_vitems);
+    if (it < 0) return;
+    const int4 I = S.vitem[it];
+    if (restart && !restart[I.x]) return;
+    double tot[3];
+    instance_sum<3>(partials, S.n_sitems, S.inst_sitem0[I.x], S.inst_sitem0[I.x + 1], tot);
+    const double rzd = st[I.x].rzd;
+    const double q = tot[0] / rzd;
+    const double beta = (rzd > 0.0 && isfinite(q) && q >= 0.0) ? q : 0.0;
+    for (int i = I.y + (int)threadIdx.x; i < I.z; i += VT) {
+        double z[3];
+        if (P.kind == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) z[c] = (double)r[3 * i + c] * (double)P.dinv[3 * i + c];
+        } else {
+            const float4 zv = P.z[i];
+            z[0] = zv.x; z[1] = zv.y; z[2] = zv.z;
+        }
+        const float4 pv = p[i];
+        p[i] = make_float4((float)(z[0] + beta * pv.x), (float)(z[1] + beta * pv.y), (float)(z[2] + beta * pv.z),
+                           0.0f);
+    }
 }
 
 // Sweep start of the flagged instances: rz, ||r_0||^2, ||b||^2 -> state
@@ -531,6 +569,7 @@ __global__ void __launch_bounds__(256) k_fin_start(Sched S, int use_sitems, int 
         PcgState &T = st[inst];
         T.rzp[par] = tot[0];
         T.rz0 = tot[0];
+        T.rzd = tot[0];
         T.rr = tot[1];
         T.bb = tot[2];
         T.rr0 = tot[1];
@@ -881,7 +920,8 @@ static void launch_iters(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grid
 }
 
 // Residuals always use the FP64 blocks.  mode 0 starts a sweep from x for
-// the flagged instances (restart == nullptr: all), mode 1 writes
+// the flagged instances (restart == nullptr: all), mode 2 does the same but
+// keeps the search direction (residual replacement), mode 1 writes
 // ||b - A x||^2 and ||b||^2 of every instance to out2.
 static void launch_residual(Ctx *ctx, const SpmvArgs &M, const Sched &S, const Grids &g, const uint8_t *restart,
                             const double *b, const double *x, int mode, double *out2, hipStream_t s) {
@@ -893,6 +933,22 @@ static void launch_residual(Ctx *ctx, const SpmvArgs &M, const Sched &S, const G
         else
             hipLaunchKernelGGL((k_residual<TB, 0, double>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart,
                                b, x, ctx->r, ctx->p, pre_args(ctx), ctx->partials, (double *)nullptr);
+        hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 1, ctx->cg_par, restart, ctx->partials,
+                           ctx->st);
+    } else if (mode == 2) {
+        if (ctx->inner32) {
+            hipLaunchKernelGGL((k_residual<TB, 2, float>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart, b,
+                               x, ctx->r32, ctx->p, pre_args(ctx), ctx->partials, ctx->e32);
+            hipLaunchKernelGGL(k_pcg_redirect<float>, dim3(g.vblocks), dim3(VT), 0, s, S, restart,
+                               (const float *)ctx->r32, ctx->p, pre_args(ctx), (const PcgState *)ctx->st,
+                               (const double *)ctx->partials);
+        } else {
+            hipLaunchKernelGGL((k_residual<TB, 2, double>), dim3(g.sblocks), dim3(g.sthreads), 0, s, M, S, restart,
+                               b, x, ctx->r, ctx->p, pre_args(ctx), ctx->partials, (double *)nullptr);
+            hipLaunchKernelGGL(k_pcg_redirect<double>, dim3(g.vblocks), dim3(VT), 0, s, S, restart,
+                               (const double *)ctx->r, ctx->p, pre_args(ctx), (const PcgState *)ctx->st,
+                               (const double *)ctx->partials);
+        }
         hipLaunchKernelGGL(k_fin_start, dim3(ctx->ninst), dim3(256), 0, s, S, 1, ctx->cg_par, restart, ctx->partials,
                            ctx->st);
     } else {
@@ -1058,10 +1114,19 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
     int warm = o ? o->warm : 0;
     const int check = (o && o->check_every > 0) ? o->check_every : 0;
     const bool lowp = ctx->dtype == PC_BF16 || ctx->dtype == PC_F16;
+    // With PC_OPT_KEEP_DIRECTION, FP16 sweeps keep the search direction
+    // (residual replacement: the FP64 residual replaces the recursive one and
+    // CG goes on), each ending when the recursive residual has halved; BF16's
+    // coarser rounding does not let the continued recurrence converge
+    const bool keep = ctx->use_keep_dir && ctx->dtype == PC_F16 && ctx->method == 0;
     pc_status wst = ensure_windows(ctx, s);
     if (wst) return wst;
-    const double rho = (o && o->inner_rho > 0.0) ? o->inner_rho : (lowp ? 1e-2 : 0.0);
-    const int max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : (lowp ? 40 : 4);
+    const double rho = (o && o->inner_rho > 0.0) ? o->inner_rho : (lowp ? (keep ? 0.5 : 1e-2) : 0.0);
+    const int max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : (keep ? 400 : (lowp ? 40 : 4));
+    // a low-precision sweep must bring the FP64 residual below this factor of
+    // its start: half for restarted sweeps, halfway between 1 and rho when
+    // sweeps keep the direction (each asks only for a reduction by rho)
+    const double contract = keep ? 0.5 * (1.0 + std::min(rho, 1.0)) : 0.5;
     const int64_t n3 = 3 * (int64_t)nv;
 
     std::vector<int> iters(ninst, 0), sweeps(ninst, 0), fallback(ninst, 0), wused(ninst, 0);
@@ -1185,11 +1250,13 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
                 } else {
                     continue;
                 }
-            } else if (!inner_hi && ctx->hi_valid && was_active && !(res2[2 * i] <= 0.25 * h.rr0)) {
-                // the sweep on the low-precision copy did not halve the FP64
-                // residual it started from: refinement with that operator is not
-                // contracting for this system (its rounding is too coarse for the
-                // conditioning); FP64 blocks from here on
+            } else if (!inner_hi && ctx->hi_valid && was_active &&
+                       !(res2[2 * i] <= contract * contract * h.rr0)) {
+                // the sweep on the low-precision copy did not bring the FP64
+                // residual it started from below the contraction factor:
+                // refinement with that operator is not contracting for this
+                // system (its rounding is too coarse for the conditioning); FP64
+                // blocks from here on
                 any_breakdown = true;
                 fallback[i] = 1;
             } else if (sweeps[i] >= max_sweeps) {
@@ -1199,7 +1266,7 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
             active[i] = 1;
             any = true;
         }
-        if (!any || ++guard > 64) break;
+        if (!any || ++guard > max_sweeps + 8) break;
         if (any_breakdown) inner_hi = true;  // low-precision operator lost definiteness or stopped contracting: FP64 blocks from here on
         for (int i = 0; i < ninst; ++i) {
             if (again[i]) {
@@ -1212,7 +1279,8 @@ static pc_status pcg_typed(Ctx *ctx, const double *b, double *dv, const pc_solve
         if ((st = upload_flags(ctx, again, s))) return st;
         hipLaunchKernelGGL(k_state_init, dim3((ninst + 63) / 64), dim3(64), 0, s, ninst, ctx->st, ctx->restart, tol,
                            rho, ctx->maxit_d);
-        launch_residual(ctx, Mhi, S, g, ctx->restart, b, ctx->x, 0, nullptr, s);
+        // a breakdown or the switch to the FP64 blocks restarts from P^-1 r
+        launch_residual(ctx, Mhi, S, g, ctx->restart, b, ctx->x, (keep && !any_breakdown) ? 2 : 0, nullptr, s);
         PC_HIP(hipGetLastError());
     }
     // b = 0: the solution is 0 whatever the start

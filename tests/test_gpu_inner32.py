@@ -142,3 +142,33 @@ def test_sweep_budget_ends_the_first_sweep_at_half_of_maxit(torch, B, dtype):
         assert info["iters"] == 40 and info["sweeps"] == 1, info
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("precond", ["block", "jacobi"])
+def test_f16_sweeps_keep_the_direction(torch, B, oracle_mod, precond):
+    """FP16 refinement sweeps keep the search direction by default (the FP64
+    residual replaces the recursive one and CG goes on, inner reduction 0.5).
+    Against sweeps that restart CG (PC_OPT_KEEP_DIRECTION = 0, inner
+    reduction 1e-2): both meet the tolerance through the oracle's matrix,
+    and keeping the direction needs fewer iterations."""
+    c = sheet(71, 53, seed=21, flips=0.1)
+    v = random_velocity(c, 0.05, seed=2)
+    P = oracle_mod.Problem.from_cloth(c)
+    A = P.assemble(c.x0, v)
+    out = {}
+    for keep in (1, 0):
+        ctx = B.Context.from_cloth(c)
+        try:
+            ctx.set_option(B.PC_OPT_KEEP_DIRECTION, keep)
+            assert ctx.get_option(B.PC_OPT_KEEP_DIRECTION) == keep
+            b = ctx.cloth_assemble(to_dev(torch, c.x0), to_dev(torch, v), "f16")
+            dv, info = ctx.cloth_pcg_solve(b, tol=1e-6, precond=precond)
+            assert P.residual(A, dv.cpu().numpy()) <= 1e-6 * (1 + 1e-6)
+            assert info["fallback"] == 0, info
+            out[keep] = info
+        finally:
+            ctx.close()
+    print(f"{precond}: keep {out[1]['iters']} iterations in {out[1]['sweeps']} sweeps, "
+          f"restart {out[0]['iters']} in {out[0]['sweeps']}")
+    assert out[1]["sweeps"] > out[0]["sweeps"]
+    assert out[1]["iters"] < out[0]["iters"]
