@@ -1357,7 +1357,7 @@ static pc_status time_iters(Ctx *ctx, const double *b, int iters, float *ms, hip
     if (wst) return wst;
     ctx->cg_par = 0;
     launch_start_zero(ctx, S, g, nullptr, b, s);
-    if (ctx->graph_chunk > 0 && graph_stale(ctx, 0, M, (int)sizeof(TB))) {
+    if (ctx->graph_chunk > 0 && graph_stale(ctx, 0, M, dtype_code<TB>())) {
         pc_status st = capture_chunk<TB>(ctx, M, S, g, ctx->graph_chunk, 0);
         if (st) return st;
     }

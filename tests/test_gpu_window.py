@@ -79,7 +79,7 @@ def test_window_batched_instances(torch, B):
     assert np.array_equal(d1.view(np.uint64), d0.view(np.uint64))
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 def test_narrow_columns_identical(torch, B, dtype):
     c = sheet(71, 53, seed=21, flips=0.1)
     v = random_velocity(c, 0.05, seed=2)
