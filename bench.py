@@ -55,9 +55,10 @@ def spmv_bytes(nv, nblk, blocks, col_bytes=4, q_bytes=24):
     block the solver layout stores (nblk: the pattern's blocks less the
     diagonal blocks it leaves out because they are zero) and its column index
     (16-bit offsets when the SpMV runs with them, else 32-bit columns), the
-    input vector once per row (float4), the output (FP64, or FP32 inside the
-    BF16 and FP16 refinement sweeps), the FP64 mass, and the row pointers."""
-    return nblk * (BLOCK_BYTES[blocks] + col_bytes) + nv * (16 + q_bytes + 8) + 4 * (nv + 1)
+    input vector once per row (three packed FP32), the output (FP64, or FP32
+    inside the BF16 and FP16 refinement sweeps), the FP64 mass, and the row
+    pointers."""
+    return nblk * (BLOCK_BYTES[blocks] + col_bytes) + nv * (12 + q_bytes + 8) + 4 * (nv + 1)
 
 
 def solver_blocks(rowptr, colidx, pinned):

@@ -239,12 +239,12 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
     ALLOC(ctx->diag, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->dinv, sizeof(float) * 3 * (size_t)nv);
     ALLOC(ctx->binv, sizeof(float) * 6 * (size_t)nv);
-    ALLOC(ctx->zb, sizeof(float4) * (size_t)nv);
+    ALLOC(ctx->zb, sizeof(float) * 3 * (size_t)nv);
     ALLOC(ctx->x, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->r, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->q, sizeof(double) * 3 * (size_t)nv);
     ALLOC(ctx->bbuf, sizeof(double) * 3 * (size_t)nv);
-    ALLOC(ctx->p, sizeof(float4) * (size_t)nv);
+    ALLOC(ctx->p, sizeof(float) * 3 * (size_t)nv);
     ALLOC(ctx->counter, sizeof(unsigned) * 4);
 #undef ALLOC
     (void)nsl;
@@ -258,7 +258,7 @@ pc_status pc_create(const pc_mesh *mesh, const pc_params *params, pc_ctx **out) 
     if ((st = mlp_scratch_init(ctx))) return fail(st);
     if (hipMemset(ctx->counter, 0, sizeof(unsigned) * 4) != hipSuccess ||
         hipMemset(ctx->tmp, 0, sizeof(double) * 3 * (size_t)nv) != hipSuccess ||
-        hipMemset(ctx->p, 0, sizeof(float4) * (size_t)nv) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        hipMemset(ctx->p, 0, sizeof(float) * 3 * (size_t)nv) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         ctx->err = "initialisation failed";
         return fail(PC_ERR_HIP);
     }

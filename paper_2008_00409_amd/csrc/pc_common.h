@@ -103,6 +103,18 @@ __device__ __forceinline__ void bitonic_lds(K *keys) {
     }
 }
 
+// Vectors of three FP32 per row stored packed, 12 B per row (the CG search
+// direction and the stored preconditioned residual): row i at 3 i.  The
+// three loads or stores of a row merge into one 12-byte access.
+__device__ __forceinline__ float4 ld3(const float *v, int64_t i) {
+    return make_float4(v[3 * i], v[3 * i + 1], v[3 * i + 2], 0.0f);
+}
+__device__ __forceinline__ void st3(float *v, int64_t i, float a, float b, float c) {
+    v[3 * i] = a;
+    v[3 * i + 1] = b;
+    v[3 * i + 2] = c;
+}
+
 // Block value storage types.  bf16 is stored as the upper half of an fp32
 // (round to nearest even on the way in).  f16 is IEEE binary16; f16 blocks
 // are stored multiplied by a power-of-two scale chosen at each assembly

@@ -241,8 +241,8 @@ struct Ctx {
 
     // solver vectors
     double *x = nullptr, *r = nullptr, *q = nullptr, *tmp = nullptr, *bbuf = nullptr;
-    float4 *p = nullptr;
-    float4 *zb = nullptr;         // preconditioned residual (block Jacobi)
+    float *p = nullptr;           // nv * 3: search direction (FP32, packed)
+    float *zb = nullptr;          // nv * 3: preconditioned residual (block Jacobi; FP32, packed)
     int precond = 0;              // preconditioner of the current / last solve
     int method = 0;               // 0 textbook PCG, 1 single-reduction (Chronopoulos-Gear) form
     double *cg_pd = nullptr;      // nv * 3: direction of the single-reduction form (FP64)

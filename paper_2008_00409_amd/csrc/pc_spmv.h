@@ -39,11 +39,12 @@ struct SpmvArgs {
 #define PC_SPMV_PIPE 1
 #endif
 
-struct VecF4 {
-    const float4 *p;
+// the FP32 search direction, packed (ld3)
+struct VecF3 {
+    const float *p;
     template <typename T>
     __device__ __forceinline__ void load(int i, T &a, T &b, T &c) const {
-        const float4 v = p[i];
+        const float4 v = ld3(p, i);
         a = v.x; b = v.y; c = v.z;
     }
 };
@@ -225,7 +226,7 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *partials
 // in win_cap rows, p[window] is first copied to LDS with coalesced loads and
 // the rows gather from there; otherwise they gather from global memory.
 template <typename TB, bool NARROW, typename TQ>
-__global__ void __launch_bounds__(1024) k_pcg_spmv(SpmvArgs M, Sched S, const float4 *p, TQ *q,
+__global__ void __launch_bounds__(1024) k_pcg_spmv(SpmvArgs M, Sched S, const float *p, TQ *q,
                                                   const PcgState *st, double *partials, const int2 *win,
                                                   int win_cap) {
     extern __shared__ float4 pwin[];
@@ -240,14 +241,14 @@ __global__ void __launch_bounds__(1024) k_pcg_spmv(SpmvArgs M, Sched S, const fl
     const int wn = W.y - W.x + 1;
     const bool use_lds = win_cap > 0 && wn > 0 && wn <= win_cap;   // uniform per block
     if (use_lds) {
-        for (int k = threadIdx.x; k < wn; k += blockDim.x) pwin[k] = p[W.x + k];
+        for (int k = threadIdx.x; k < wn; k += blockDim.x) pwin[k] = ld3(p, W.x + k);
         __syncthreads();
     }
     double pq = 0.0;
     if (w < I.z) {
         double y[3], xi[3];
         const int row = use_lds ? spmv_row<TB, VecLds, NARROW>(M, I.y + w, lane, VecLds{pwin, W.x}, y, xi)
-                                : spmv_row<TB, VecF4, NARROW>(M, I.y + w, lane, VecF4{p}, y, xi);
+                                : spmv_row<TB, VecF3, NARROW>(M, I.y + w, lane, VecF3{p}, y, xi);
         if (row >= 0) {
             // q as stored (FP64, or FP32 for the inner vectors of a refinement
             // sweep); p.q with the stored values, which the update uses

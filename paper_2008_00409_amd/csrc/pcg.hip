@@ -44,7 +44,7 @@ struct PreArgs {
     int kind;
     const float *dinv;
     const float *binv;
-    float4 *z;
+    float *z;   // packed, 3 per row (st3 / ld3)
 };
 
 __device__ __forceinline__ void precond3(const PreArgs &P, int i, double r0, double r1, double r2, double z[3]) {
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(VT) k_pcg_update(Sched S, int par, TV *r, cons
                     const double z1 = xy * rk[0] + yy * rk[1] + yz * rk[2];
                     const double z2 = xz * rk[0] + yz * rk[1] + zz * rk[2];
                     rz += rk[0] * z0 + rk[1] * z1 + rk[2] * z2;
-                    P.z[i] = make_float4((float)z0, (float)z1, (float)z2, 0.0f);
+                    st3(P.z, i, (float)z0, (float)z1, (float)z2);
                 }
             }
         }
@@ -266,8 +266,8 @@ struct DirRow {
     TV r[3];       // Jacobi: r and dinv
     float d[3];
 
-    __device__ __forceinline__ void load(int i, const TV *x_, const TV *r_, const float4 *p_, const PreArgs &P) {
-        p = p_[i];
+    __device__ __forceinline__ void load(int i, const TV *x_, const TV *r_, const float *p_, const PreArgs &P) {
+        p = ld3(p_, i);
 #pragma unroll
         for (int c = 0; c < 3; ++c) x[c] = x_[3 * i + c];
         if (P.kind == 0) {
@@ -277,13 +277,13 @@ struct DirRow {
                 d[c] = P.dinv[3 * i + c];
             }
         } else {
-            z = P.z[i];
+            z = ld3(P.z, i);
         }
     }
 };
 
 template <typename TV>
-__global__ void __launch_bounds__(VT) k_pcg_dir(Sched S, int par, TV *x, const TV *r, float4 *p, PreArgs P,
+__global__ void __launch_bounds__(VT) k_pcg_dir(Sched S, int par, TV *x, const TV *r, float *p, PreArgs P,
                                                  PcgState *st, const double *part_u) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
@@ -328,18 +328,13 @@ __global__ void __launch_bounds__(VT) k_pcg_dir(Sched S, int par, TV *x, const T
             } else {
                 z[0] = row.z.x; z[1] = row.z.y; z[2] = row.z.z;
             }
-            float4 o;
-            o.x = (float)(z[0] + beta * pv.x);
-            o.y = (float)(z[1] + beta * pv.y);
-            o.z = (float)(z[2] + beta * pv.z);
-            o.w = 0.0f;
-            p[i] = o;
+            st3(p, i, (float)(z[0] + beta * pv.x), (float)(z[1] + beta * pv.y), (float)(z[2] + beta * pv.z));
         }
     }
 }
 
 // ---- single-reduction form (Chronopoulos and Gear, 1989; s = 1) ----
-// Iteration k: w = A u_k (the SpMV above, with u_k in the float4 buffer
+// Iteration k: w = A u_k (the SpMV above, with u_k in the direction buffer
 // and partials of delta_k = u_k.w), then one block per instance sums
 // delta_k and the vector kernel's partials of gamma_k = r_k.z_k and
 // ||r_k||^2 (z = P^-1 r before rounding; at k = 0 the sweep start's values),
@@ -397,10 +392,10 @@ __global__ void __launch_bounds__(1024) k_fin_cgcg(Sched S, const double *partia
 // sweep), x += alpha p, r -= alpha s over the item's rows with flat
 // component indexing (consecutive threads touch consecutive 8-byte
 // elements), each VT-row chunk of the new r staged in LDS; then one thread
-// per row forms u = P^-1 r, stores it as float4 for the next product and
+// per row forms u = P^-1 r, stores it as packed FP32 for the next product and
 // adds to the partials of r.u (with the stored, rounded u, the vector the
 // product and the direction use) and ||r||^2.
-__global__ void __launch_bounds__(VT) k_cgcg_vec(Sched S, double *x, double *r, float4 *u, const double *w,
+__global__ void __launch_bounds__(VT) k_cgcg_vec(Sched S, double *x, double *r, float *u, const double *w,
                                                   double *pd, double *sv, PreArgs P, const PcgState *st,
                                                   double *part_u) {
     __shared__ double rs[3 * VT];
@@ -411,14 +406,12 @@ __global__ void __launch_bounds__(VT) k_cgcg_vec(Sched S, double *x, double *r, 
     if (T.done) return;
     const double alpha = T.alpha, beta = T.beta;
     const bool first = T.kc == 1;
-    const float *uf = (const float *)u;
     double gz = 0.0, rr = 0.0;
     for (int r0 = I.y; r0 < I.z; r0 += VT) {
         const int nr = min(VT, I.z - r0);
         for (int k = threadIdx.x; k < 3 * nr; k += blockDim.x) {
             const int64_t kk = 3 * (int64_t)r0 + k;
-            const int i = (int)(kk / 3);
-            const double uk = uf[4 * (int64_t)i + (kk - 3 * (int64_t)i)];
+            const double uk = u[kk];
             const double pk = first ? uk : uk + beta * pd[kk];
             const double sk = first ? w[kk] : w[kk] + beta * sv[kk];
             pd[kk] = pk;
@@ -437,7 +430,7 @@ __global__ void __launch_bounds__(VT) k_cgcg_vec(Sched S, double *x, double *r, 
             precond3(P, i, a0, a1, a2, z);
             const float4 zf = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
             gz += a0 * (double)zf.x + a1 * (double)zf.y + a2 * (double)zf.z;
-            u[i] = zf;
+            st3(u, i, zf.x, zf.y, zf.z);
         }
         __syncthreads();
     }
@@ -450,7 +443,7 @@ __global__ void __launch_bounds__(VT) k_cgcg_vec(Sched S, double *x, double *r, 
 // vectors are FP32); partials of r.z, ||r||^2 and ||b||^2.
 template <typename TV>
 __global__ void __launch_bounds__(VT) k_pcg_start_zero(Sched S, const uint8_t *restart, const double *b, double *x,
-                                                        TV *r, float4 *p, PreArgs P, double *partials, TV *e) {
+                                                        TV *r, float *p, PreArgs P, double *partials, TV *e) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
     const int4 I = S.vitem[it];
@@ -467,7 +460,7 @@ __global__ void __launch_bounds__(VT) k_pcg_start_zero(Sched S, const uint8_t *r
         }
         rz += r0 * z[0] + r1 * z[1] + r2 * z[2];
         rr += r0 * r0 + r1 * r1 + r2 * r2;
-        p[i] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
+        st3(p, i, (float)z[0], (float)z[1], (float)z[2]);
     }
     double v[3] = {rz, rr, rr};
     block_partials<3>(v, partials, it, S.n_vitems);
@@ -481,7 +474,7 @@ __global__ void __launch_bounds__(VT) k_pcg_start_zero(Sched S, const uint8_t *r
 // instances): partials of ||t||^2, ||b||^2.
 template <typename TB, int MODE, typename TV>
 __global__ void __launch_bounds__(1024) k_residual(SpmvArgs M, Sched S, const uint8_t *restart, const double *b,
-                                                  const double *x, TV *r, float4 *p, PreArgs P,
+                                                  const double *x, TV *r, float *p, PreArgs P,
                                                   double *partials, TV *e) {
     const int it = item_of_block(S.n_sitems);
     if (it < 0) return;
@@ -511,9 +504,9 @@ __global__ void __launch_bounds__(1024) k_residual(SpmvArgs M, Sched S, const ui
                 }
                 rz += t[0] * z[0] + t[1] * z[1] + t[2] * z[2];
                 if (MODE == 0)
-                    p[row] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
+                    st3(p, row, (float)z[0], (float)z[1], (float)z[2]);
                 else if (P.kind != 0)
-                    P.z[row] = make_float4((float)z[0], (float)z[1], (float)z[2], 0.0f);
+                    st3(P.z, row, (float)z[0], (float)z[1], (float)z[2]);
             }
         }
     }
@@ -528,7 +521,7 @@ __global__ void __launch_bounds__(1024) k_residual(SpmvArgs M, Sched S, const ui
 // direction kernel forms it (Jacobi: the stored r times P^-1; block Jacobi:
 // the stored z).  Every block sums its instance's partials in the same order.
 template <typename TV>
-__global__ void __launch_bounds__(VT) k_pcg_redirect(Sched S, const uint8_t *restart, const TV *r, float4 *p,
+__global__ void __launch_bounds__(VT) k_pcg_redirect(Sched S, const uint8_t *restart, const TV *r, float *p,
                                                       PreArgs P, const PcgState *st, const double *partials) {
     const int it = item_of_block(S.n_vitems);
     if (it < 0) return;
@@ -545,12 +538,11 @@ __global__ void __launch_bounds__(VT) k_pcg_redirect(Sched S, const uint8_t *res
 #pragma unroll
             for (int c = 0; c < 3; ++c) z[c] = (double)r[3 * i + c] * (double)P.dinv[3 * i + c];
         } else {
-            const float4 zv = P.z[i];
+            const float4 zv = ld3(P.z, i);
             z[0] = zv.x; z[1] = zv.y; z[2] = zv.z;
         }
-        const float4 pv = p[i];
-        p[i] = make_float4((float)(z[0] + beta * pv.x), (float)(z[1] + beta * pv.y), (float)(z[2] + beta * pv.z),
-                           0.0f);
+        const float4 pv = ld3(p, i);
+        st3(p, i, (float)(z[0] + beta * pv.x), (float)(z[1] + beta * pv.y), (float)(z[2] + beta * pv.z));
     }
 }
 

@@ -25,10 +25,11 @@ def test_more_than_one_gpu_is_refused():
 
 def test_spmv_byte_model_at_full_size():
     nv, nnzb = 828153, 10617589
-    # BF16 blocks (18 B), FP32 product (12 B per row), per stored block
-    assert bench.spmv_bytes(nv, nnzb, "bf16", 2, 12) == nnzb * 20 + nv * 36 + 4 * (nv + 1) == 245477904
+    # BF16 blocks (18 B), packed FP32 direction (12 B per row), FP32 product
+    # (12 B per row), FP64 mass, per stored block
+    assert bench.spmv_bytes(nv, nnzb, "bf16", 2, 12) == nnzb * 20 + nv * 32 + 4 * (nv + 1) == 242165292
     # FP32 blocks (36 B), FP64 product (24 B per row)
-    assert bench.spmv_bytes(nv, nnzb, "f32", 2, 24) == nnzb * 38 + nv * 48 + 4 * (nv + 1) == 446532342
+    assert bench.spmv_bytes(nv, nnzb, "f32", 2, 24) == nnzb * 38 + nv * 44 + 4 * (nv + 1) == 443219730
     # 32-bit columns add 2 B per block
     assert bench.spmv_bytes(nv, nnzb, "bf16", 4, 12) - bench.spmv_bytes(nv, nnzb, "bf16", 2, 12) == 2 * nnzb
 
